@@ -1,0 +1,244 @@
+/*
+ * mhdeoct.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of MH-DEOCT: differential-evolution fitness evaluation of
+ * classification trees (Ren et al., arXiv 2311.06952).
+ *
+ * Conventions
+ * -----------
+ *  - Plain C: no C++ types, no exceptions cross this boundary.
+ *  - Every array argument is a DEVICE pointer (HBM of the context's GPU)
+ *    unless its comment says "host".  The caller owns every buffer it passes
+ *    in; the library never frees or keeps a caller pointer past the call
+ *    (the serving calls keep the dataset pointers of a request until it
+ *    completes; see mh_server_submit).
+ *  - A context (mh_ctx) is bound to one device and one HIP stream.  Calls
+ *    queue their kernels on that stream and return without waiting, except
+ *    those that fill host memory (subtree_solve, mh_train, mh_server_poll,
+ *    mh_ctx_stats), which synchronise the stream before returning.
+ *  - The context owns an internal device arena for its scratch (tile
+ *    layouts, DE state, counters).  It grows on demand with hipMalloc and is
+ *    released by mh_ctx_destroy.
+ *  - Errors: every call returns an mh_status; a negative value is an error
+ *    and mh_last_error() gives a message.  Invalid arguments are reported
+ *    before any kernel is queued.  MH_EDEVICE carries the HIP error string.
+ *    A context is not thread-safe: use one per host thread.
+ *  - Indices are 0-based.  Tree nodes are stored in the paper's heap order
+ *    (node t = 1..2^D-1 at slot t-1; children of t are 2t and 2t+1); leaves
+ *    are numbered left to right, 0..2^D-1.  A node's feature is 0 for "no
+ *    split", else f + 1 for feature f.
+ */
+#ifndef MHDEOCT_H
+#define MHDEOCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mh_status;
+enum {
+  MH_OK = 0,
+  MH_EINVAL = -1,    /* invalid argument (bad size, depth, null pointer, NaN) */
+  MH_ENOMEM = -2,    /* device allocation failed */
+  MH_EDEVICE = -3,   /* a HIP call or kernel launch failed */
+  MH_EBUSY = -4,     /* serving: admission refused (no slot or HBM budget) */
+  MH_ECANCELED = -5  /* serving: request cancelled */
+};
+
+/* Limits.  Depth covers the paper's deepest trees (D = 8) with margin. */
+#define MH_MAX_DEPTH 10
+#define MH_MAX_POP 1024     /* population size P per DE problem */
+#define MH_MAX_CLASSES 255
+#define MH_MAX_FEATURES 255
+#define MH_MAX_BRANCH ((1 << MH_MAX_DEPTH) - 1)
+
+typedef struct mh_ctx mh_ctx;
+
+/* A rank-encoded training set (Section 2 notation: n samples, F features,
+ * K classes).  ranks[f * ld + i] is the dense rank of x[i][f] among the
+ * sorted unique values of feature f (the threshold sets of Section 3.1,
+ * generated once); 0 <= rank < n_unique[f].  labels[i] < K. */
+typedef struct {
+  uint32_t n, F, K;
+  uint32_t ld;               /* column stride of ranks, >= n */
+  const uint32_t *ranks;     /* device, column-major [F][ld] */
+  const uint8_t *labels;     /* device, [n] */
+  const uint32_t *n_unique;  /* device, [F] */
+} mh_dataset;
+
+/* DE parameters (Section 2 eqs. mutation / crossover / selection; Section
+ * 3.3; Algorithm 4).  M < 0 draws M_r ~ U[0,1) per individual and
+ * generation (the paper's DEOCT setting); M >= 0 is a fixed factor. */
+typedef struct {
+  uint32_t P;      /* population size, 3 <= P <= MH_MAX_POP */
+  uint32_t G;      /* generations; P * (G + 1) trees are evaluated */
+  double M;        /* mutation factor */
+  double CR;       /* crossover probability */
+  uint64_t seed;   /* DE seed; draws are keyed by (seed, problem, g, r, slot) */
+  uint32_t n_min;  /* minimum leaf size of the soft constraint (>= 1) */
+  double alpha;    /* complexity penalty per split (>= 0) */
+} mh_de_params;
+
+/* A decoded tree with its leaf classes and objective (host struct). */
+typedef struct {
+  uint32_t D;
+  uint8_t feat[MH_MAX_BRANCH];     /* 0 = no split, else feature + 1 */
+  uint32_t tau[MH_MAX_BRANCH];     /* left iff rank < tau */
+  uint8_t label[1 << MH_MAX_DEPTH];
+  uint32_t correct;                /* correctly classified training samples */
+  double cost;                     /* objective of the Section 3.2 fitness */
+} mh_tree;
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on `device`, queuing work on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives the handle. */
+mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out);
+void mh_ctx_destroy(mh_ctx *ctx);
+/* Message of the last error on this context (never NULL; static storage
+ * owned by the context).  With ctx == NULL: the last mh_ctx_create error. */
+const char *mh_last_error(const mh_ctx *ctx);
+/* Library version string (static). */
+const char *mh_version(void);
+
+/* Timing of the fitness kernel.  When enabled, the library brackets every
+ * fitness-kernel launch with HIP events on the context's stream and adds up
+ * their elapsed time.  mh_ctx_stats synchronises the stream and reports the
+ * totals since the last reset: launches, milliseconds, sample-tree
+ * evaluations (sum over launches of trees x samples) and scanned tiles. */
+mh_status mh_ctx_profile(mh_ctx *ctx, int enable);
+mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms,
+                       uint64_t *evals, uint64_t *tiles, int reset);
+
+/* ---------------------------------------------------------------------- */
+/* a1. Threshold sets as dense ranks (Section 3.1: the sets B_p of sorted    */
+/* unique values, generated once; min-max scaling does not change ranks).    */
+/* ---------------------------------------------------------------------- */
+
+/* X: device, row-major [n][F] float32.  Writes ranks (device [F][ld],
+ * ld >= n) and n_unique (device [F]).  -0 and +0 are one value.  Returns
+ * MH_EINVAL (after the kernels ran, since it synchronises to check) if X
+ * holds a NaN.  Synchronises the stream. */
+mh_status mh_rank_encode(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F,
+                         uint32_t ld, uint32_t *ranks, uint32_t *n_unique);
+
+/* ---------------------------------------------------------------------- */
+/* a2. Decoding individuals (Section 3.1, eq. aenc and eq. benc).           */
+/* ---------------------------------------------------------------------- */
+
+/* genes: device [P][2*SB] float64, SB = 2^D - 1, laid out
+ * [a^_1..a^_SB, b^_1..b^_SB].  feat_t = min(floor(clamp(a^_t, 0, F+1)), F);
+ * tau_t = min(floor(clamp(b^_t, 0, 1) * (n_unique[feat_t - 1] + 1)),
+ * n_unique[feat_t - 1]) for feat_t != 0, else 0.  Writes feat (device
+ * [P][SB] uint8) and tau (device [P][SB] uint32). */
+mh_status tree_decode(mh_ctx *ctx, const double *genes, uint32_t P, uint32_t D,
+                      uint32_t F, const uint32_t *n_unique, uint8_t *feat,
+                      uint32_t *tau);
+
+/* ---------------------------------------------------------------------- */
+/* a3-a5. Fitness of P trees (Algorithm 1; eq. opt_c; eq. opt_all; the      */
+/* soft-constraint fitness of Section 3.2).                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Routes each of the n_sub samples (idx[j] if idx != NULL, else j) through
+ * every tree (left iff feat != 0 and rank < tau) and counts, per tree, leaf
+ * and class.  Outputs (device; any may be NULL except cost):
+ *   counts  [P][2^D][K] uint32
+ *   correct [P] uint32   sum over leaves of the largest class count
+ *   label   [P][2^D] uint8 lowest class attaining the largest count
+ *   cost    [P] float64  (n_sub - correct) + alpha * #splits
+ *                        + #{leaves with 0 < size < n_min}
+ * feat / tau: device [P][SB] as written by tree_decode.  1 <= D <= 10,
+ * 1 <= P <= MH_MAX_POP, n_sub >= 0.  Builds the tiled sample layout in the
+ * context arena on every call (see mh_tileset_build to reuse it). */
+mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                       uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
+                       uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                       uint32_t *counts, uint32_t *correct, uint8_t *label,
+                       double *cost);
+
+/* The tiled sample layout the fitness kernel reads: samples grouped by
+ * class into tiles of at most 63, each tile holding, per feature, its ranks
+ * in ascending order and the prefix bitmasks of the sample positions in
+ * that order.  mh_tileset_bytes gives the device bytes a layout for n_sub
+ * samples needs; mh_tileset_build fills a caller-owned device buffer of at
+ * least that size (256-byte aligned).  The layout stays valid as long as
+ * the dataset's ranks and labels do not change. */
+mh_status mh_tileset_bytes(uint32_t n_sub, uint32_t F, uint32_t K, size_t *bytes);
+mh_status mh_tileset_build(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                           uint32_t n_sub, void *tiles, size_t bytes);
+/* fitness_eval over a prebuilt layout (same outputs as fitness_eval). */
+mh_status fitness_eval_tiles(mh_ctx *ctx, const void *tiles, const uint32_t *n_unique,
+                             const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                             uint32_t D, uint32_t n_min, double alpha,
+                             uint32_t *counts, uint32_t *correct, uint8_t *label,
+                             double *cost);
+
+/* ---------------------------------------------------------------------- */
+/* a6. DE step (Section 2 eqs. mutation / crossover / selection; Section    */
+/* 3.3; Algorithm 4).                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Initial population (Algorithm 4, first loop): rows 0..W-1 copied from
+ * warm (device [W][2*SB], may be NULL when W == 0), the rest drawn inside
+ * the range limits: a^ = U (F + 1), b^ = U with U ~ U[0,1).  pop: device
+ * [P][2*SB] float64. */
+mh_status de_init(mh_ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
+                  uint64_t problem_id, const double *warm, uint32_t W, double *pop);
+
+/* One DE step for generation g >= 1 of problem `problem_id`:
+ *  1. if trial != NULL: selection, pop[r] <- trial[r] and cost[r] <-
+ *     trial_cost[r] when trial_cost[r] <= cost[r];
+ *  2. best = lowest index of the minimum cost, written to *best (device);
+ *  3. if next_trial != NULL: DE/best/1 mutation v = pop[best] + M_r
+ *     (pop[r1] - pop[r2]) with r1 != r, r2 not in {r, r1}, clamped to the
+ *     range limits, and binomial crossover with CR and q_rand, writing the
+ *     trial population of generation g to next_trial (device [P][2*SB]).
+ * pop, cost ([P] float64), trial, trial_cost, next_trial: device. */
+mh_status de_step(mh_ctx *ctx, const mh_de_params *prm, uint32_t D, uint32_t F,
+                  uint64_t problem_id, uint32_t g, double *pop, double *cost,
+                  const double *trial, const double *trial_cost, uint32_t *best,
+                  double *next_trial);
+
+/* DEOCT (Algorithm 4) on the samples idx[0..n_sub) (all n if idx == NULL):
+ * initialise (warm: HOST [W][2*SB] float64, may be NULL), evaluate, then G
+ * generations of trial construction from the previous best, population-wide
+ * evaluation and selection, all on the device.  Fills *out (host) with the
+ * best tree, its leaf labels, correct count and cost.  Synchronises. */
+mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                        uint32_t n_sub, uint32_t D, const mh_de_params *prm,
+                        const double *warm, uint32_t W, uint64_t problem_id,
+                        mh_tree *out);
+
+/* ---------------------------------------------------------------------- */
+/* a7. Moving-horizon DEOCT (Algorithm 2; Section 4).                       */
+/* ---------------------------------------------------------------------- */
+
+#define MH_SEQUENTIAL 0u  /* node by node in heap order, as in Algorithm 2 */
+#define MH_BATCHED 1u     /* every node of a level in one batched launch */
+
+/* Trains a depth-D tree node by node: each branch node whose subset has
+ * more than n_min samples and more than one class gets the first node of a
+ * DEOCT subtree of depth min(D_MH, D - depth(t)) (problem id t), or the
+ * exact best depth-1 split when that depth is 1; other nodes get no split.
+ * The batched form solves all nodes of a level together and returns the
+ * identical tree.  Fills *out (host).  Synchronises. */
+mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
+                   const mh_de_params *prm, uint32_t flags, mh_tree *out);
+
+/* Exact best depth-1 split under the 0-1 loss (Algorithm 2, horizon-1
+ * branch): candidates no-split first, then features ascending, thresholds
+ * 1..n_f-1 ascending; the first strict maximum of correct wins.  Writes
+ * feat/tau/correct to host.  Synchronises. */
+mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                 uint32_t n_sub, uint8_t *feat, uint32_t *tau, uint32_t *correct);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHDEOCT_H */

@@ -1,0 +1,345 @@
+"""Thin ctypes binding of the C ABI in include/mhdeoct.h.
+
+Only argument marshalling happens here: torch provides device memory and the
+HIP stream, every computation runs in the HIP library.  There is no CPU
+fallback: loading fails loudly if libmhdeoct.so is missing or does not export
+the declared symbols.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhdeoct.so")
+
+MH_OK, MH_EINVAL, MH_ENOMEM, MH_EDEVICE, MH_EBUSY, MH_ECANCELED = 0, -1, -2, -3, -4, -5
+MH_MAX_DEPTH = 10
+MH_SEQUENTIAL, MH_BATCHED = 0, 1
+
+# Every entry point the header declares (checked by the CPU test suite).
+EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh_ctx_profile",
+           "mh_ctx_stats", "mh_rank_encode", "tree_decode", "fitness_eval", "mh_tileset_bytes",
+           "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
+           "mh_train", "split1")
+
+
+class MhError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mhdeoct error {code}: {msg}")
+        self.code = code
+
+
+class DatasetC(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("F", C.c_uint32), ("K", C.c_uint32), ("ld", C.c_uint32),
+                ("ranks", C.c_void_p), ("labels", C.c_void_p), ("n_unique", C.c_void_p)]
+
+
+class DEParamsC(C.Structure):
+    _fields_ = [("P", C.c_uint32), ("G", C.c_uint32), ("M", C.c_double), ("CR", C.c_double),
+                ("seed", C.c_uint64), ("n_min", C.c_uint32), ("alpha", C.c_double)]
+
+
+class TreeC(C.Structure):
+    _fields_ = [("D", C.c_uint32), ("feat", C.c_uint8 * 1023), ("tau", C.c_uint32 * 1023),
+                ("label", C.c_uint8 * 1024), ("correct", C.c_uint32), ("cost", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmhdeoct.so and declare the signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    V, U32, U64, I32, D = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_double
+    sig = {
+        "mh_version": ([], C.c_char_p),
+        "mh_ctx_create": ([C.c_int, V, C.POINTER(V)], I32),
+        "mh_ctx_destroy": ([V], None),
+        "mh_last_error": ([V], C.c_char_p),
+        "mh_ctx_profile": ([V, C.c_int], I32),
+        "mh_ctx_stats": ([V, C.POINTER(U64), C.POINTER(D), C.POINTER(U64), C.POINTER(U64), C.c_int],
+                         I32),
+        "mh_rank_encode": ([V, V, U32, U32, U32, V, V], I32),
+        "tree_decode": ([V, V, U32, U32, U32, V, V, V], I32),
+        "fitness_eval": ([V, C.POINTER(DatasetC), V, U32, V, V, U32, U32, U32, D, V, V, V, V], I32),
+        "mh_tileset_bytes": ([U32, U32, U32, C.POINTER(C.c_size_t)], I32),
+        "mh_tileset_build": ([V, C.POINTER(DatasetC), V, U32, V, C.c_size_t], I32),
+        "fitness_eval_tiles": ([V, V, V, V, V, U32, U32, U32, D, V, V, V, V], I32),
+        "de_init": ([V, U32, U32, U32, U64, U64, V, U32, V], I32),
+        "de_step": ([V, C.POINTER(DEParamsC), U32, U32, U64, U32, V, V, V, V, V, V], I32),
+        "subtree_solve": ([V, C.POINTER(DatasetC), V, U32, U32, C.POINTER(DEParamsC), V, U32, U64,
+                           C.POINTER(TreeC)], I32),
+        "mh_train": ([V, C.POINTER(DatasetC), U32, U32, C.POINTER(DEParamsC), U32,
+                      C.POINTER(TreeC)], I32),
+        "split1": ([V, C.POINTER(DatasetC), V, U32, C.POINTER(C.c_uint8), C.POINTER(U32),
+                    C.POINTER(U32)], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)  # AttributeError if a symbol is missing
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+# --------------------------------------------------------------------------
+# torch-backed helpers (imported lazily so that the CPU suite can inspect the
+# library without initialising a GPU)
+# --------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An mh_ctx bound to a device and a HIP stream (torch's current stream
+    at creation unless one is given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU; none is visible")
+        self.lib = load_library()
+        self.device = device
+        with torch.cuda.device(device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = self.lib.mh_ctx_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != MH_OK:
+            raise MhError(rc, self.lib.mh_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mh_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int):
+        if rc != MH_OK:
+            raise MhError(rc, self.lib.mh_last_error(self.h).decode())
+
+    def profile(self, enable: bool):
+        self.check(self.lib.mh_ctx_profile(self.h, 1 if enable else 0))
+
+    def stats(self, reset: bool = False):
+        la, ev, ti = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        ms = C.c_double()
+        self.check(self.lib.mh_ctx_stats(self.h, C.byref(la), C.byref(ms), C.byref(ev),
+                                         C.byref(ti), 1 if reset else 0))
+        return dict(launches=la.value, ms=ms.value, evals=ev.value, tiles=ti.value)
+
+
+_default: dict[int, Context] = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+@dataclass
+class Dataset:
+    """Rank-encoded training set resident on the device."""
+    ranks: object      # torch.int32 [F][ld] (uint32 bits)
+    labels: object     # torch.uint8 [n]
+    n_unique: object   # torch.int32 [F] (uint32 bits)
+    n: int
+    F: int
+    K: int
+
+    @property
+    def ld(self) -> int:
+        return int(self.ranks.shape[1])
+
+    def cstruct(self) -> DatasetC:
+        return DatasetC(self.n, self.F, self.K, self.ld, self.ranks.data_ptr(),
+                        self.labels.data_ptr(), self.n_unique.data_ptr())
+
+
+def rank_encode(X, ctx: Context | None = None, pad_to: int = 256):
+    """mh_rank_encode: X float32 [n][F] (torch, on the device) -> (ranks
+    int32 [F][ld], n_unique int32 [F]) with ld = n rounded up to pad_to."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    X = X.contiguous()
+    n, F = X.shape
+    ld = max(pad_to, ((n + pad_to - 1) // pad_to) * pad_to)
+    ranks = torch.zeros((F, ld), dtype=torch.int32, device=X.device)
+    nu = torch.zeros(F, dtype=torch.int32, device=X.device)
+    ctx.check(ctx.lib.mh_rank_encode(ctx.h, _ptr(X), n, F, ld, _ptr(ranks), _ptr(nu)))
+    return ranks, nu
+
+
+def dataset(X, y, K: int, ctx: Context | None = None) -> Dataset:
+    """Upload float32 X [n][F] and labels y [n] and rank-encode on the device."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    dev = torch.device("cuda", ctx.device)
+    Xt = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    yt = torch.as_tensor(np.ascontiguousarray(y, dtype=np.uint8)).to(dev)
+    ranks, nu = rank_encode(Xt, ctx)
+    return Dataset(ranks, yt, nu, int(Xt.shape[0]), int(Xt.shape[1]), int(K))
+
+
+def tree_decode(genes, D: int, F: int, n_unique, ctx: Context | None = None):
+    torch = _torch()
+    ctx = ctx or default_context()
+    SB = (1 << D) - 1
+    genes = genes.contiguous().view(-1, 2 * SB)
+    P = genes.shape[0]
+    feat = torch.zeros((P, SB), dtype=torch.uint8, device=genes.device)
+    tau = torch.zeros((P, SB), dtype=torch.int32, device=genes.device)
+    ctx.check(ctx.lib.tree_decode(ctx.h, _ptr(genes), P, D, F, _ptr(n_unique), _ptr(feat),
+                                  _ptr(tau)))
+    return feat, tau
+
+
+def fitness_eval(ds: Dataset, feat, tau, D: int, idx=None, n_min: int = 1, alpha: float = 0.0,
+                 ctx: Context | None = None, want_counts: bool = True):
+    """fitness_eval: returns (counts [P][SL][K] int32, correct [P] int32,
+    label [P][SL] uint8, cost [P] float64), all on the device."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    SB = (1 << D) - 1
+    SL = SB + 1
+    feat = feat.contiguous().view(-1, SB)
+    tau = tau.contiguous().view(-1, SB)
+    P = feat.shape[0]
+    dev = feat.device
+    counts = torch.zeros((P, SL, ds.K), dtype=torch.int32, device=dev) if want_counts else None
+    correct = torch.zeros(P, dtype=torch.int32, device=dev)
+    label = torch.zeros((P, SL), dtype=torch.uint8, device=dev)
+    cost = torch.zeros(P, dtype=torch.float64, device=dev)
+    n_sub = ds.n if idx is None else int(idx.numel())
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.fitness_eval(ctx.h, C.byref(dsc), _ptr(idx), n_sub, _ptr(feat), _ptr(tau),
+                                   P, D, n_min, alpha, _ptr(counts), _ptr(correct), _ptr(label),
+                                   _ptr(cost)))
+    return counts, correct, label, cost
+
+
+class TileSet:
+    """A prebuilt tiled sample layout (device buffer owned by torch)."""
+
+    def __init__(self, ds: Dataset, idx=None, ctx: Context | None = None):
+        torch = _torch()
+        self.ctx = ctx or default_context()
+        self.ds = ds
+        n_sub = ds.n if idx is None else int(idx.numel())
+        nb = C.c_size_t()
+        self.ctx.check(self.ctx.lib.mh_tileset_bytes(n_sub, ds.F, ds.K, C.byref(nb)))
+        self.buf = torch.empty(nb.value + 256, dtype=torch.uint8, device=ds.labels.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.view = self.buf[off:off + nb.value]
+        self.bytes = nb.value
+        dsc = ds.cstruct()
+        self.ctx.check(self.ctx.lib.mh_tileset_build(self.ctx.h, C.byref(dsc), _ptr(idx), n_sub,
+                                                     _ptr(self.view), nb.value))
+
+    def fitness(self, feat, tau, D: int, n_min: int = 1, alpha: float = 0.0, out=None):
+        torch = _torch()
+        SB = (1 << D) - 1
+        P = feat.numel() // SB
+        dev = feat.device
+        if out is None:
+            out = (None, None, None, torch.zeros(P, dtype=torch.float64, device=dev))
+        counts, correct, label, cost = out
+        ctx = self.ctx
+        ctx.check(ctx.lib.fitness_eval_tiles(ctx.h, _ptr(self.view), _ptr(self.ds.n_unique),
+                                             _ptr(feat), _ptr(tau), P, D, n_min, alpha,
+                                             _ptr(counts), _ptr(correct), _ptr(label), _ptr(cost)))
+        return out
+
+
+def de_params(P, G, M=0.5, CR=0.9, seed=0, n_min=1, alpha=0.0) -> DEParamsC:
+    return DEParamsC(P, G, M, CR, seed, n_min, alpha)
+
+
+def de_init(P, D, F, seed, prob, warm=None, ctx: Context | None = None, device=0):
+    torch = _torch()
+    ctx = ctx or default_context()
+    SB = (1 << D) - 1
+    pop = torch.zeros((P, 2 * SB), dtype=torch.float64, device=torch.device("cuda", ctx.device))
+    W = 0 if warm is None else int(warm.shape[0])
+    ctx.check(ctx.lib.de_init(ctx.h, P, D, F, seed, prob, _ptr(warm), W, _ptr(pop)))
+    return pop
+
+
+def de_step(prm: DEParamsC, D, F, prob, g, pop, cost, trial=None, trial_cost=None,
+            make_trial=True, ctx: Context | None = None):
+    """One DE step; returns (best int32 [1] device tensor, next_trial or None).
+    pop and cost are updated in place."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    best = torch.zeros(1, dtype=torch.int32, device=pop.device)
+    nxt = torch.zeros_like(pop) if make_trial else None
+    ctx.check(ctx.lib.de_step(ctx.h, C.byref(prm), D, F, prob, g, _ptr(pop), _ptr(cost),
+                              _ptr(trial), _ptr(trial_cost), _ptr(best), _ptr(nxt)))
+    return best, nxt
+
+
+def _tree_dict(t: TreeC) -> dict:
+    SB = (1 << t.D) - 1
+    SL = SB + 1
+    return dict(D=t.D, feat=np.array(t.feat[:SB], dtype=np.uint8),
+                tau=np.array(t.tau[:SB], dtype=np.uint32),
+                label=np.array(t.label[:SL], dtype=np.uint8), correct=int(t.correct),
+                cost=float(t.cost))
+
+
+def subtree_solve(ds: Dataset, D: int, prm: DEParamsC, idx=None, warm=None, prob: int = 0,
+                  ctx: Context | None = None) -> dict:
+    """DEOCT on the device; warm is a host float64 array [W][2*SB]."""
+    ctx = ctx or default_context()
+    n_sub = ds.n if idx is None else int(idx.numel())
+    W = 0
+    wp = None
+    if warm is not None:
+        warm = np.ascontiguousarray(warm, dtype=np.float64).reshape(-1, 2 * ((1 << D) - 1))
+        W = warm.shape[0]
+        wp = warm.ctypes.data_as(C.c_void_p)
+    out = TreeC()
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.subtree_solve(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp, W,
+                                    prob, C.byref(out)))
+    return _tree_dict(out)
+
+
+def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParamsC, batched: bool = False,
+             ctx: Context | None = None) -> dict:
+    ctx = ctx or default_context()
+    out = TreeC()
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.mh_train(ctx.h, C.byref(dsc), D, D_MH, C.byref(prm),
+                               MH_BATCHED if batched else MH_SEQUENTIAL, C.byref(out)))
+    return _tree_dict(out)
+
+
+def split1(ds: Dataset, idx=None, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    n_sub = ds.n if idx is None else int(idx.numel())
+    f, t, c = C.c_uint8(), C.c_uint32(), C.c_uint32()
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.split1(ctx.h, C.byref(dsc), _ptr(idx), n_sub, C.byref(f), C.byref(t),
+                             C.byref(c)))
+    return int(f.value), int(t.value), int(c.value)

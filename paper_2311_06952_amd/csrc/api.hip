@@ -1,0 +1,440 @@
+// api.hip -- the C ABI (include/mhdeoct.h): context, arena, argument checks
+// and the host-side orchestration of the device kernels.
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "device_common.h"
+#include "internal.h"
+
+struct mh_ctx {
+  mh::Ctx c;
+};
+
+namespace mh {
+
+static thread_local std::string g_create_err;
+
+mh_status fail(Ctx *ctx, mh_status code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? MH_ENOMEM : MH_EDEVICE, m);
+}
+
+void *arena_get(Ctx *ctx, const char *name, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = align256(bytes);
+  for (auto &b : ctx->arena.bufs) {
+    if (b.name == name) {
+      if (b.bytes >= bytes) return b.ptr;
+      // the stream may still use the old buffer
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) return nullptr;
+      (void)hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+      if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        ctx->err = std::string("device allocation failed for ") + name;
+        b.ptr = nullptr;
+        return nullptr;
+      }
+      b.bytes = bytes;
+      return b.ptr;
+    }
+  }
+  Arena::Buf nb;
+  nb.name = name;
+  if (hipMalloc(&nb.ptr, bytes) != hipSuccess) {
+    ctx->err = std::string("device allocation failed for ") + name;
+    return nullptr;
+  }
+  nb.bytes = bytes;
+  ctx->arena.bufs.push_back(nb);
+  return nb.ptr;
+}
+
+// Tile path limits: depth templates 1..5, one LDS tile <= 64 KiB.
+static bool tile_path_ok(uint32_t D, uint32_t F) { return D >= 1 && D <= 5 && F <= 80; }
+
+static mh_status check_dataset(Ctx *ctx, const mh_dataset *ds) {
+  if (!ds) return fail(ctx, MH_EINVAL, "dataset is null");
+  if (ds->F == 0 || ds->F > MH_MAX_FEATURES) return fail(ctx, MH_EINVAL, "F must be in 1..255");
+  if (ds->K == 0 || ds->K > MH_MAX_CLASSES) return fail(ctx, MH_EINVAL, "K must be in 1..255");
+  if (ds->ld < ds->n) return fail(ctx, MH_EINVAL, "ld must be >= n");
+  if (ds->n > 0 && (!ds->ranks || !ds->labels)) return fail(ctx, MH_EINVAL, "null ranks or labels");
+  if (!ds->n_unique) return fail(ctx, MH_EINVAL, "null n_unique");
+  return MH_OK;
+}
+
+static mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D) {
+  if (!p) return fail(ctx, MH_EINVAL, "DE params are null");
+  if (p->P < 3 || p->P > MH_MAX_POP) return fail(ctx, MH_EINVAL, "P must be in 3..1024");
+  if (D < 1 || D > MH_MAX_DEPTH) return fail(ctx, MH_EINVAL, "D must be in 1..10");
+  if (p->G >= (1u << 24)) return fail(ctx, MH_EINVAL, "G must be < 2^24");
+  if (!(p->CR >= 0.0 && p->CR <= 1.0)) return fail(ctx, MH_EINVAL, "CR must be in [0, 1]");
+  if (!(p->alpha >= 0.0)) return fail(ctx, MH_EINVAL, "alpha must be >= 0");
+  if (p->M != p->M) return fail(ctx, MH_EINVAL, "M is NaN");
+  if (p->n_min < 1) return fail(ctx, MH_EINVAL, "n_min must be >= 1");
+  if ((1u << D) * 2u + 4u >= (1u << 20)) return fail(ctx, MH_EINVAL, "too many genes");
+  return MH_OK;
+}
+
+// Evaluate P trees (feat/tau, device) over a subset: tile path when a tile
+// set is given, else the walk path.
+struct EvalSet {
+  const mh_dataset *ds;
+  const uint32_t *idx;
+  uint32_t n_sub;
+  const void *tiles;  // nullptr: walk path
+  uint32_t max_tiles;
+  uint32_t *cnt;
+};
+
+static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, const uint32_t *tau,
+                            uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                            const FitnessOut &out) {
+  if (es.tiles)
+    return launch_fitness_tiles(ctx, es.tiles, es.ds->F, es.ds->K, es.n_sub, 1, es.max_tiles, feat,
+                                tau, P, D, n_min, alpha, es.cnt, out);
+  return launch_fitness_walk(ctx, es.ds, es.idx, es.n_sub, feat, tau, P, D, n_min, alpha, out);
+}
+
+static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                              uint32_t D, uint32_t P, const char *tile_name, const char *cnt_name,
+                              EvalSet &es) {
+  es.ds = ds;
+  es.idx = idx;
+  es.n_sub = n_sub;
+  es.tiles = nullptr;
+  es.cnt = nullptr;
+  es.max_tiles = 0;
+  if (!tile_path_ok(D, ds->F)) return MH_OK;
+  TileHdr h = tile_layout(n_sub, ds->F, ds->K, 1);
+  void *tiles = arena_get(ctx, tile_name, h.total_bytes);
+  uint32_t *cnt = (uint32_t *)arena_get(ctx, cnt_name, cnt_bytes(1, D, ds->K, P));
+  if (!tiles || !cnt) return MH_ENOMEM;
+  mh_status s = launch_tile_build(ctx, ds, idx, nullptr, n_sub, 1, tiles, h.total_bytes);
+  if (s) return s;
+  MH_HIP(ctx, hipMemsetAsync(cnt, 0, cnt_bytes(1, D, ds->K, P), ctx->stream));
+  es.tiles = tiles;
+  es.cnt = cnt;
+  es.max_tiles = h.max_tiles;
+  return MH_OK;
+}
+
+// DEOCT (Algorithm 4) fully on the device; the best tree goes to *out.
+static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                       uint32_t D, const mh_de_params *prm, const double *warm_host, uint32_t W,
+                       uint64_t prob, mh_tree *out) {
+  const uint32_t P = prm->P, SB = (1u << D) - 1u, SL = 1u << D, m = 2 * SB, K = ds->K;
+  hipStream_t st = ctx->stream;
+  EvalSet es;
+  mh_status s = prepare_eval(ctx, ds, idx, n_sub, D, P, "ss_tiles", "ss_cnt", es);
+  if (s) return s;
+  double *pop = (double *)arena_get(ctx, "ss_pop", (size_t)P * m * 8);
+  double *trial = (double *)arena_get(ctx, "ss_trial", (size_t)P * m * 8);
+  double *cost = (double *)arena_get(ctx, "ss_cost", (size_t)P * 8);
+  double *tcost = (double *)arena_get(ctx, "ss_tcost", (size_t)P * 8);
+  uint8_t *feat = (uint8_t *)arena_get(ctx, "ss_feat", (size_t)P * SB);
+  uint32_t *tau = (uint32_t *)arena_get(ctx, "ss_tau", (size_t)P * SB * 4);
+  uint32_t *best = (uint32_t *)arena_get(ctx, "ss_best", 256);
+  uint8_t *f1 = (uint8_t *)arena_get(ctx, "ss_f1", SB);
+  uint32_t *t1 = (uint32_t *)arena_get(ctx, "ss_t1", (size_t)SB * 4);
+  uint8_t *lab1 = (uint8_t *)arena_get(ctx, "ss_lab1", SL);
+  uint32_t *corr1 = (uint32_t *)arena_get(ctx, "ss_corr1", 256);
+  double *cost1 = (double *)arena_get(ctx, "ss_cost1", 256);
+  double *warm = nullptr;
+  if (W > 0) {
+    warm = (double *)arena_get(ctx, "ss_warm", (size_t)W * m * 8);
+    if (!warm) return MH_ENOMEM;
+    MH_HIP(ctx, hipMemcpyAsync(warm, warm_host, (size_t)W * m * 8, hipMemcpyHostToDevice, st));
+  }
+  if (!pop || !trial || !cost || !tcost || !feat || !tau || !best || !f1 || !t1 || !lab1 ||
+      !corr1 || !cost1)
+    return MH_ENOMEM;
+  DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique};
+  // g = 0: initialise, decode, evaluate
+  s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop);
+  if (s) return s;
+  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr);
+  if (s) return s;
+  FitnessOut fo;
+  fo.cost = cost;
+  s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, fo);
+  if (s) return s;
+  // best of generation 0, and the trial population of generation 1
+  s = launch_de_step(ctx, de, nullptr, prob, 1, 1, pop, cost, nullptr, nullptr, best,
+                     prm->G >= 1 ? trial : nullptr, feat, tau);
+  if (s) return s;
+  FitnessOut ft;
+  ft.cost = tcost;
+  for (uint32_t g = 1; g <= prm->G; ++g) {
+    s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, ft);
+    if (s) return s;
+    s = launch_de_step(ctx, de, nullptr, prob, 1, g + 1, pop, cost, trial, tcost, best,
+                       g < prm->G ? trial : nullptr, feat, tau);
+    if (s) return s;
+  }
+  // the best individual: decode and evaluate for its labels
+  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best);
+  if (s) return s;
+  FitnessOut fb;
+  fb.label = lab1;
+  fb.correct = corr1;
+  fb.cost = cost1;
+  s = eval_trees(ctx, es, f1, t1, 1, D, prm->n_min, prm->alpha, fb);
+  if (s) return s;
+  std::memset(out, 0, sizeof(*out));
+  out->D = D;
+  MH_HIP(ctx, hipMemcpyAsync(out->feat, f1, SB, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(out->tau, t1, (size_t)SB * 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(out->label, lab1, SL, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(&out->correct, corr1, 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(&out->cost, cost1, 8, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipStreamSynchronize(st));
+  (void)K;
+  return MH_OK;
+}
+
+}  // namespace mh
+
+using namespace mh;
+
+#define CTX_OR_FAIL(ctx)                                              \
+  do {                                                                \
+    if (!(ctx)) return fail(nullptr, MH_EINVAL, "context is null");   \
+    hipError_t e_ = hipSetDevice((ctx)->c.device);                    \
+    if (e_ != hipSuccess) return hip_fail(&(ctx)->c, e_, "hipSetDevice"); \
+  } while (0)
+
+extern "C" {
+
+const char *mh_version(void) { return "mhdeoct-gfx950 0.1"; }
+
+mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
+  if (!out) return fail(nullptr, MH_EINVAL, "out is null");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(nullptr, MH_EINVAL, "no such device");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  mh_ctx *c = new mh_ctx();
+  c->c.device = device;
+  c->c.stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    c->c.num_cu = cus;
+  if (hipEventCreate(&c->c.ev0) != hipSuccess || hipEventCreate(&c->c.ev1) != hipSuccess) {
+    delete c;
+    return fail(nullptr, MH_EDEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return MH_OK;
+}
+
+void mh_ctx_destroy(mh_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (auto &b : ctx->c.arena.bufs) (void)hipFree(b.ptr);
+  if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
+  if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
+  delete ctx;
+}
+
+const char *mh_last_error(const mh_ctx *ctx) {
+  return ctx ? ctx->c.err.c_str() : g_create_err.c_str();
+}
+
+mh_status mh_ctx_profile(mh_ctx *ctx, int enable) {
+  CTX_OR_FAIL(ctx);
+  ctx->c.profile = enable != 0;
+  return MH_OK;
+}
+
+mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms, uint64_t *evals,
+                       uint64_t *tiles, int reset) {
+  CTX_OR_FAIL(ctx);
+  MH_HIP(&ctx->c, hipStreamSynchronize(ctx->c.stream));
+  if (launches) *launches = ctx->c.prof_launches;
+  if (ms) *ms = ctx->c.prof_ms;
+  if (evals) *evals = ctx->c.prof_evals;
+  if (tiles) *tiles = ctx->c.prof_tiles;
+  if (reset) {
+    ctx->c.prof_launches = ctx->c.prof_evals = ctx->c.prof_tiles = 0;
+    ctx->c.prof_ms = 0.0;
+  }
+  return MH_OK;
+}
+
+mh_status mh_rank_encode(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
+                         uint32_t *ranks, uint32_t *n_unique) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  if (F == 0 || F > MH_MAX_FEATURES) return fail(c, MH_EINVAL, "F must be in 1..255");
+  if (ld < n) return fail(c, MH_EINVAL, "ld must be >= n");
+  if ((n > 0 && (!X || !ranks)) || !n_unique) return fail(c, MH_EINVAL, "null pointer");
+  return launch_rank_encode(c, X, n, F, ld, ranks, n_unique);
+}
+
+mh_status tree_decode(mh_ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
+                      const uint32_t *n_unique, uint8_t *feat, uint32_t *tau) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
+  if (F == 0 || F > MH_MAX_FEATURES) return fail(c, MH_EINVAL, "F must be in 1..255");
+  if (P > 0 && (!genes || !n_unique || !feat || !tau)) return fail(c, MH_EINVAL, "null pointer");
+  return launch_decode(c, genes, P, D, F, n_unique, feat, tau, 1, nullptr);
+}
+
+mh_status mh_tileset_bytes(uint32_t n_sub, uint32_t F, uint32_t K, size_t *bytes) {
+  if (!bytes || F == 0 || F > MH_MAX_FEATURES || K == 0 || K > MH_MAX_CLASSES)
+    return fail(nullptr, MH_EINVAL, "bad tileset size arguments");
+  *bytes = tile_layout(n_sub, F, K, 1).total_bytes;
+  return MH_OK;
+}
+
+mh_status mh_tileset_build(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                           void *tiles, size_t bytes) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  if (!tiles) return fail(c, MH_EINVAL, "tiles is null");
+  return launch_tile_build(c, ds, idx, nullptr, n_sub, 1, tiles, bytes);
+}
+
+static mh_status check_fit_args(Ctx *c, uint32_t P, uint32_t D, const uint8_t *feat,
+                                const uint32_t *tau, uint32_t n_min, double alpha,
+                                const double *cost) {
+  if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
+  if (P < 1 || P > MH_MAX_POP) return fail(c, MH_EINVAL, "P must be in 1..1024");
+  if (!feat || !tau || !cost) return fail(c, MH_EINVAL, "null feat, tau or cost");
+  if (n_min < 1) return fail(c, MH_EINVAL, "n_min must be >= 1");
+  if (!(alpha >= 0.0)) return fail(c, MH_EINVAL, "alpha must be >= 0");
+  return MH_OK;
+}
+
+mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                       const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                       uint32_t n_min, double alpha, uint32_t *counts, uint32_t *correct,
+                       uint8_t *label, double *cost) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  s = check_fit_args(c, P, D, feat, tau, n_min, alpha, cost);
+  if (s) return s;
+  if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  EvalSet es;
+  s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es);
+  if (s) return s;
+  FitnessOut out;
+  out.counts = counts;
+  out.correct = correct;
+  out.label = label;
+  out.cost = cost;
+  return eval_trees(c, es, feat, tau, P, D, n_min, alpha, out);
+}
+
+mh_status fitness_eval_tiles(mh_ctx *ctx, const void *tiles, const uint32_t *n_unique,
+                             const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                             uint32_t n_min, double alpha, uint32_t *counts, uint32_t *correct,
+                             uint8_t *label, double *cost) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_fit_args(c, P, D, feat, tau, n_min, alpha, cost);
+  if (s) return s;
+  if (!tiles) return fail(c, MH_EINVAL, "tiles is null");
+  (void)n_unique;
+  TileHdr h;
+  MH_HIP(c, hipMemcpyAsync(&h, tiles, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  if (h.magic != TILE_MAGIC || h.n_problems != 1) return fail(c, MH_EINVAL, "not a tile set");
+  if (!tile_path_ok(D, h.F)) return fail(c, MH_EINVAL, "tile path needs D <= 5 and F <= 80");
+  uint32_t *cnt = (uint32_t *)arena_get(c, "fe_cnt", cnt_bytes(1, D, h.K, P));
+  if (!cnt) return MH_ENOMEM;
+  MH_HIP(c, hipMemsetAsync(cnt, 0, cnt_bytes(1, D, h.K, P), c->stream));
+  FitnessOut out;
+  out.counts = counts;
+  out.correct = correct;
+  out.label = label;
+  out.cost = cost;
+  return launch_fitness_tiles(c, tiles, h.F, h.K, h.n_sub, 1, h.max_tiles, feat, tau, P, D, n_min,
+                              alpha, cnt, out);
+}
+
+mh_status de_init(mh_ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
+                  uint64_t problem_id, const double *warm, uint32_t W, double *pop) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
+  if (P > MH_MAX_POP || W > P) return fail(c, MH_EINVAL, "bad P or W");
+  if (!pop || (W > 0 && !warm)) return fail(c, MH_EINVAL, "null pointer");
+  return launch_de_init(c, P, D, F, seed, nullptr, problem_id, 1, warm, W, pop);
+}
+
+mh_status de_step(mh_ctx *ctx, const mh_de_params *prm, uint32_t D, uint32_t F,
+                  uint64_t problem_id, uint32_t g, double *pop, double *cost,
+                  const double *trial, const double *trial_cost, uint32_t *best,
+                  double *next_trial) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_de(c, prm, D);
+  if (s) return s;
+  if (!pop || !cost || !best) return fail(c, MH_EINVAL, "null pop, cost or best");
+  if (trial && !trial_cost) return fail(c, MH_EINVAL, "trial without trial_cost");
+  if (g >= (1u << 24)) return fail(c, MH_EINVAL, "g must be < 2^24");
+  DeDev de{prm->P, D, F, prm->G, prm->M, prm->CR, prm->seed, nullptr};
+  return launch_de_step(c, de, nullptr, problem_id, 1, g, pop, cost, trial, trial_cost, best,
+                        next_trial, nullptr, nullptr);
+}
+
+mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                        uint32_t D, const mh_de_params *prm, const double *warm, uint32_t W,
+                        uint64_t problem_id, mh_tree *out) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  s = check_de(c, prm, D);
+  if (s) return s;
+  if (!out) return fail(c, MH_EINVAL, "out is null");
+  if (W > prm->P || (W > 0 && !warm)) return fail(c, MH_EINVAL, "bad warm starts");
+  if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  return deoct(c, ds, idx, n_sub, D, prm, warm, W, problem_id, out);
+}
+
+mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
+                   const mh_de_params *prm, uint32_t flags, mh_tree *out) {
+  CTX_OR_FAIL(ctx);
+  (void)ds;
+  (void)D;
+  (void)D_MH;
+  (void)prm;
+  (void)flags;
+  (void)out;
+  return fail(&ctx->c, MH_EINVAL, "mh_train: not built yet");
+}
+
+mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                 uint8_t *feat, uint32_t *tau, uint32_t *correct) {
+  CTX_OR_FAIL(ctx);
+  (void)ds;
+  (void)idx;
+  (void)n_sub;
+  (void)feat;
+  (void)tau;
+  (void)correct;
+  return fail(&ctx->c, MH_EINVAL, "split1: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,432 @@
+// fitness.hip -- population fitness of classification trees (Algorithm 1;
+// eq. opt_c; eq. opt_all; the soft-constraint fitness of Section 3.2).
+//
+// Main kernel (depth 1..5): lane = tree, 64 trees per wave, all trees of the
+// block sharing one LDS-staged tile of up to 63 same-class samples.  For each
+// branch node the lane finds c = #{tile ranks < tau} of its feature by a
+// 6-step binary search over the tile's sorted column and takes the prefix
+// mask pm[c] = the tile samples going left.  The samples reaching node t are
+// a 64-bit mask R_t: R_1 = the tile, R_2t = R_t & pm, R_2t+1 = R_t & ~pm.  The
+// lane accumulates popcount(R_t & pm) per node in registers; since the tile
+// is single-class these are the per-(tree, node, class) left counts, and the
+// leaf counts follow from them and the class totals in the epilogue:
+// reach(1) = N_k, reach(2t) = left(t), reach(2t+1) = reach(t) - left(t).
+//
+// Walk kernel (any depth 1..10): lane = sample, the Algorithm 1 walk of one
+// tree at a time with an LDS histogram per (leaf, class).
+#include "device_common.h"
+#include "internal.h"
+
+namespace mh {
+
+size_t cnt_bytes(uint32_t n_problems, uint32_t D, uint32_t K, uint32_t P) {
+  return (size_t)n_problems * ((1u << D) - 1u) * K * pad64(P) * 4;
+}
+
+namespace {
+
+// LDS layout of one staged tile: sorted ranks [F][65] u32 (one pad word per
+// column spreads columns over banks), then prefix masks [F][65] u64.
+constexpr uint32_t SCOL = 65 * 4;
+constexpr uint32_t MCOL = 65 * 8;
+static_assert(MCOL == 2 * SCOL, "mask column offset is twice the rank column offset");
+// Byte offset of the mask region (8-byte aligned for ds_read_b64).
+__host__ __device__ __forceinline__ uint32_t mask_region(uint32_t F) {
+  return (F * SCOL + 15u) & ~15u;
+}
+
+template <int D>
+struct NodeState {
+  static constexpr int SB = (1 << D) - 1;
+  uint32_t col[SB];   // byte offset of the node feature's sorted column
+  uint32_t thr[SB];   // tau
+  uint32_t acc[SB];   // left counts since the last flush
+};
+
+// Left mask of node T over the staged tile (see the file comment).
+template <int D, int T>
+__device__ __forceinline__ uint64_t node_mask(const uint8_t *__restrict__ lds, uint32_t mregion,
+                                              const NodeState<D> &ns) {
+  uint32_t a = ns.col[T - 1];
+  const uint32_t th = ns.thr[T - 1];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    uint32_t v = *reinterpret_cast<const uint32_t *>(lds + a + (s - 1) * 4);
+    a = (v < th) ? a + s * 4 : a;
+  }
+  return *reinterpret_cast<const uint64_t *>(lds + mregion + 2 * a);
+}
+
+template <int D, int T, int LEFT>
+__device__ __forceinline__ void visit(const uint8_t *__restrict__ lds, uint32_t mregion,
+                                      NodeState<D> &ns, uint64_t R) {
+  const uint64_t m = node_mask<D, T>(lds, mregion, ns);
+  const uint64_t A = R & m;
+  ns.acc[T - 1] += (uint32_t)__popcll(A);
+  if constexpr (LEFT > 1) {
+    const uint64_t B = R & ~m;
+    visit<D, 2 * T, LEFT - 1>(lds, mregion, ns, A);
+    visit<D, 2 * T + 1, LEFT - 1>(lds, mregion, ns, B);
+  }
+}
+
+template <int D, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
+    const TileHdr *__restrict__ hdr, const uint8_t *__restrict__ feat,
+    const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt) {
+  constexpr int SB = (1 << D) - 1;
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint8_t *base = reinterpret_cast<const uint8_t *>(hdr);
+  const uint32_t F = hdr->F, K = hdr->K;
+  const uint32_t n_tiles = hdr->n_tiles;
+  const uint32_t t_begin = (uint32_t)((uint64_t)n_tiles * blockIdx.x / gridDim.x);
+  const uint32_t t_end = (uint32_t)((uint64_t)n_tiles * (blockIdx.x + 1) / gridDim.x);
+  if (t_begin >= t_end) return;
+  const uint32_t *__restrict__ info = reinterpret_cast<const uint32_t *>(base + hdr->off_info);
+  const uint8_t *__restrict__ data = base + hdr->off_data;
+  const size_t rec_bytes = tile_bytes(F);
+  const uint32_t r = blockIdx.y * (WAVES * 64) + threadIdx.x;
+  const bool live = r < P;
+  const uint32_t Ppad = pad64(P);
+  const uint32_t mregion = mask_region(F);
+
+  NodeState<D> ns;
+  uint32_t cur_sub = 0xFFFFFFFFu, cur_cls = 0xFFFFFFFFu;
+#pragma unroll
+  for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
+
+  auto flush = [&](uint32_t sub, uint32_t cls) {
+    if (!live) return;
+    uint32_t *c = cnt + ((size_t)sub * SB * K + cls) * Ppad + r;
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      if (ns.acc[t]) atomicAdd(c + (size_t)t * K * Ppad, ns.acc[t]);
+      ns.acc[t] = 0;
+    }
+  };
+
+  for (uint32_t tile = t_begin; tile < t_end; ++tile) {
+    const uint32_t inf = info[tile];
+    const uint32_t sub = inf >> 16, cls = (inf >> 8) & 0xFFu, count = inf & 0xFFu;
+    if (sub != cur_sub || cls != cur_cls) {
+      if (cur_sub != 0xFFFFFFFFu) flush(cur_sub, cur_cls);
+      if (sub != cur_sub) {
+        const uint8_t *fr = feat + ((size_t)sub * P + (live ? r : 0)) * SB;
+        const uint32_t *tr = tau + ((size_t)sub * P + (live ? r : 0)) * SB;
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+          uint32_t f = live ? fr[t] : 0u;
+          f = f <= F ? f : 0u;  // an out-of-range feature is treated as no split
+          ns.col[t] = (f ? f - 1u : 0u) * SCOL;
+          ns.thr[t] = f ? tr[t] : 0u;
+        }
+      }
+      cur_sub = sub;
+      cur_cls = cls;
+    }
+    // stage the tile record: sorted [F][64] u32 then masks [F][64] u64
+    __syncthreads();
+    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+    const uint32_t nchunk = 48u * F;  // 16-byte chunks
+    for (uint32_t c = threadIdx.x; c < nchunk; c += WAVES * 64) {
+      uint4 v = src[c];
+      if (c < 16u * F) {
+        uint32_t f = c >> 4, j0 = (c & 15u) * 4u;
+        uint32_t *d = reinterpret_cast<uint32_t *>(lds + f * SCOL) + j0;
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+      } else {
+        uint32_t cc = c - 16u * F;
+        uint32_t f = cc >> 5, e0 = (cc & 31u) * 2u;
+        uint64_t *d = reinterpret_cast<uint64_t *>(lds + mregion + f * MCOL) + e0;
+        d[0] = ((uint64_t)v.y << 32) | v.x;
+        d[1] = ((uint64_t)v.w << 32) | v.z;
+      }
+    }
+    __syncthreads();
+    const uint64_t R1 = (1ull << count) - 1ull;  // count <= 63
+    visit<D, 1, D>(lds, mregion, ns, R1);
+  }
+  flush(cur_sub, cur_cls);
+}
+
+// Epilogue from node left counts (tile path).  One thread per (sub, tree):
+// leaf counts per class by the reach recursion, then the leaf classes,
+// correct count and cost; the consumed counters are re-zeroed.
+template <int D>
+__global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ ctot,
+                                 const uint8_t *__restrict__ feat, uint32_t P, uint32_t K,
+                                 uint32_t n_problems, uint32_t n_min, double alpha,
+                                 FitnessOut out) {
+  constexpr int SB = (1 << D) - 1, SL = 1 << D;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_problems * P) return;
+  const uint32_t sub = gid / P, r = gid % P;
+  const uint32_t Ppad = pad64(P);
+  uint32_t nl[SL], best[SL], bk[SL];
+#pragma unroll
+  for (int l = 0; l < SL; ++l) nl[l] = best[l] = bk[l] = 0;
+  uint32_t n_sub = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    uint32_t reach[2 * SL];
+    reach[1] = ctot[sub * K + k];
+    n_sub += reach[1];
+#pragma unroll
+    for (int t = 1; t <= SB; ++t) {
+      uint32_t *c = cnt + (((size_t)sub * SB + (t - 1)) * K + k) * Ppad + r;
+      uint32_t a = *c;
+      *c = 0;
+      reach[2 * t] = a;
+      reach[2 * t + 1] = reach[t] - a;
+    }
+#pragma unroll
+    for (int l = 0; l < SL; ++l) {
+      uint32_t v = reach[SL + l];
+      if (out.counts) out.counts[(((size_t)sub * P + r) * SL + l) * K + k] = v;
+      nl[l] += v;
+      if (v > best[l]) {
+        best[l] = v;
+        bk[l] = k;
+      }
+    }
+  }
+  uint32_t correct = 0, nviol = 0, nsplit = 0;
+#pragma unroll
+  for (int l = 0; l < SL; ++l) {
+    correct += best[l];
+    nviol += (nl[l] > 0 && nl[l] < n_min) ? 1u : 0u;
+    if (out.label) out.label[((size_t)sub * P + r) * SL + l] = (uint8_t)bk[l];
+  }
+  const uint8_t *fr = feat + ((size_t)sub * P + r) * SB;
+#pragma unroll
+  for (int t = 0; t < SB; ++t) nsplit += fr[t] != 0;
+  if (out.correct) out.correct[(size_t)sub * P + r] = correct;
+  if (out.cost) {
+    double v = (double)(n_sub - correct);
+    v = __dadd_rn(v, __dmul_rn(alpha, (double)nsplit));
+    v = __dadd_rn(v, (double)nviol);
+    out.cost[(size_t)sub * P + r] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Walk kernel (any depth).  Block = 256 threads over a chunk of samples; for
+// each tree: stage (feat, tau) in LDS, walk every sample of the chunk down
+// the tree, histogram (leaf, class) in LDS, add the histogram to leafcnt.
+// ---------------------------------------------------------------------------
+constexpr uint32_t WALK_THREADS = 256;
+constexpr uint32_t WALK_ITEMS = 8;
+
+__global__ __launch_bounds__(WALK_THREADS) void k_fitness_walk(
+    const uint32_t *__restrict__ ranks, uint32_t ld, const uint8_t *__restrict__ labels,
+    const uint32_t *__restrict__ idx, uint32_t n_sub, const uint8_t *__restrict__ feat,
+    const uint32_t *__restrict__ tau, uint32_t P, uint32_t D, uint32_t F, uint32_t K, uint32_t n,
+    uint32_t *__restrict__ leafcnt, uint32_t hist_in_lds) {
+  extern __shared__ __align__(16) uint32_t wl[];
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
+  uint32_t *s_feat = wl;
+  uint32_t *s_tau = wl + SB;
+  uint32_t *hist = wl + 2 * SB;
+  const uint32_t j0 = blockIdx.x * WALK_THREADS * WALK_ITEMS;
+  uint32_t ii[WALK_ITEMS];
+  uint32_t yy[WALK_ITEMS];
+#pragma unroll
+  for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
+    uint32_t j = j0 + k * WALK_THREADS + threadIdx.x;
+    ii[k] = 0xFFFFFFFFu;
+    yy[k] = 0;
+    if (j < n_sub) {
+      const uint32_t i = idx ? idx[j] : j;
+      if (i < n && labels[i] < K) {  // invalid samples are left out
+        ii[k] = i;
+        yy[k] = labels[i];
+      }
+    }
+  }
+  for (uint32_t r = 0; r < P; ++r) {
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < SB; t += WALK_THREADS) {
+      uint32_t f = feat[(size_t)r * SB + t];
+      f = f <= F ? f : 0u;
+      s_feat[t] = f;
+      s_tau[t] = f ? tau[(size_t)r * SB + t] : 0u;
+    }
+    if (hist_in_lds)
+      for (uint32_t e = threadIdx.x; e < SL * K; e += WALK_THREADS) hist[e] = 0;
+    __syncthreads();
+    uint32_t *dst = leafcnt + (size_t)r * SL * K;
+#pragma unroll
+    for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
+      if (ii[k] == 0xFFFFFFFFu) continue;
+      uint32_t t = 1;
+      while (t <= SB) {
+        uint32_t f = s_feat[t - 1];
+        bool left = f != 0 && ranks[(size_t)(f - 1) * ld + ii[k]] < s_tau[t - 1];
+        t = left ? 2 * t : 2 * t + 1;
+      }
+      uint32_t e = (t - SL) * K + yy[k];
+      if (hist_in_lds)
+        atomicAdd(&hist[e], 1u);
+      else
+        atomicAdd(&dst[e], 1u);
+    }
+    if (hist_in_lds) {
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < SL * K; e += WALK_THREADS)
+        if (hist[e]) atomicAdd(&dst[e], hist[e]);
+    }
+  }
+}
+
+// Epilogue from leaf counts (walk path), any depth.  Thread per tree.
+__global__ void k_epilogue_leaves(uint32_t *__restrict__ leafcnt, const uint8_t *__restrict__ feat,
+                                  uint32_t P, uint32_t D, uint32_t K, uint32_t n_min, double alpha,
+                                  FitnessOut out) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P) return;
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
+  uint32_t correct = 0, nviol = 0, nsplit = 0, n_sub = 0;
+  for (uint32_t l = 0; l < SL; ++l) {
+    uint32_t *c = leafcnt + ((size_t)r * SL + l) * K;
+    uint32_t best = 0, bk = 0, nl = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+      uint32_t v = c[k];
+      c[k] = 0;
+      if (out.counts) out.counts[((size_t)r * SL + l) * K + k] = v;
+      nl += v;
+      if (v > best) {
+        best = v;
+        bk = k;
+      }
+    }
+    n_sub += nl;
+    correct += best;
+    nviol += (nl > 0 && nl < n_min) ? 1u : 0u;
+    if (out.label) out.label[(size_t)r * SL + l] = (uint8_t)bk;
+  }
+  for (uint32_t t = 0; t < SB; ++t) nsplit += feat[(size_t)r * SB + t] != 0;
+  if (out.correct) out.correct[r] = correct;
+  if (out.cost) {
+    double v = (double)(n_sub - correct);
+    v = __dadd_rn(v, __dmul_rn(alpha, (double)nsplit));
+    v = __dadd_rn(v, (double)nviol);
+    out.cost[r] = v;
+  }
+}
+
+template <int D, int WAVES>
+hipError_t launch_bits(const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
+                       const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
+                       hipStream_t st) {
+  size_t lds = (size_t)mask_region(F) + (size_t)F * MCOL;
+  k_fitness_bits<D, WAVES><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_bits_w(uint32_t waves, const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
+                         const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
+                         hipStream_t st) {
+  if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+  if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+  return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+}
+
+template <int D>
+void launch_epi(uint32_t *cnt, const uint32_t *ctot, const uint8_t *feat, uint32_t P, uint32_t K,
+                uint32_t n_problems, uint32_t n_min, double alpha, const FitnessOut &out,
+                hipStream_t st) {
+  uint32_t n = n_problems * P;
+  k_epilogue_nodes<D><<<(n + 127) / 128, 128, 0, st>>>(cnt, ctot, feat, P, K, n_problems, n_min,
+                                                       alpha, out);
+}
+
+}  // namespace
+
+mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint32_t n_sub,
+                               uint32_t n_problems, uint32_t max_tiles, const uint8_t *feat,
+                               const uint32_t *tau, uint32_t P, uint32_t D, uint32_t n_min,
+                               double alpha, uint32_t *cnt, const FitnessOut &out) {
+  if (D < 1 || D > 5) return fail(ctx, MH_EINVAL, "tile fitness kernel supports depth 1..5");
+  const TileHdr *hdr = reinterpret_cast<const TileHdr *>(tiles);
+  const uint8_t *b = reinterpret_cast<const uint8_t *>(tiles);
+  TileHdr h = tile_layout(n_sub, F, K, n_problems);
+  const uint32_t *ctot = reinterpret_cast<const uint32_t *>(b + h.off_ctot);
+  hipStream_t st = ctx->stream;
+  uint32_t Ppad = pad64(P);
+  uint32_t waves = Ppad / 64 >= 4 ? 4 : Ppad / 64;
+  uint32_t gy = (Ppad + waves * 64 - 1) / (waves * 64);
+  // enough blocks to fill the chip, but at least a few tiles per block
+  uint32_t want = (uint32_t)ctx->num_cu * 4u;
+  want = (want + gy - 1) / gy;
+  uint32_t cap = (max_tiles + 3) / 4;
+  uint32_t gx = want < cap ? want : cap;
+  if (gx == 0) gx = 1;
+  if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
+  hipError_t e = hipSuccess;
+  switch (D) {
+    case 1: e = launch_bits_w<1>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+    case 2: e = launch_bits_w<2>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+    case 3: e = launch_bits_w<3>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+    case 4: e = launch_bits_w<4>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+    case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "k_fitness_bits");
+  if (ctx->profile) {
+    MH_HIP(ctx, hipEventRecord(ctx->ev1, st));
+    MH_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->prof_ms += ms;
+    ctx->prof_launches += 1;
+    ctx->prof_evals += (uint64_t)n_sub * P * n_problems;  // upper bound for multi-problem sets
+    ctx->prof_tiles += max_tiles;
+  }
+  switch (D) {
+    case 1: launch_epi<1>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+    case 2: launch_epi<2>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+    case 3: launch_epi<3>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+    case 4: launch_epi<4>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+    case 5: launch_epi<5>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+  }
+  MH_LAUNCHED(ctx, "k_epilogue_nodes");
+  return MH_OK;
+}
+
+mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                              const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                              uint32_t n_min, double alpha, const FitnessOut &out) {
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
+  const size_t cells = (size_t)P * SL * ds->K;
+  uint32_t *leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
+  if (!leafcnt) return MH_ENOMEM;
+  hipStream_t st = ctx->stream;
+  MH_HIP(ctx, hipMemsetAsync(leafcnt, 0, cells * 4, st));
+  const uint32_t hist_cells = SL * ds->K;
+  const uint32_t in_lds = hist_cells <= 12288u ? 1u : 0u;
+  size_t lds = (size_t)(2 * SB + (in_lds ? hist_cells : 0u)) * 4;
+  if (n_sub > 0) {
+    uint32_t blocks = (n_sub + WALK_THREADS * WALK_ITEMS - 1) / (WALK_THREADS * WALK_ITEMS);
+    if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
+    k_fitness_walk<<<blocks, WALK_THREADS, lds, st>>>(ds->ranks, ds->ld, ds->labels, idx, n_sub,
+                                                      feat, tau, P, D, ds->F, ds->K, ds->n,
+                                                      leafcnt, in_lds);
+    MH_LAUNCHED(ctx, "k_fitness_walk");
+    if (ctx->profile) {
+      MH_HIP(ctx, hipEventRecord(ctx->ev1, st));
+      MH_HIP(ctx, hipEventSynchronize(ctx->ev1));
+      float ms = 0.f;
+      MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      ctx->prof_ms += ms;
+      ctx->prof_launches += 1;
+      ctx->prof_evals += (uint64_t)n_sub * P;
+    }
+  }
+  k_epilogue_leaves<<<(P + 127) / 128, 128, 0, st>>>(leafcnt, feat, P, D, ds->K, n_min, alpha, out);
+  MH_LAUNCHED(ctx, "k_epilogue_leaves");
+  return MH_OK;
+}
+
+}  // namespace mh

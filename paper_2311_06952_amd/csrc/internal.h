@@ -1,0 +1,169 @@
+// internal.h -- host-side internals shared by the library's translation
+// units: the context, its device arena, error reporting, the tiled sample
+// layout and the kernel launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mhdeoct.h"
+
+namespace mh {
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct Arena {
+  // Named, growable device buffers owned by the context.  Each name keeps
+  // one allocation that is reallocated (without copying) when a larger size
+  // is asked for.
+  struct Buf {
+    std::string name;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::vector<Buf> bufs;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  std::string err;
+  Arena arena;
+  // fitness-kernel timing
+  bool profile = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint64_t prof_launches = 0, prof_evals = 0, prof_tiles = 0;
+  double prof_ms = 0.0;
+};
+
+// Returns a device buffer of at least `bytes` for `name`, or nullptr (and
+// sets ctx->err) on allocation failure.
+void *arena_get(Ctx *ctx, const char *name, size_t bytes);
+
+mh_status fail(Ctx *ctx, mh_status code, const std::string &msg);
+mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what);
+
+#define MH_HIP(ctx, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+#define MH_LAUNCHED(ctx, what)                             \
+  do {                                                     \
+    hipError_t e_ = hipGetLastError();                     \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, what); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Tiled sample layout (the fitness kernel's input).
+//
+// Samples of each (subproblem, class) segment are cut into tiles of at most
+// TILE_CAP = 63.  A tile record holds, per feature f, the tile's ranks in
+// ascending order (64 u32; unused entries 0xFFFFFFFF) followed, per feature,
+// by the 64 prefix masks pm[c] = set of tile positions of the c smallest
+// ranks (u64; pm[0] = 0).  "rank < tau" over the tile is then pm[c] with
+// c = #{sorted ranks < tau}, found by binary search.
+// ---------------------------------------------------------------------------
+constexpr uint32_t TILE_CAP = 63;
+constexpr uint32_t TILE_W = 64;
+constexpr uint32_t TILE_MAGIC = 0x3154484du;  // "MHT1"
+
+struct TileHdr {
+  uint32_t magic;
+  uint32_t F, K;
+  uint32_t n_sub;        // samples in the layout
+  uint32_t n_tiles;      // tiles in use (written on the device)
+  uint32_t max_tiles;    // capacity
+  uint32_t n_problems;   // subproblems
+  uint32_t pad0;
+  uint64_t off_info;     // u32 [max_tiles]: sub << 16 | class << 8 | count
+  uint64_t off_ctot;     // u32 [n_problems][K]: samples per class
+  uint64_t off_data;     // [max_tiles][tile_bytes(F)]
+  uint64_t off_order;    // u32 [max_tiles][64]: sample ids (build scratch)
+  uint64_t off_segoff;   // u32 [n_problems * K + 1]: first tile of a segment
+  uint64_t off_cursor;   // u32 [n_problems * K]: fill cursors (build scratch)
+  uint64_t total_bytes;
+  uint32_t pad1[64 - 22];
+};
+static_assert(sizeof(TileHdr) == 256, "tile header is 256 bytes");
+
+__host__ __device__ inline size_t tile_bytes(uint32_t F) { return (size_t)F * (TILE_W * 4 + TILE_W * 8); }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline uint32_t max_tiles_for(uint32_t n_sub, uint32_t n_problems, uint32_t K) {
+  return (n_sub + TILE_CAP - 1) / TILE_CAP + n_problems * K;
+}
+// Host-side layout of a tile set (offsets only; no device access).
+TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (one per .hip file)
+// ---------------------------------------------------------------------------
+// rank_encode.hip
+mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F,
+                             uint32_t ld, uint32_t *ranks, uint32_t *n_unique);
+// Sorts (key, value) pairs by the low `key_bits` of key (stable LSD radix
+// sort, 8 bits per pass).  Buffers are ping-ponged; the sorted result ends in
+// (*keys, *vals) which may point at the alternate buffers on return.
+mh_status radix_sort_pairs(Ctx *ctx, uint64_t **keys, uint32_t **vals, uint64_t *keys_alt,
+                           uint32_t *vals_alt, uint32_t count, uint32_t key_bits);
+
+// tiles.hip
+// Builds the tiled layout at `base` for samples idx[0..n_sub) (all if
+// idx == nullptr); sub_of (device [n_sub], may be null) assigns each sample a
+// subproblem < n_problems.
+mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                            const uint32_t *sub_of, uint32_t n_sub, uint32_t n_problems,
+                            void *base, size_t bytes);
+
+// fitness.hip
+struct FitnessOut {
+  uint32_t *counts = nullptr;   // [sub][P][SL][K]
+  uint32_t *correct = nullptr;  // [sub][P]
+  uint8_t *label = nullptr;     // [sub][P][SL]
+  double *cost = nullptr;       // [sub][P]
+};
+// Node-count accumulator size for a tile set: [n_problems][SB][K][Ppad].
+size_t cnt_bytes(uint32_t n_problems, uint32_t D, uint32_t K, uint32_t P);
+__host__ __device__ inline uint32_t pad64(uint32_t P) { return (P + 63u) & ~63u; }
+// Evaluate trees feat/tau ([n_problems][P][SB]) over the tile set: accumulates
+// into cnt (must be zero), then the epilogue writes `out` and re-zeroes cnt.
+mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                               uint32_t n_sub, uint32_t n_problems, uint32_t max_tiles,
+                               const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                               uint32_t D, uint32_t n_min, double alpha, uint32_t *cnt,
+                               const FitnessOut &out);
+// Direct per-sample walk for any depth (1..10): one tree at a time, leaf
+// counts per (tree, leaf, class), then the same epilogue.
+mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                              uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
+                              uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                              const FitnessOut &out);
+
+// de.hip
+struct DeDev {
+  uint32_t P, D, F, G;
+  double M, CR;
+  uint64_t seed;
+  const uint32_t *n_unique;
+};
+mh_status launch_de_init(Ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
+                         const uint64_t *prob_ids, uint64_t prob_base, uint32_t n_problems,
+                         const double *warm, uint32_t W, double *pop);
+mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
+                        const uint32_t *n_unique, uint8_t *feat, uint32_t *tau,
+                        uint32_t n_problems, const uint32_t *row_sel);
+// One DE step for n_problems problems (block per problem).  When feat/tau are
+// given, the new trial population is also decoded into them.
+mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
+                         uint64_t prob_base, uint32_t n_problems, uint32_t g, double *pop,
+                         double *cost, const double *trial, const double *trial_cost,
+                         uint32_t *best, double *next_trial, uint8_t *feat, uint32_t *tau);
+
+}  // namespace mh

@@ -1,0 +1,223 @@
+// tiles.hip -- builds the tiled sample layout the fitness kernel reads.
+//
+// The fitness of a tree only depends on how many samples of each class reach
+// each leaf (eq. opt_c), so samples may be regrouped freely.  They are grouped
+// by (subproblem, class) and cut into tiles of at most 63.  For every tile and
+// feature the 63 ranks are sorted once; the set of tile samples with
+// rank < tau is then a prefix of that order, i.e. one of 64 precomputed
+// bitmasks, selected by a 6-step binary search.  Every tree of the population
+// reuses the same tile, so the sort cost is paid once per dataset (or once
+// per moving-horizon level), not once per evaluation.
+#include "device_common.h"
+#include "internal.h"
+
+namespace mh {
+
+TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems) {
+  TileHdr h{};
+  h.magic = TILE_MAGIC;
+  h.F = F;
+  h.K = K;
+  h.n_sub = n_sub;
+  h.n_tiles = 0;
+  h.max_tiles = max_tiles_for(n_sub, n_problems, K);
+  h.n_problems = n_problems;
+  size_t off = 256;
+  h.off_info = off;
+  off = align256(off + (size_t)h.max_tiles * 4);
+  h.off_ctot = off;
+  off = align256(off + (size_t)n_problems * K * 4);
+  h.off_data = off;
+  off = align256(off + (size_t)h.max_tiles * tile_bytes(F));
+  h.off_order = off;
+  off = align256(off + (size_t)h.max_tiles * TILE_W * 4);
+  h.off_segoff = off;
+  off = align256(off + ((size_t)n_problems * K + 1) * 4);
+  h.off_cursor = off;
+  off = align256(off + (size_t)n_problems * K * 4);
+  h.total_bytes = off;
+  return h;
+}
+
+namespace {
+
+// The header travels as a kernel argument (no host buffer outlives the call).
+__global__ void k_tile_hdr(TileHdr *__restrict__ dst, TileHdr h) { *dst = h; }
+
+// Per-(subproblem, class) sample counts.
+// Samples with an index >= n, a label >= K or a subproblem >= n_problems are
+// invalid input and are left out (here and in the scatter).
+__device__ __forceinline__ bool sample_ok(const uint8_t *__restrict__ labels,
+                                          const uint32_t *__restrict__ idx,
+                                          const uint32_t *__restrict__ sub_of, uint32_t j,
+                                          uint32_t n, uint32_t K, uint32_t n_problems,
+                                          uint32_t &i, uint32_t &seg) {
+  i = idx ? idx[j] : j;
+  if (i >= n) return false;
+  const uint32_t y = labels[i];
+  const uint32_t s = sub_of ? sub_of[j] : 0u;
+  if (y >= K || s >= n_problems) return false;
+  seg = s * K + y;
+  return true;
+}
+
+__global__ void k_tile_count(const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
+                             const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n,
+                             uint32_t K, uint32_t n_problems, uint32_t *__restrict__ ctot) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_sub) return;
+  uint32_t i, seg;
+  if (sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) atomicAdd(&ctot[seg], 1u);
+}
+
+// Segment plan: tiles per (subproblem, class) segment, their first tile, and
+// the info word of every tile.  One block; segments are few (<= 128 * 255).
+__global__ void k_tile_plan(TileHdr *__restrict__ hdr, uint32_t nseg) {
+  uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
+  const uint32_t *ctot = reinterpret_cast<const uint32_t *>(base + hdr->off_ctot);
+  uint32_t *segoff = reinterpret_cast<uint32_t *>(base + hdr->off_segoff);
+  uint32_t *cursor = reinterpret_cast<uint32_t *>(base + hdr->off_cursor);
+  uint32_t *info = reinterpret_cast<uint32_t *>(base + hdr->off_info);
+  const uint32_t K = hdr->K;
+  __shared__ uint32_t carry;
+  __shared__ uint32_t part[1024];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  // exclusive scan of tiles-per-segment, in chunks of blockDim
+  for (uint32_t s0 = 0; s0 < nseg; s0 += blockDim.x) {
+    uint32_t s = s0 + threadIdx.x;
+    uint32_t v = (s < nseg) ? (ctot[s] + TILE_CAP - 1) / TILE_CAP : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
+      uint32_t t = (threadIdx.x >= d) ? part[threadIdx.x - d] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (s < nseg) {
+      segoff[s] = carry + part[threadIdx.x] - v;
+      cursor[s] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) carry += part[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    segoff[nseg] = carry;
+    hdr->n_tiles = carry;
+  }
+  __syncthreads();
+  // info words
+  for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) {
+    uint32_t c = ctot[s];
+    uint32_t t0 = segoff[s];
+    uint32_t sub = s / K, cls = s % K;
+    for (uint32_t q = 0; q * TILE_CAP < c; ++q) {
+      uint32_t cnt = min(TILE_CAP, c - q * TILE_CAP);
+      info[t0 + q] = (sub << 16) | (cls << 8) | cnt;
+    }
+  }
+}
+
+// Scatter sample ids into their tile slots.  The order inside a segment is
+// whatever the atomics give; counts do not depend on it.
+__global__ void k_tile_scatter(const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
+                               const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n,
+                               TileHdr *__restrict__ hdr) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_sub) return;
+  uint32_t i, s;
+  if (!sample_ok(labels, idx, sub_of, j, n, hdr->K, hdr->n_problems, i, s)) return;
+  uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
+  const uint32_t *segoff = reinterpret_cast<const uint32_t *>(base + hdr->off_segoff);
+  uint32_t *cursor = reinterpret_cast<uint32_t *>(base + hdr->off_cursor);
+  uint32_t *order = reinterpret_cast<uint32_t *>(base + hdr->off_order);
+  uint32_t pos = atomicAdd(&cursor[s], 1u);
+  uint32_t tile = segoff[s] + pos / TILE_CAP;
+  order[tile * TILE_W + pos % TILE_CAP] = i;
+}
+
+// One wave per (tile, feature): sort the tile's ranks with their positions
+// (bitonic network across the 64 lanes), write the sorted ranks and the
+// prefix masks of the positions in sorted order.
+__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ ranks, uint32_t ld,
+                                                   TileHdr *__restrict__ hdr) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t F = hdr->F;
+  const uint32_t tile = w / F, f = w % F;
+  if (tile >= hdr->n_tiles) return;
+  uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
+  const uint32_t info = reinterpret_cast<const uint32_t *>(base + hdr->off_info)[tile];
+  const uint32_t *order = reinterpret_cast<const uint32_t *>(base + hdr->off_order);
+  const uint32_t cnt = info & 0xFFu;
+  uint32_t key = 0xFFFFFFFFu;
+  if (lane < cnt) key = ranks[(size_t)f * ld + order[tile * TILE_W + lane]];
+  // composite (key, position): distinct, so the network sorts a total order
+  uint64_t v = ((uint64_t)key << 6) | lane;
+#pragma unroll
+  for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      uint64_t o = __shfl_xor(v, (int)j, 64);
+      bool up = (lane & k) == 0;
+      bool lo = (lane & j) == 0;
+      uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+      v = (lo == up) ? mn : mx;
+    }
+  }
+  const uint32_t skey = (uint32_t)(v >> 6);
+  const uint32_t pos = (uint32_t)(v & 63u);
+  uint64_t bit = (lane < cnt) ? (1ull << pos) : 0ull;
+  // inclusive OR-scan over lanes: pm[lane + 1]
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t t = __shfl_up(bit, (unsigned)d, 64);
+    if ((int)lane >= d) bit |= t;
+  }
+  uint8_t *rec = base + hdr->off_data + (size_t)tile * tile_bytes(F);
+  uint32_t *sorted = reinterpret_cast<uint32_t *>(rec) + f * TILE_W;
+  uint64_t *pm = reinterpret_cast<uint64_t *>(rec + (size_t)F * TILE_W * 4) + f * TILE_W;
+  sorted[lane] = skey;
+  if (lane < 63u) pm[lane + 1] = bit;
+  else pm[0] = 0ull;
+}
+
+}  // namespace
+
+mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                            const uint32_t *sub_of, uint32_t n_sub, uint32_t n_problems,
+                            void *base, size_t bytes) {
+  TileHdr h = tile_layout(n_sub, ds->F, ds->K, n_problems);
+  if (bytes < h.total_bytes) return fail(ctx, MH_EINVAL, "tile buffer too small");
+  if (((uintptr_t)base & 255u) != 0) return fail(ctx, MH_EINVAL, "tile buffer not 256-byte aligned");
+  if (n_problems == 0 || n_problems > 65535) return fail(ctx, MH_EINVAL, "bad subproblem count");
+  hipStream_t st = ctx->stream;
+  TileHdr *dh = reinterpret_cast<TileHdr *>(base);
+  k_tile_hdr<<<1, 1, 0, st>>>(dh, h);
+  MH_LAUNCHED(ctx, "k_tile_hdr");
+  uint8_t *b = reinterpret_cast<uint8_t *>(base);
+  MH_HIP(ctx, hipMemsetAsync(b + h.off_ctot, 0, (size_t)n_problems * ds->K * 4, st));
+  const uint32_t nseg = n_problems * ds->K;
+  if (n_sub > 0) {
+    uint32_t nb = (n_sub + 255) / 256;
+    k_tile_count<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, ds->K, n_problems,
+                                     reinterpret_cast<uint32_t *>(b + h.off_ctot));
+    MH_LAUNCHED(ctx, "k_tile_count");
+  }
+  k_tile_plan<<<1, 1024, 0, st>>>(dh, nseg);
+  MH_LAUNCHED(ctx, "k_tile_plan");
+  if (n_sub > 0) {
+    uint32_t nb = (n_sub + 255) / 256;
+    k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, dh);
+    MH_LAUNCHED(ctx, "k_tile_scatter");
+    uint64_t waves = (uint64_t)h.max_tiles * ds->F;
+    uint32_t blocks = (uint32_t)((waves + 3) / 4);
+    k_tile_sort<<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
+    MH_LAUNCHED(ctx, "k_tile_sort");
+  }
+  return MH_OK;
+}
+
+}  // namespace mh

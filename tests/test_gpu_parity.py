@@ -1,0 +1,243 @@
+"""GPU parity: every step of the HIP path against the oracle, element by
+element, on seeded inputs.  All results are integers or exactly rounded f64,
+so the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, np_, random_trees, u32
+from paper_2311_06952_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mh():
+    import paper_2311_06952_amd as m
+    return m
+
+
+def gpu_ds(mh, X, y, K):
+    return mh.dataset(X, y, K)
+
+
+# ---------------------------------------------------------------- rank encode
+@pytest.mark.parametrize("seed,n,F,levels", [(1, 1, 1, None), (2, 63, 3, None), (3, 64, 2, 5),
+                                             (4, 1000, 4, 17), (5, 4097, 7, None),
+                                             (6, 100_000, 16, None), (7, 20_000, 33, 300)])
+def test_rank_encode(mh, seed, n, F, levels):
+    X, y = synth.random_small(seed, n, F, 3, levels)
+    want_r, want_nu = oracle.rank_encode(X)
+    ds = gpu_ds(mh, X, y, 3)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :n], want_r)
+
+
+def test_rank_encode_signed_zero_and_nan(mh):
+    X = np.array([[0.0, 1.0], [-0.0, 1.0], [-2.5, np.inf], [3.0, -np.inf]], dtype=np.float32)
+    want_r, want_nu = oracle.rank_encode(X)
+    ds = gpu_ds(mh, X, np.zeros(4, np.uint8), 2)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :4], want_r)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    Xn = X.copy()
+    Xn[2, 1] = np.nan
+    with pytest.raises(mh.MhError):
+        gpu_ds(mh, Xn, np.zeros(4, np.uint8), 2)
+
+
+# --------------------------------------------------------------------- decode
+def test_decode_edges(mh):
+    rng = np.random.default_rng(0)
+    F, D = 5, 3
+    SB = (1 << D) - 1
+    nu = np.array([1, 2, 7, 255, 100_000], dtype=np.uint32)
+    P = 400
+    genes = np.column_stack([rng.random((P, SB)) * 7 - 0.5, rng.random((P, SB)) * 1.2 - 0.1])
+    # interval ends, one ulp either side, range ends, NaN
+    for r in range(0, P, 4):
+        f = rng.integers(1, F + 1)
+        k = rng.integers(0, nu[f - 1] + 1)
+        b = k / (nu[f - 1] + 1.0)
+        genes[r, 0] = f + 0.25
+        genes[r, SB] = [b, np.nextafter(b, 0), np.nextafter(b, 2), 1.0][r % 4]
+    genes[1, 1] = np.nan
+    genes[2, SB + 1] = np.nan
+    genes[3, 2] = F + 1.0
+    genes[5, 3] = -0.0
+    want_f, want_t = oracle.decode(genes, D, F, nu)
+    gf, gt = mh.tree_decode(dev(genes), D, F, dev(nu))
+    np.testing.assert_array_equal(np_(gf), want_f)
+    np.testing.assert_array_equal(u32(gt), want_t)
+
+
+# -------------------------------------------------------------------- fitness
+FIT_CASES = [
+    # seed, n, F, K, D, P, levels
+    (1, 1, 2, 2, 1, 1, None),
+    (2, 63, 3, 2, 2, 3, None),
+    (3, 64, 3, 3, 3, 64, 4),
+    (4, 127, 4, 5, 4, 65, None),
+    (5, 5000, 6, 4, 5, 130, 50),
+    (6, 3001, 8, 1, 3, 256, None),
+    (7, 20_000, 16, 3, 3, 300, None),
+    (8, 2000, 5, 3, 6, 20, 30),      # walk path
+    (9, 1500, 4, 2, 8, 5, None),     # walk path
+    (10, 700, 90, 3, 2, 40, None),   # F > 80: walk path
+]
+
+
+@pytest.mark.parametrize("seed,n,F,K,D,P,levels", FIT_CASES)
+def test_fitness(mh, seed, n, F, K, D, P, levels):
+    X, y = synth.random_small(seed, n, F, K, levels)
+    ods = oracle.dataset_from_X(X, y, K)
+    rng = np.random.default_rng(seed)
+    feat, tau = random_trees(rng, P, D, F, ods.n_unique)
+    want = oracle.fitness(ods, feat, tau, D)
+    ds = gpu_ds(mh, X, y, K)
+    got = mh.fitness_eval(ds, dev(feat), dev(tau), D)
+    np.testing.assert_array_equal(u32(got[0]), want[0])
+    np.testing.assert_array_equal(u32(got[1]), want[1])
+    np.testing.assert_array_equal(np_(got[2]), want[2])
+    np.testing.assert_array_equal(np_(got[3]), want[3])
+
+
+@pytest.mark.parametrize("D", [2, 4, 6])
+def test_fitness_subset_and_penalties(mh, D):
+    X, y = synth.random_small(11, 3000, 5, 3, 40)
+    ods = oracle.dataset_from_X(X, y, 3)
+    rng = np.random.default_rng(D)
+    feat, tau = random_trees(rng, 70, D, 5, ods.n_unique)
+    idx = np.sort(rng.choice(3000, size=1234, replace=False)).astype(np.uint32)
+    want = oracle.fitness(ods, feat, tau, D, idx=idx, n_min=7, alpha=0.375)
+    ds = gpu_ds(mh, X, y, 3)
+    got = mh.fitness_eval(ds, dev(feat), dev(tau), D, idx=dev(idx), n_min=7, alpha=0.375)
+    np.testing.assert_array_equal(u32(got[0]), want[0])
+    np.testing.assert_array_equal(np_(got[2]), want[2])
+    np.testing.assert_array_equal(np_(got[3]), want[3])
+
+
+def test_fitness_empty_subset(mh):
+    X, y = synth.random_small(12, 100, 3, 2)
+    ds = gpu_ds(mh, X, y, 2)
+    feat = np.ones((4, 3), np.uint8)
+    tau = np.ones((4, 3), np.uint32)
+    idx = dev(np.zeros(0, np.uint32))
+    got = mh.fitness_eval(ds, dev(feat), dev(tau), 2, idx=idx)
+    assert u32(got[0]).sum() == 0 and (u32(got[1]) == 0).all()
+    assert (np_(got[3]) == 0).all()
+
+
+def test_tileset_reuse_matches(mh):
+    X, y = synth.random_small(13, 9000, 6, 4, None)
+    ods = oracle.dataset_from_X(X, y, 4)
+    rng = np.random.default_rng(1)
+    ds = gpu_ds(mh, X, y, 4)
+    ts = mh.TileSet(ds)
+    for D in (1, 3, 5):
+        feat, tau = random_trees(rng, 100, D, 6, ods.n_unique)
+        want = oracle.fitness(ods, feat, tau, D)
+        import torch
+        SL = 1 << D
+        out = (torch.zeros((100, SL, 4), dtype=torch.int32, device="cuda"),
+               torch.zeros(100, dtype=torch.int32, device="cuda"),
+               torch.zeros((100, SL), dtype=torch.uint8, device="cuda"),
+               torch.zeros(100, dtype=torch.float64, device="cuda"))
+        for _ in range(2):  # the counters are re-zeroed by each call
+            ts.fitness(dev(feat), dev(tau), D, out=out)
+            np.testing.assert_array_equal(u32(out[0]), want[0])
+            np.testing.assert_array_equal(np_(out[3]), want[3])
+
+
+# ------------------------------------------------------------------------- DE
+def test_de_init_and_steps(mh):
+    P, D, F = 37, 3, 6
+    SB = (1 << D) - 1
+    rng = np.random.default_rng(4)
+    warm = rng.random((3, 2 * SB))
+    want = oracle.de_init(P, D, F, 99, 5, warm)
+    got = mh.de_init(P, D, F, 99, 5, warm=dev(warm))
+    np.testing.assert_array_equal(np_(got), want)
+    prm = mh.de_params(P, 10, M=0.7, CR=0.3, seed=99)
+    cost = rng.integers(0, 5, size=P).astype(np.float64)
+    pop = want.copy()
+    gpop, gcost = got, dev(cost)
+    for g in range(1, 5):
+        trial = oracle.de_trial(pop, D, F, 0.7, 0.3, 99, 5, g, oracle.argmin(cost))
+        tcost = rng.integers(0, 5, size=P).astype(np.float64)
+        # device: selection of the previous trial is done by the next step
+        best, gtrial = mh.de_step(prm, D, F, 5, g, gpop, gcost)
+        assert int(np_(best)[0]) == oracle.argmin(cost)
+        np.testing.assert_array_equal(np_(gtrial), trial)
+        oracle.de_select(pop, cost, trial, tcost)
+        mh.de_step(prm, D, F, 5, g, gpop, gcost, trial=gtrial, trial_cost=dev(tcost),
+                   make_trial=False)
+        np.testing.assert_array_equal(np_(gpop), pop)
+        np.testing.assert_array_equal(np_(gcost), cost)
+
+
+def test_de_random_mutation_factor(mh):
+    P, D, F = 50, 2, 4
+    pop = oracle.de_init(P, D, F, 3, 0)
+    want = oracle.de_trial(pop, D, F, -1.0, 0.5, 3, 0, 7, 11)
+    cost = np.full(P, 9.0)
+    cost[11] = 1.0
+    prm = mh.de_params(P, 10, M=-1.0, CR=0.5, seed=3)
+    _, gtrial = mh.de_step(prm, D, F, 0, 7, dev(pop), dev(cost))
+    np.testing.assert_array_equal(np_(gtrial), want)
+
+
+# -------------------------------------------------------------------- DEOCT
+def _deoct_both(mh, w, seed, G=None, idx=None, P=None, prob=0, warm=None):
+    G = w.G if G is None else G
+    P = w.P if P is None else P
+    ods = oracle.dataset_from_X(w.X, w.y, w.K)
+    prm_o = oracle.de_params(P, G, w.M, w.CR, seed)
+    want = oracle.deoct(ods, w.D, prm_o, idx=idx, warm=warm, prob=prob)
+    ds = gpu_ds(mh, w.X, w.y, w.K)
+    prm = mh.de_params(P, G, w.M, w.CR, seed)
+    got = mh.subtree_solve(ds, w.D, prm, idx=None if idx is None else dev(idx), warm=warm,
+                           prob=prob)
+    return want, got, ods
+
+
+def _same_tree(want, got):
+    np.testing.assert_array_equal(got["feat"], want["feat"])
+    np.testing.assert_array_equal(got["tau"], want["tau"])
+    np.testing.assert_array_equal(got["label"], want["label"])
+    assert got["correct"] == want["correct"]
+    assert got["cost"] == want["cost"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_subtree_solve_plain_small(mh, seed):
+    """n = 1000, F = 4, K = 2, depth 2, P = 32, 50 generations (M = 0.5,
+    CR = 0.9): identical to the oracle and never above the exact optimum."""
+    w = synth.plain_small(seed)
+    want, got, ods = _deoct_both(mh, w, 1000 + seed)
+    _same_tree(want, got)
+    assert got["correct"] <= oracle.opt2(ods)[0]
+
+
+def test_subtree_solve_subset_warm_and_random_m(mh):
+    w = synth.plain_small(6, n=2000)
+    w.M = -1.0
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(2000, 1500, replace=False)).astype(np.uint32)
+    warm = rng.random((2, 6)) * [5, 5, 5, 1, 1, 1]
+    want, got, _ = _deoct_both(mh, w, 77, G=20, idx=idx, warm=warm, prob=9)
+    _same_tree(want, got)
+
+
+def test_subtree_solve_plain_scale_full_n(mh):
+    """n = 100,000, F = 16, K = 3, depth 3, P = 256 at full size, 5
+    generations (the oracle's share of the run is a few seconds)."""
+    w = synth.plain_scale(1)
+    want, got, _ = _deoct_both(mh, w, 1001, G=5)
+    _same_tree(want, got)
+
+
+def test_subtree_solve_depth6_walk_path(mh):
+    w = synth.plain_small(7, n=1500)
+    w.D = 6
+    want, got, _ = _deoct_both(mh, w, 5, G=6, P=12)
+    _same_tree(want, got)
