@@ -1,6 +1,8 @@
 // api.hip -- the C ABI (include/mhdeoct.h): context, arena, argument checks
 // and the host-side orchestration of the device kernels.
+#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -162,22 +164,39 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   if (s) return s;
   s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr);
   if (s) return s;
-  FitnessOut fo;
-  fo.cost = cost;
-  s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, fo);
-  if (s) return s;
-  // best of generation 0, and the trial population of generation 1
-  s = launch_de_step(ctx, de, nullptr, prob, 1, 1, pop, cost, nullptr, nullptr, best,
-                     prm->G >= 1 ? trial : nullptr, feat, tau);
-  if (s) return s;
-  FitnessOut ft;
-  ft.cost = tcost;
-  for (uint32_t g = 1; g <= prm->G; ++g) {
-    s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, ft);
+  if (es.tiles) {
+    // tile path: per generation the counting kernel, then the epilogue fused
+    // with selection, best and the next trial
+    const TileHdr h = tile_layout(n_sub, ds->F, K, 1);
+    const uint32_t *ctot =
+        reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(es.tiles) + h.off_ctot);
+    for (uint32_t g = 0; g <= prm->G; ++g) {
+      s = launch_fitness_count(ctx, es.tiles, ds->F, K, n_sub, 1, es.max_tiles, feat, tau, P, D,
+                               es.cnt);
+      if (s) return s;
+      s = launch_de_gen(ctx, de, nullptr, prob, 1, g + 1, g == 0, pop, cost, trial, best,
+                        g < prm->G ? trial : nullptr, feat, tau, es.cnt, ctot, K, prm->n_min,
+                        prm->alpha);
+      if (s) return s;
+    }
+  } else {
+    FitnessOut fo;
+    fo.cost = cost;
+    s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, fo);
     if (s) return s;
-    s = launch_de_step(ctx, de, nullptr, prob, 1, g + 1, pop, cost, trial, tcost, best,
-                       g < prm->G ? trial : nullptr, feat, tau);
+    // best of generation 0, and the trial population of generation 1
+    s = launch_de_step(ctx, de, nullptr, prob, 1, 1, pop, cost, nullptr, nullptr, best,
+                       prm->G >= 1 ? trial : nullptr, feat, tau);
     if (s) return s;
+    FitnessOut ft;
+    ft.cost = tcost;
+    for (uint32_t g = 1; g <= prm->G; ++g) {
+      s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, ft);
+      if (s) return s;
+      s = launch_de_step(ctx, de, nullptr, prob, 1, g + 1, pop, cost, trial, tcost, best,
+                         g < prm->G ? trial : nullptr, feat, tau);
+      if (s) return s;
+    }
   }
   // the best individual: decode and evaluate for its labels
   s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best);
@@ -197,6 +216,27 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   MH_HIP(ctx, hipMemcpyAsync(&out->cost, cost1, 8, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipStreamSynchronize(st));
   (void)K;
+  return MH_OK;
+}
+
+// Sequential moving-horizon step: DEOCT on the samples at node t, problem id
+// t; returns the root of the best subtree.
+static mh_status solve_node(Ctx *ctx, const mh_dataset *ds, const uint32_t *node_of, uint32_t t,
+                            uint32_t De, const mh_de_params *prm, uint8_t *feat, uint32_t *tau) {
+  uint32_t *idx = (uint32_t *)arena_get(ctx, "mh_idx", (size_t)(ds->n ? ds->n : 1) * 4);
+  uint32_t *cursor = nullptr;
+  if (!idx) return MH_ENOMEM;
+  mh_status s = launch_compact(ctx, node_of, ds->n, t, idx);
+  if (s) return s;
+  cursor = (uint32_t *)arena_get(ctx, "mh_cursor", 256);
+  uint32_t n_t = 0;
+  MH_HIP(ctx, hipMemcpyAsync(&n_t, cursor, 4, hipMemcpyDeviceToHost, ctx->stream));
+  MH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  mh_tree tr;
+  s = deoct(ctx, ds, idx, n_t, De, prm, nullptr, 0, t, &tr);
+  if (s) return s;
+  *feat = tr.feat[0];
+  *tau = tr.tau[0];
   return MH_OK;
 }
 
@@ -231,6 +271,9 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)
     c->c.num_cu = cus;
+  // launch-shape overrides for tuning sweeps
+  if (const char *v = std::getenv("MHDEOCT_FIT_BLOCKS_PER_CU")) c->c.fit_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
+  if (const char *v = std::getenv("MHDEOCT_FIT_MIN_TILES")) c->c.fit_min_tiles = (uint32_t)std::max(1, atoi(v));
   if (hipEventCreate(&c->c.ev0) != hipSuccess || hipEventCreate(&c->c.ev1) != hipSuccess) {
     delete c;
     return fail(nullptr, MH_EDEVICE, "hipEventCreate failed");
@@ -416,25 +459,28 @@ mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, 
 mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
                    const mh_de_params *prm, uint32_t flags, mh_tree *out) {
   CTX_OR_FAIL(ctx);
-  (void)ds;
-  (void)D;
-  (void)D_MH;
-  (void)prm;
-  (void)flags;
-  (void)out;
-  return fail(&ctx->c, MH_EINVAL, "mh_train: not built yet");
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  s = check_de(c, prm, D);
+  if (s) return s;
+  if (!out) return fail(c, MH_EINVAL, "out is null");
+  if (D_MH < 1) return fail(c, MH_EINVAL, "D_MH must be >= 1");
+  if (flags & ~MH_BATCHED) return fail(c, MH_EINVAL, "unknown flags");
+  if ((flags & MH_BATCHED) && (std::min(D_MH, D) > 5 || ds->F > 80))
+    return fail(c, MH_EINVAL, "the batched form needs subtree depth <= 5 and F <= 80");
+  return mh_train_impl(c, ds, D, D_MH, prm, flags, out, solve_node);
 }
 
 mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                  uint8_t *feat, uint32_t *tau, uint32_t *correct) {
   CTX_OR_FAIL(ctx);
-  (void)ds;
-  (void)idx;
-  (void)n_sub;
-  (void)feat;
-  (void)tau;
-  (void)correct;
-  return fail(&ctx->c, MH_EINVAL, "split1: not built yet");
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  if (!feat || !tau || !correct) return fail(c, MH_EINVAL, "null output");
+  if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  return split1_subset(c, ds, idx, n_sub, feat, tau, correct);
 }
 
 }  // extern "C"

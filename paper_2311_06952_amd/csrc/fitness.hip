@@ -15,12 +15,13 @@
 // Walk kernel (any depth 1..10): lane = sample, the Algorithm 1 walk of one
 // tree at a time with an LDS histogram per (leaf, class).
 #include "device_common.h"
+#include "epilogue.h"
 #include "internal.h"
 
 namespace mh {
 
 size_t cnt_bytes(uint32_t n_problems, uint32_t D, uint32_t K, uint32_t P) {
-  return (size_t)n_problems * ((1u << D) - 1u) * K * pad64(P) * 4;
+  return CNT_REP * cnt_copy_elems(n_problems, (1u << D) - 1u, K, P) * 4;
 }
 
 namespace {
@@ -38,35 +39,93 @@ __host__ __device__ __forceinline__ uint32_t mask_region(uint32_t F) {
 template <int D>
 struct NodeState {
   static constexpr int SB = (1 << D) - 1;
-  uint32_t col[SB];   // byte offset of the node feature's sorted column
+  uint32_t col[SB];   // LDS address of the node feature's sorted column
   uint32_t thr[SB];   // tau
   uint32_t acc[SB];   // left counts since the last flush
 };
 
-// Left mask of node T over the staged tile (see the file comment).
-template <int D, int T>
-__device__ __forceinline__ uint64_t node_mask(const uint8_t *__restrict__ lds, uint32_t mregion,
-                                              const NodeState<D> &ns) {
-  uint32_t a = ns.col[T - 1];
-  const uint32_t th = ns.thr[T - 1];
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) {
-    uint32_t v = *reinterpret_cast<const uint32_t *>(lds + a + (s - 1) * 4);
-    a = (v < th) ? a + s * 4 : a;
-  }
-  return *reinterpret_cast<const uint64_t *>(lds + mregion + 2 * a);
+// Nodes are evaluated in heap (BFS) order, in groups of up to ILP nodes: the
+// binary searches of a group are independent and run interleaved (6 rounds of
+// ILP independent LDS reads), then the group's masks update the reach masks
+// R (R_2t = R_t & pm, R_2t+1 = R_t & ~pm) and the left counts.
+constexpr int ILP = 16;
+
+// LDS reads go through an address-space-3 pointer with base 0 and absolute
+// byte addresses (the kernel's dynamic LDS base is folded into the column
+// offsets once), so that each search step is one read, compare and select.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32_t;
+typedef __attribute__((address_space(3))) const uint64_t lds_u64_t;
+
+__device__ __forceinline__ uint32_t lds_rd32(uint32_t addr) {
+  return *reinterpret_cast<lds_u32_t *>(static_cast<uintptr_t>(addr));
+}
+__device__ __forceinline__ uint64_t lds_rd64(uint32_t addr) {
+  return *reinterpret_cast<lds_u64_t *>(static_cast<uintptr_t>(addr));
 }
 
-template <int D, int T, int LEFT>
-__device__ __forceinline__ void visit(const uint8_t *__restrict__ lds, uint32_t mregion,
-                                      NodeState<D> &ns, uint64_t R) {
-  const uint64_t m = node_mask<D, T>(lds, mregion, ns);
-  const uint64_t A = R & m;
-  ns.acc[T - 1] += (uint32_t)__popcll(A);
-  if constexpr (LEFT > 1) {
-    const uint64_t B = R & ~m;
-    visit<D, 2 * T, LEFT - 1>(lds, mregion, ns, A);
-    visit<D, 2 * T + 1, LEFT - 1>(lds, mregion, ns, B);
+template <int D, int T0, int T1>
+__device__ __forceinline__ void eval_group(uint32_t kmask, NodeState<D> &ns,
+                                           uint64_t (&R)[1 << D]) {
+  constexpr int NG = T1 - T0;
+  uint32_t a[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) a[i] = ns.col[T0 - 1 + i];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    uint32_t v[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) v[i] = lds_rd32(a[i] + (s - 1) * 4);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) a[i] += (v[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
+  }
+  uint64_t m[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) m[i] = lds_rd64(kmask + 2 * a[i]);
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    constexpr int SL = 1 << D;
+    const int t = T0 + i;
+    const uint64_t A = R[t] & m[i];
+    ns.acc[t - 1] += (uint32_t)__popcll(A);
+    if (2 * t < SL) {
+      R[2 * t + 1] = R[t] & ~m[i];
+      R[2 * t] = A;
+    }
+  }
+}
+
+template <int D, int T0>
+__device__ __forceinline__ void eval_nodes(uint32_t kmask, NodeState<D> &ns,
+                                           uint64_t (&R)[1 << D]) {
+  constexpr int SB = (1 << D) - 1;
+  if constexpr (T0 <= SB) {
+    constexpr int T1 = (T0 + ILP <= SB + 1) ? T0 + ILP : SB + 1;
+    eval_group<D, T0, T1>(kmask, ns, R);
+    eval_nodes<D, T1>(kmask, ns, R);
+  }
+}
+
+// Staging: the tile record (sorted [F][64] u32, then masks [F][64] u64) moves
+// as 16-byte chunks; chunk c < 16F is four ranks of column c / 16, the rest
+// two masks each.  Up to PF chunks per thread are prefetched into registers
+// one tile ahead so that the HBM latency hides behind the current tile.
+constexpr int PF = 4;
+
+__device__ __forceinline__ void stage_chunk(uint8_t *__restrict__ lds, uint32_t mregion,
+                                            uint32_t F, uint32_t c, const uint4 &v) {
+  if (c < 16u * F) {
+    const uint32_t f = c >> 4, j0 = (c & 15u) * 4u;
+    uint32_t *d = reinterpret_cast<uint32_t *>(lds + f * SCOL) + j0;
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
+  } else {
+    const uint32_t cc = c - 16u * F;
+    const uint32_t f = cc >> 5, e0 = (cc & 31u) * 2u;
+    uint64_t *d = reinterpret_cast<uint64_t *>(lds + mregion + f * MCOL) + e0;
+    d[0] = ((uint64_t)v.y << 32) | v.x;
+    d[1] = ((uint64_t)v.w << 32) | v.z;
   }
 }
 
@@ -75,6 +134,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
     const TileHdr *__restrict__ hdr, const uint8_t *__restrict__ feat,
     const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt) {
   constexpr int SB = (1 << D) - 1;
+  constexpr uint32_t NT = WAVES * 64;
   extern __shared__ __align__(16) uint8_t lds[];
   const uint8_t *base = reinterpret_cast<const uint8_t *>(hdr);
   const uint32_t F = hdr->F, K = hdr->K;
@@ -85,25 +145,43 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
   const uint32_t *__restrict__ info = reinterpret_cast<const uint32_t *>(base + hdr->off_info);
   const uint8_t *__restrict__ data = base + hdr->off_data;
   const size_t rec_bytes = tile_bytes(F);
-  const uint32_t r = blockIdx.y * (WAVES * 64) + threadIdx.x;
+  const uint32_t nchunk = 48u * F;
+  const uint32_t r = blockIdx.y * NT + threadIdx.x;
   const bool live = r < P;
   const uint32_t Ppad = pad64(P);
   const uint32_t mregion = mask_region(F);
+  // absolute LDS addresses: sorted column f at s0 + f * SCOL; after the
+  // search a = s0 + f * SCOL + 4c, and pm[c] of column f is at kmask + 2a
+  const uint32_t s0 = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds);
+  const uint32_t kmask = s0 + mregion - 2u * s0;
 
   NodeState<D> ns;
   uint32_t cur_sub = 0xFFFFFFFFu, cur_cls = 0xFFFFFFFFu;
 #pragma unroll
   for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
 
+  uint32_t *const cnt_rep =
+      cnt + (blockIdx.x % CNT_REP) * cnt_copy_elems(hdr->n_problems, SB, K, P);
   auto flush = [&](uint32_t sub, uint32_t cls) {
     if (!live) return;
-    uint32_t *c = cnt + ((size_t)sub * SB * K + cls) * Ppad + r;
+    uint32_t *c = cnt_rep + ((size_t)sub * SB * K + cls) * Ppad + r;
 #pragma unroll
     for (int t = 0; t < SB; ++t) {
       if (ns.acc[t]) atomicAdd(c + (size_t)t * K * Ppad, ns.acc[t]);
       ns.acc[t] = 0;
     }
   };
+
+  uint4 pf[PF];
+  auto prefetch = [&](uint32_t tile) {
+    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const uint32_t c = threadIdx.x + k * NT;
+      if (c < nchunk) pf[k] = src[c];
+    }
+  };
+  prefetch(t_begin);
 
   for (uint32_t tile = t_begin; tile < t_end; ++tile) {
     const uint32_t inf = info[tile];
@@ -117,44 +195,38 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
         for (int t = 0; t < SB; ++t) {
           uint32_t f = live ? fr[t] : 0u;
           f = f <= F ? f : 0u;  // an out-of-range feature is treated as no split
-          ns.col[t] = (f ? f - 1u : 0u) * SCOL;
+          ns.col[t] = s0 + (f ? f - 1u : 0u) * SCOL;
           ns.thr[t] = f ? tr[t] : 0u;
         }
+        // the parameters must have landed before the prefetch below is
+        // issued, or every later wait would have to drain the prefetch too
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       }
       cur_sub = sub;
       cur_cls = cls;
     }
-    // stage the tile record: sorted [F][64] u32 then masks [F][64] u64
-    __syncthreads();
-    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
-    const uint32_t nchunk = 48u * F;  // 16-byte chunks
-    for (uint32_t c = threadIdx.x; c < nchunk; c += WAVES * 64) {
-      uint4 v = src[c];
-      if (c < 16u * F) {
-        uint32_t f = c >> 4, j0 = (c & 15u) * 4u;
-        uint32_t *d = reinterpret_cast<uint32_t *>(lds + f * SCOL) + j0;
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
-      } else {
-        uint32_t cc = c - 16u * F;
-        uint32_t f = cc >> 5, e0 = (cc & 31u) * 2u;
-        uint64_t *d = reinterpret_cast<uint64_t *>(lds + mregion + f * MCOL) + e0;
-        d[0] = ((uint64_t)v.y << 32) | v.x;
-        d[1] = ((uint64_t)v.w << 32) | v.z;
-      }
+    __syncthreads();  // the previous tile is no longer read
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const uint32_t c = threadIdx.x + k * NT;
+      if (c < nchunk) stage_chunk(lds, mregion, F, c, pf[k]);
+    }
+    if (nchunk > PF * NT) {  // wide rows: the rest without prefetch
+      const uint4 *__restrict__ src =
+          reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+      for (uint32_t c = threadIdx.x + PF * NT; c < nchunk; c += NT)
+        stage_chunk(lds, mregion, F, c, src[c]);
     }
     __syncthreads();
-    const uint64_t R1 = (1ull << count) - 1ull;  // count <= 63
-    visit<D, 1, D>(lds, mregion, ns, R1);
+    if (tile + 1 < t_end) prefetch(tile + 1);
+    uint64_t R[1 << D];
+    R[1] = (1ull << count) - 1ull;  // count <= 63
+    eval_nodes<D, 1>(kmask, ns, R);
   }
   flush(cur_sub, cur_cls);
 }
 
-// Epilogue from node left counts (tile path).  One thread per (sub, tree):
-// leaf counts per class by the reach recursion, then the leaf classes,
-// correct count and cost; the consumed counters are re-zeroed.
+// Epilogue from node left counts (tile path).  One thread per (sub, tree).
 template <int D>
 __global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ ctot,
                                  const uint8_t *__restrict__ feat, uint32_t P, uint32_t K,
@@ -165,50 +237,13 @@ __global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__r
   if (gid >= n_problems * P) return;
   const uint32_t sub = gid / P, r = gid % P;
   const uint32_t Ppad = pad64(P);
-  uint32_t nl[SL], best[SL], bk[SL];
-#pragma unroll
-  for (int l = 0; l < SL; ++l) nl[l] = best[l] = bk[l] = 0;
-  uint32_t n_sub = 0;
-  for (uint32_t k = 0; k < K; ++k) {
-    uint32_t reach[2 * SL];
-    reach[1] = ctot[sub * K + k];
-    n_sub += reach[1];
-#pragma unroll
-    for (int t = 1; t <= SB; ++t) {
-      uint32_t *c = cnt + (((size_t)sub * SB + (t - 1)) * K + k) * Ppad + r;
-      uint32_t a = *c;
-      *c = 0;
-      reach[2 * t] = a;
-      reach[2 * t + 1] = reach[t] - a;
-    }
-#pragma unroll
-    for (int l = 0; l < SL; ++l) {
-      uint32_t v = reach[SL + l];
-      if (out.counts) out.counts[(((size_t)sub * P + r) * SL + l) * K + k] = v;
-      nl[l] += v;
-      if (v > best[l]) {
-        best[l] = v;
-        bk[l] = k;
-      }
-    }
-  }
-  uint32_t correct = 0, nviol = 0, nsplit = 0;
-#pragma unroll
-  for (int l = 0; l < SL; ++l) {
-    correct += best[l];
-    nviol += (nl[l] > 0 && nl[l] < n_min) ? 1u : 0u;
-    if (out.label) out.label[((size_t)sub * P + r) * SL + l] = (uint8_t)bk[l];
-  }
-  const uint8_t *fr = feat + ((size_t)sub * P + r) * SB;
-#pragma unroll
-  for (int t = 0; t < SB; ++t) nsplit += fr[t] != 0;
-  if (out.correct) out.correct[(size_t)sub * P + r] = correct;
-  if (out.cost) {
-    double v = (double)(n_sub - correct);
-    v = __dadd_rn(v, __dmul_rn(alpha, (double)nsplit));
-    v = __dadd_rn(v, (double)nviol);
-    out.cost[(size_t)sub * P + r] = v;
-  }
+  const size_t tr = (size_t)sub * P + r;
+  TreeScore sc = epilogue_node_counts<D, CNT_REP>(
+      cnt + (size_t)sub * SB * K * Ppad, ctot + (size_t)sub * K, K, Ppad, r, feat + tr * SB,
+      n_min, alpha, out.counts ? out.counts + tr * SL * K : nullptr,
+      out.label ? out.label + tr * SL : nullptr, cnt_copy_elems(n_problems, SB, K, P));
+  if (out.correct) out.correct[tr] = sc.correct;
+  if (out.cost) out.cost[tr] = sc.cost;
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +366,8 @@ hipError_t launch_bits_w(uint32_t waves, const TileHdr *hdr, uint32_t F, uint32_
                          hipStream_t st) {
   if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, st);
   if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, st);
-  return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+  if (waves == 4) return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+  return launch_bits<D, 8>(hdr, F, gx, gy, feat, tau, P, cnt, st);
 }
 
 template <int D>
@@ -345,23 +381,24 @@ void launch_epi(uint32_t *cnt, const uint32_t *ctot, const uint8_t *feat, uint32
 
 }  // namespace
 
-mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint32_t n_sub,
-                               uint32_t n_problems, uint32_t max_tiles, const uint8_t *feat,
-                               const uint32_t *tau, uint32_t P, uint32_t D, uint32_t n_min,
-                               double alpha, uint32_t *cnt, const FitnessOut &out) {
+mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                               uint32_t n_sub, uint32_t n_problems, uint32_t max_tiles,
+                               const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                               uint32_t *cnt) {
   if (D < 1 || D > 5) return fail(ctx, MH_EINVAL, "tile fitness kernel supports depth 1..5");
   const TileHdr *hdr = reinterpret_cast<const TileHdr *>(tiles);
-  const uint8_t *b = reinterpret_cast<const uint8_t *>(tiles);
-  TileHdr h = tile_layout(n_sub, F, K, n_problems);
-  const uint32_t *ctot = reinterpret_cast<const uint32_t *>(b + h.off_ctot);
   hipStream_t st = ctx->stream;
-  uint32_t Ppad = pad64(P);
-  uint32_t waves = Ppad / 64 >= 4 ? 4 : Ppad / 64;
-  uint32_t gy = (Ppad + waves * 64 - 1) / (waves * 64);
-  // enough blocks to fill the chip, but at least a few tiles per block
-  uint32_t want = (uint32_t)ctx->num_cu * 4u;
+  const uint32_t Ppad = pad64(P);
+  // one block covers up to 8 waves of 64 trees, so a tile is staged once for
+  // populations up to 512
+  uint32_t waves = Ppad / 64;
+  waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
+  const uint32_t gy = (Ppad + waves * 64 - 1) / (waves * 64);
+  // blocks: about blocks_per_cu per CU over all tree groups, each with at
+  // least min_tiles tiles
+  uint32_t want = (uint32_t)ctx->num_cu * ctx->fit_blocks_per_cu;
   want = (want + gy - 1) / gy;
-  uint32_t cap = (max_tiles + 3) / 4;
+  const uint32_t cap = (max_tiles + ctx->fit_min_tiles - 1) / ctx->fit_min_tiles;
   uint32_t gx = want < cap ? want : cap;
   if (gx == 0) gx = 1;
   if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
@@ -381,18 +418,43 @@ mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
     MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->prof_ms += ms;
     ctx->prof_launches += 1;
-    ctx->prof_evals += (uint64_t)n_sub * P * n_problems;  // upper bound for multi-problem sets
+    ctx->prof_evals += (uint64_t)n_sub * P;
     ctx->prof_tiles += max_tiles;
   }
+  (void)K;
+  (void)n_problems;
+  return MH_OK;
+}
+
+mh_status launch_fitness_epilogue(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                                  uint32_t n_sub, uint32_t n_problems, const uint8_t *feat,
+                                  uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                                  uint32_t *cnt, const FitnessOut &out) {
+  const uint8_t *b = reinterpret_cast<const uint8_t *>(tiles);
+  const TileHdr h = tile_layout(n_sub, F, K, n_problems);
+  const uint32_t *ctot = reinterpret_cast<const uint32_t *>(b + h.off_ctot);
+  hipStream_t st = ctx->stream;
   switch (D) {
     case 1: launch_epi<1>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
     case 2: launch_epi<2>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
     case 3: launch_epi<3>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
     case 4: launch_epi<4>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
     case 5: launch_epi<5>(cnt, ctot, feat, P, K, n_problems, n_min, alpha, out, st); break;
+    default: return fail(ctx, MH_EINVAL, "tile epilogue supports depth 1..5");
   }
   MH_LAUNCHED(ctx, "k_epilogue_nodes");
   return MH_OK;
+}
+
+mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint32_t n_sub,
+                               uint32_t n_problems, uint32_t max_tiles, const uint8_t *feat,
+                               const uint32_t *tau, uint32_t P, uint32_t D, uint32_t n_min,
+                               double alpha, uint32_t *cnt, const FitnessOut &out) {
+  mh_status s = launch_fitness_count(ctx, tiles, F, K, n_sub, n_problems, max_tiles, feat, tau, P,
+                                     D, cnt);
+  if (s) return s;
+  return launch_fitness_epilogue(ctx, tiles, F, K, n_sub, n_problems, feat, P, D, n_min, alpha,
+                                 cnt, out);
 }
 
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,

@@ -40,6 +40,9 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint64_t prof_launches = 0, prof_evals = 0, prof_tiles = 0;
   double prof_ms = 0.0;
+  // fitness-kernel launch shape (tunable)
+  uint32_t fit_blocks_per_cu = 2;
+  uint32_t fit_min_tiles = 1;
 };
 
 // Returns a device buffer of at least `bytes` for `name`, or nullptr (and
@@ -114,6 +117,9 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F,
 mh_status radix_sort_pairs(Ctx *ctx, uint64_t **keys, uint32_t **vals, uint64_t *keys_alt,
                            uint32_t *vals_alt, uint32_t count, uint32_t key_bits);
 
+// Exclusive or inclusive scan of n u32 values (in may equal out).
+mh_status scan_u32(Ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, bool inclusive);
+
 // tiles.hip
 // Builds the tiled layout at `base` for samples idx[0..n_sub) (all if
 // idx == nullptr); sub_of (device [n_sub], may be null) assigns each sample a
@@ -129,7 +135,15 @@ struct FitnessOut {
   uint8_t *label = nullptr;     // [sub][P][SL]
   double *cost = nullptr;       // [sub][P]
 };
-// Node-count accumulator size for a tile set: [n_problems][SB][K][Ppad].
+// Node-count accumulator for a tile set: CNT_REP copies of
+// [n_problems][SB][K][Ppad]; fitness blocks add into copy blockIdx % CNT_REP
+// so that fewer blocks contend for the same cache lines, and the epilogue sums
+// the copies.
+constexpr uint32_t CNT_REP = 4;
+__host__ __device__ inline size_t cnt_copy_elems(uint32_t n_problems, uint32_t SB, uint32_t K,
+                                                 uint32_t P) {
+  return (size_t)n_problems * SB * K * ((P + 63u) & ~63u);
+}
 size_t cnt_bytes(uint32_t n_problems, uint32_t D, uint32_t K, uint32_t P);
 __host__ __device__ inline uint32_t pad64(uint32_t P) { return (P + 63u) & ~63u; }
 // Evaluate trees feat/tau ([n_problems][P][SB]) over the tile set: accumulates
@@ -139,6 +153,16 @@ mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
                                const uint8_t *feat, const uint32_t *tau, uint32_t P,
                                uint32_t D, uint32_t n_min, double alpha, uint32_t *cnt,
                                const FitnessOut &out);
+// The two halves of launch_fitness_tiles: the counting kernel (timed when
+// profiling) and the epilogue.
+mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                               uint32_t n_sub, uint32_t n_problems, uint32_t max_tiles,
+                               const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                               uint32_t *cnt);
+mh_status launch_fitness_epilogue(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                                  uint32_t n_sub, uint32_t n_problems, const uint8_t *feat,
+                                  uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                                  uint32_t *cnt, const FitnessOut &out);
 // Direct per-sample walk for any depth (1..10): one tree at a time, leaf
 // counts per (tree, leaf, class), then the same epilogue.
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
@@ -159,11 +183,46 @@ mh_status launch_de_init(Ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t 
 mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
                         const uint32_t *n_unique, uint8_t *feat, uint32_t *tau,
                         uint32_t n_problems, const uint32_t *row_sel);
+// Fitness epilogue fused with the DE step (tile path, depth 1..5): the
+// population just evaluated (trial, or pop itself when init) gets its cost
+// from the node counts cnt, then selection, best and the next trial.
+mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base,
+                        uint32_t n_problems, uint32_t g, bool init, double *pop, double *cost,
+                        const double *trial, uint32_t *best, double *next_trial, uint8_t *feat,
+                        uint32_t *tau, uint32_t *cnt, const uint32_t *ctot, uint32_t K,
+                        uint32_t n_min, double alpha);
 // One DE step for n_problems problems (block per problem).  When feat/tau are
 // given, the new trial population is also decoded into them.
 mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
                          uint64_t prob_base, uint32_t n_problems, uint32_t g, double *pop,
                          double *cost, const double *trial, const double *trial_cost,
                          uint32_t *best, double *next_trial, uint8_t *feat, uint32_t *tau);
+
+// mh.hip
+// Exact best depth-1 split (Algorithm 2, horizon-1 branch) of every subset
+// {i : sub_of[i] == s}, s < nsub (samples with sub_of >= nsub are ignored;
+// sub_of == nullptr puts every sample in subset 0).  tot: device [nsub][K]
+// class totals of the subsets.  Writes feat/tau/correct (device, [nsub]).
+mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
+                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct);
+// DEOCT for n_problems subproblems at once (problem ids prob_ids, device),
+// samples assigned by sub_of (device [n], >= n_problems = not in any).
+// Writes the decoded best tree of each problem to feat_out/tau_out (device,
+// [n_problems][SB]) and its cost to cost_out (device [n_problems]).
+mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
+                        uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
+                        const mh_de_params *prm, uint8_t *feat_out, uint32_t *tau_out);
+
+// Sequential-form helpers: the samples at node t (device idx, atomics
+// order), the exact split of an explicit subset (host outputs), and the
+// moving-horizon driver itself.
+mh_status launch_compact(Ctx *ctx, const uint32_t *node_of, uint32_t n, uint32_t t, uint32_t *idx);
+mh_status split1_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                        uint8_t *feat, uint32_t *tau, uint32_t *correct);
+mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
+                        const mh_de_params *prm, uint32_t flags, mh_tree *out,
+                        mh_status (*solve_one)(Ctx *, const mh_dataset *, const uint32_t *,
+                                               uint32_t, uint32_t, const mh_de_params *,
+                                               uint8_t *, uint32_t *));
 
 }  // namespace mh

@@ -1,0 +1,523 @@
+// mh.hip -- the moving-horizon driver (Algorithm 2; Section 4) and the exact
+// depth-1 split it uses at the last levels.
+//
+// The tree is grown level by level.  node_of[i] is the node sample i sits at
+// (heap numbering); the subset of node t is {i : node_of[i] == t}.  Nodes of a
+// level have disjoint subsets and depend only on their ancestors, so solving
+// them one after another (Algorithm 2's order) or all at once gives the same
+// tree: the batched form runs one multi-problem DEOCT (or one batched split)
+// per level, the sequential form one per node.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mh {
+namespace {
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t n, uint32_t v) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Class histogram of the nodes of one level: hist[(t - t0) * K + y] for
+// samples with node_of in [t0, t0 + width).  Block-aggregated in LDS.
+__global__ __launch_bounds__(256) void k_level_hist(const uint32_t *__restrict__ node_of,
+                                                    const uint8_t *__restrict__ labels, uint32_t n,
+                                                    uint32_t K, uint32_t t0, uint32_t width,
+                                                    uint32_t *__restrict__ hist, int in_lds) {
+  extern __shared__ uint32_t h[];
+  const uint32_t cells = width * K;
+  if (in_lds)
+    for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) h[c] = 0;
+  __syncthreads();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint32_t t = node_of[i], y = labels[i];
+    if (t >= t0 && t - t0 < width && y < K) atomicAdd(in_lds ? &h[(t - t0) * K + y] : &hist[(t - t0) * K + y], 1u);
+  }
+  __syncthreads();
+  if (in_lds)
+    for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x)
+      if (h[c]) atomicAdd(&hist[c], h[c]);
+}
+
+// Subproblem of every sample: sub_map[t - t0] for samples at a node of the
+// level, else n_problems (not in any).
+__global__ void k_assign_sub(const uint32_t *__restrict__ node_of, uint32_t n, uint32_t t0,
+                             uint32_t width, const uint32_t *__restrict__ sub_map,
+                             uint32_t n_problems, uint32_t *__restrict__ sub_of) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = node_of[i];
+  sub_of[i] = (t >= t0 && t - t0 < width) ? sub_map[t - t0] : n_problems;
+}
+
+// Move every sample at a node of the level to its child (Section 2: left iff
+// the node splits and rank < tau; a node without a split sends all right).
+__global__ void k_route_level(uint32_t *__restrict__ node_of, uint32_t n, uint32_t t0,
+                              uint32_t width, const uint8_t *__restrict__ feat,
+                              const uint32_t *__restrict__ tau, const uint32_t *__restrict__ ranks,
+                              uint32_t ld, uint32_t F) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = node_of[i];
+  if (t < t0 || t - t0 >= width) return;
+  const uint32_t f = feat[t - 1];
+  const bool left = f != 0 && f <= F && ranks[(size_t)(f - 1) * ld + i] < tau[t - 1];
+  node_of[i] = left ? 2 * t : 2 * t + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Exact depth-1 split, batched over subsets.
+//
+// Every (sample, feature) of every subset becomes a key
+// (subset, feature, rank) with the class as payload; after a radix sort a
+// (subset, feature) segment lists the subset's ranks of that feature in order.
+// With per-class inclusive counts P_k over the sorted array, a threshold right
+// after position j (tau = rank_j + 1, taken where the rank changes) leaves
+// L_k = P_k[j] - P_k[start - 1] samples of class k on the left; its correct
+// count is max_k L_k + max_k (N_k - L_k).  The winner per subset is the first
+// strict maximum in the order (no split, then feature, then tau): the largest
+// correct count, ties to the smallest (feature, tau), and no split unless a
+// split is strictly better.
+// ---------------------------------------------------------------------------
+__global__ void k_split_keys(const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
+                             const uint32_t *__restrict__ ranks, uint32_t ld, uint32_t F,
+                             const uint8_t *__restrict__ labels, uint32_t K,
+                             uint32_t *__restrict__ cursor, uint64_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals, uint32_t fbits) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (i < n && sub_of) ? sub_of[i] : 0u;
+  const uint32_t y = i < n ? labels[i] : 0u;
+  const bool member = i < n && s < nsub && y < K;
+  const uint32_t p = block_reserve(member, cursor);
+  if (!member) return;
+  for (uint32_t f = 0; f < F; ++f) {
+    const uint64_t sid = (uint64_t)s << fbits | f;
+    keys[(size_t)p * F + f] = sid << 32 | ranks[(size_t)f * ld + i];
+    vals[(size_t)p * F + f] = y;
+  }
+}
+
+__global__ void k_split_flags(const uint32_t *__restrict__ vals, uint32_t N, uint32_t k,
+                              uint32_t *__restrict__ flags) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) flags[j] = vals[j] == k ? 1u : 0u;
+}
+
+__global__ void k_split_bounds(const uint64_t *__restrict__ keys, uint32_t N,
+                               uint32_t *__restrict__ seg_lo, uint32_t *__restrict__ seg_hi) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const uint64_t sid = keys[j] >> 32;
+  if (j == 0 || (keys[j - 1] >> 32) != sid) seg_lo[sid] = j;
+  if (j == N - 1 || (keys[j + 1] >> 32) != sid) seg_hi[sid] = j;
+}
+
+__device__ __forceinline__ uint32_t split_correct(const uint32_t *__restrict__ pk, uint32_t N,
+                                                  uint32_t K, uint32_t lo, uint32_t j,
+                                                  uint32_t hi) {
+  uint32_t ml = 0, mr = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t *p = pk + (size_t)k * N;
+    const uint32_t base = lo ? p[lo - 1] : 0u;
+    const uint32_t L = p[j] - base, T = p[hi] - base;
+    ml = L > ml ? L : ml;
+    mr = T - L > mr ? T - L : mr;
+  }
+  return ml + mr;
+}
+
+// pass 1: the best correct count per subset (atomicMax over candidates).
+// pass 2: the smallest (feature + 1, tau) among candidates attaining it.
+__global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
+                             const uint32_t *__restrict__ pk, uint32_t K,
+                             const uint32_t *__restrict__ seg_lo, const uint32_t *__restrict__ seg_hi,
+                             uint32_t fbits, uint32_t pass, uint32_t *__restrict__ best_c,
+                             unsigned long long *__restrict__ best_ft) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  bool cand = false;
+  uint32_t s = 0xFFFFFFFFu, c = 0;
+  uint64_t ft = ~0ull;
+  if (j < N) {
+    const uint64_t key = keys[j];
+    const uint64_t sid = key >> 32;
+    const uint32_t hi = seg_hi[sid];
+    s = (uint32_t)(sid >> fbits);
+    // a boundary: the rank changes between j and j + 1 inside the segment
+    if (j != hi && (keys[j + 1] & 0xFFFFFFFFull) != (key & 0xFFFFFFFFull)) {
+      const uint32_t f = (uint32_t)(sid & ((1u << fbits) - 1u));
+      c = split_correct(pk, N, K, seg_lo[sid], j, hi);
+      ft = ((uint64_t)(f + 1) << 32) | ((key & 0xFFFFFFFFull) + 1);
+      cand = pass == 0 || c == best_c[s];
+    }
+  }
+  // most waves see one subset: reduce in the wave, one atomic per wave
+  const uint32_t s0 = __shfl(s, 0, 64);
+  const bool uniform = __ballot(j < N && s != s0) == 0ull;
+  const bool any_cand = __ballot(cand) != 0ull;
+  if (uniform) {
+    uint32_t vc = cand ? c : 0u;
+    uint64_t vf = cand ? ft : ~0ull;
+    for (int d = 32; d > 0; d >>= 1) {
+      const uint32_t oc = __shfl_xor(vc, d, 64);
+      const uint64_t of = __shfl_xor(vf, d, 64);
+      vc = oc > vc ? oc : vc;
+      vf = of < vf ? of : vf;
+    }
+    if ((threadIdx.x & 63u) == 0 && s0 != 0xFFFFFFFFu && any_cand) {
+      if (pass == 0) atomicMax(&best_c[s0], vc);
+      else atomicMin(&best_ft[s0], (unsigned long long)vf);
+    }
+  } else if (cand) {
+    if (pass == 0) atomicMax(&best_c[s], c);
+    else atomicMin(&best_ft[s], (unsigned long long)ft);
+  }
+}
+
+__global__ void k_split_init(const uint32_t *__restrict__ tot, uint32_t nsub, uint32_t K,
+                             uint32_t *__restrict__ best_c, unsigned long long *__restrict__ best_ft) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsub) return;
+  uint32_t m = 0;
+  for (uint32_t k = 0; k < K; ++k) m = tot[s * K + k] > m ? tot[s * K + k] : m;
+  best_c[s] = m;            // no split
+  best_ft[s] = ~0ull;       // no split unless a split is strictly better
+}
+
+__global__ void k_split_final(const uint32_t *__restrict__ tot, uint32_t nsub, uint32_t K,
+                              const uint32_t *__restrict__ best_c,
+                              const unsigned long long *__restrict__ best_ft, uint8_t *__restrict__ feat,
+                              uint32_t *__restrict__ tau, uint32_t *__restrict__ correct) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsub) return;
+  uint32_t m = 0;
+  for (uint32_t k = 0; k < K; ++k) m = tot[s * K + k] > m ? tot[s * K + k] : m;
+  const uint64_t ft = best_ft[s];
+  if (best_c[s] > m && ft != ~0ull) {
+    feat[s] = (uint8_t)(ft >> 32);
+    tau[s] = (uint32_t)ft;
+  } else {
+    feat[s] = 0;
+    tau[s] = 0;
+  }
+  correct[s] = best_c[s];
+}
+
+// Scatter the root node of each problem's best tree into the full tree.
+__global__ void k_put_roots(const uint8_t *__restrict__ f1, const uint32_t *__restrict__ t1,
+                            uint32_t SB1, const uint32_t *__restrict__ nodes, uint32_t cnt,
+                            uint8_t *__restrict__ feat, uint32_t *__restrict__ tau) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt) return;
+  feat[nodes[s] - 1] = f1[(size_t)s * SB1];
+  tau[nodes[s] - 1] = t1[(size_t)s * SB1];
+}
+
+inline uint32_t nblk(uint32_t n, uint32_t b = 256) { return (n + b - 1) / b; }
+
+// Samples at node t, in whatever order the atomics give (the counts of a
+// subset do not depend on the order of its samples).
+__global__ void k_compact(const uint32_t *__restrict__ node_of, uint32_t n, uint32_t t,
+                          uint32_t *__restrict__ cursor, uint32_t *__restrict__ idx) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n && node_of[i] == t;
+  const uint32_t p = block_reserve(in, cursor);
+  if (in) idx[p] = i;
+}
+
+// sub_of for an explicit subset: 0 for idx members, 1 for the rest; and the
+// subset's class totals.
+__global__ void k_mark_subset(const uint32_t *__restrict__ idx, uint32_t n_sub, uint32_t n,
+                              const uint8_t *__restrict__ labels, uint32_t K,
+                              uint32_t *__restrict__ sub_of, uint32_t *__restrict__ tot) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_sub) return;
+  const uint32_t i = idx ? idx[j] : j;
+  if (i >= n || labels[i] >= K) return;
+  if (atomicExch(&sub_of[i], 0u) == 0u) return;  // a repeated index counts once
+  atomicAdd(&tot[labels[i]], 1u);
+}
+
+}  // namespace
+
+mh_status launch_compact(Ctx *ctx, const uint32_t *node_of, uint32_t n, uint32_t t, uint32_t *idx) {
+  uint32_t *cursor = (uint32_t *)arena_get(ctx, "mh_cursor", 256);
+  if (!cursor) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(cursor, 0, 4, ctx->stream));
+  if (n) {
+    k_compact<<<nblk(n), 256, 0, ctx->stream>>>(node_of, n, t, cursor, idx);
+    MH_LAUNCHED(ctx, "k_compact");
+  }
+  return MH_OK;
+}
+
+mh_status split1_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                        uint8_t *feat, uint32_t *tau, uint32_t *correct) {
+  hipStream_t st = ctx->stream;
+  const uint32_t n = ds->n;
+  uint32_t *sub_of = (uint32_t *)arena_get(ctx, "s1_sub_of", (size_t)(n ? n : 1) * 4);
+  uint32_t *tot = (uint32_t *)arena_get(ctx, "s1_tot", (size_t)ds->K * 4);
+  uint8_t *f = (uint8_t *)arena_get(ctx, "s1_f", 256);
+  uint32_t *t = (uint32_t *)arena_get(ctx, "s1_t", 256);
+  uint32_t *c = (uint32_t *)arena_get(ctx, "s1_c", 256);
+  if (!sub_of || !tot || !f || !t || !c) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(tot, 0, (size_t)ds->K * 4, st));
+  if (n) {
+    k_fill_u32<<<nblk(n), 256, 0, st>>>(sub_of, n, 1u);
+    MH_LAUNCHED(ctx, "k_fill_u32");
+  }
+  if (n_sub) {
+    k_mark_subset<<<nblk(n_sub), 256, 0, st>>>(idx, n_sub, n, ds->labels, ds->K, sub_of, tot);
+    MH_LAUNCHED(ctx, "k_mark_subset");
+  }
+  mh_status s = launch_split1(ctx, ds, sub_of, 1, tot, f, t, c);
+  if (s) return s;
+  MH_HIP(ctx, hipMemcpyAsync(feat, f, 1, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(tau, t, 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(correct, c, 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipStreamSynchronize(st));
+  return MH_OK;
+}
+
+mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
+                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct) {
+  hipStream_t st = ctx->stream;
+  const uint32_t n = ds->n, F = ds->F, K = ds->K;
+  uint32_t fbits = 1;
+  while ((1u << fbits) < F) ++fbits;
+  uint32_t sbits = 0;
+  while ((1u << sbits) < nsub) ++sbits;
+  if (fbits + sbits > 31) return fail(ctx, MH_EINVAL, "too many subsets for split1");
+  uint32_t *cursor = (uint32_t *)arena_get(ctx, "sp_cursor", 256);
+  uint32_t *best_c = (uint32_t *)arena_get(ctx, "sp_best_c", (size_t)nsub * 4);
+  unsigned long long *best_ft =
+      (unsigned long long *)arena_get(ctx, "sp_best_ft", (size_t)nsub * 8);
+  if (!cursor || !best_c || !best_ft) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(cursor, 0, 4, st));
+  k_split_init<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, best_c, best_ft);
+  MH_LAUNCHED(ctx, "k_split_init");
+  // elements: (member sample, feature) pairs; members counted on the host
+  uint32_t members = 0;
+  {
+    std::vector<uint32_t> h((size_t)nsub * K);
+    MH_HIP(ctx, hipMemcpyAsync(h.data(), tot, h.size() * 4, hipMemcpyDeviceToHost, st));
+    MH_HIP(ctx, hipStreamSynchronize(st));
+    for (uint32_t v : h) members += v;
+  }
+  const uint64_t N64 = (uint64_t)members * F;
+  if (N64 >= 0xFFFFFFFFull) return fail(ctx, MH_EINVAL, "split1: too many elements");
+  const uint32_t N = (uint32_t)N64;
+  if (N > 0) {
+    uint64_t *ka = (uint64_t *)arena_get(ctx, "sp_keys_a", (size_t)N * 8);
+    uint64_t *kb = (uint64_t *)arena_get(ctx, "sp_keys_b", (size_t)N * 8);
+    uint32_t *va = (uint32_t *)arena_get(ctx, "sp_vals_a", (size_t)N * 4);
+    uint32_t *vb = (uint32_t *)arena_get(ctx, "sp_vals_b", (size_t)N * 4);
+    uint32_t *pk = (uint32_t *)arena_get(ctx, "sp_prefix", (size_t)N * K * 4);
+    const size_t nseg = (size_t)nsub << fbits;
+    uint32_t *seg_lo = (uint32_t *)arena_get(ctx, "sp_seg_lo", nseg * 4);
+    uint32_t *seg_hi = (uint32_t *)arena_get(ctx, "sp_seg_hi", nseg * 4);
+    if (!ka || !kb || !va || !vb || !pk || !seg_lo || !seg_hi) return MH_ENOMEM;
+    k_split_keys<<<nblk(n), 256, 0, st>>>(sub_of, n, nsub, ds->ranks, ds->ld, F, ds->labels, K,
+                                           cursor, ka, va, fbits);
+    MH_LAUNCHED(ctx, "k_split_keys");
+    uint64_t *keys = ka;
+    uint32_t *vals = va;
+    const uint32_t key_bits = ((32 + fbits + sbits + 7) / 8) * 8;
+    mh_status s = radix_sort_pairs(ctx, &keys, &vals, keys == ka ? kb : ka, vals == va ? vb : va,
+                                   N, key_bits);
+    if (s) return s;
+    for (uint32_t k = 0; k < K; ++k) {
+      uint32_t *p = pk + (size_t)k * N;
+      k_split_flags<<<nblk(N), 256, 0, st>>>(vals, N, k, p);
+      MH_LAUNCHED(ctx, "k_split_flags");
+      s = scan_u32(ctx, p, p, N, true);
+      if (s) return s;
+    }
+    k_split_bounds<<<nblk(N), 256, 0, st>>>(keys, N, seg_lo, seg_hi);
+    MH_LAUNCHED(ctx, "k_split_bounds");
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+      k_split_eval<<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass, best_c,
+                                            best_ft);
+      MH_LAUNCHED(ctx, "k_split_eval");
+    }
+  }
+  k_split_final<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, best_c, best_ft, feat, tau, correct);
+  MH_LAUNCHED(ctx, "k_split_final");
+  return MH_OK;
+}
+
+// Multi-problem DEOCT: one tile set over all problems, one fitness launch and
+// one fused epilogue + DE step (a block per problem) per generation.
+mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
+                        uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
+                        const mh_de_params *prm, uint8_t *feat_out, uint32_t *tau_out) {
+  const uint32_t P = prm->P, SB = (1u << D) - 1u, m = 2 * SB, K = ds->K, F = ds->F;
+  if (D > 5 || F > 80) return fail(ctx, MH_EINVAL, "batched DEOCT needs depth <= 5 and F <= 80");
+  hipStream_t st = ctx->stream;
+  TileHdr h = tile_layout(ds->n, F, K, n_problems);
+  void *tiles = arena_get(ctx, "mb_tiles", h.total_bytes);
+  const size_t cb = cnt_bytes(n_problems, D, K, P);
+  uint32_t *cnt = (uint32_t *)arena_get(ctx, "mb_cnt", cb);
+  double *pop = (double *)arena_get(ctx, "mb_pop", (size_t)n_problems * P * m * 8);
+  double *trial = (double *)arena_get(ctx, "mb_trial", (size_t)n_problems * P * m * 8);
+  double *cost = (double *)arena_get(ctx, "mb_cost", (size_t)n_problems * P * 8);
+  uint8_t *feat = (uint8_t *)arena_get(ctx, "mb_feat", (size_t)n_problems * P * SB);
+  uint32_t *tau = (uint32_t *)arena_get(ctx, "mb_tau", (size_t)n_problems * P * SB * 4);
+  uint32_t *best = (uint32_t *)arena_get(ctx, "mb_best", (size_t)n_problems * 4);
+  if (!tiles || !cnt || !pop || !trial || !cost || !feat || !tau || !best) return MH_ENOMEM;
+  mh_status s = launch_tile_build(ctx, ds, nullptr, sub_of, ds->n, n_problems, tiles, h.total_bytes);
+  if (s) return s;
+  MH_HIP(ctx, hipMemsetAsync(cnt, 0, cb, st));
+  const uint32_t *ctot =
+      reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tiles) + h.off_ctot);
+  DeDev de{P, D, F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique};
+  s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop);
+  if (s) return s;
+  s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat, tau, n_problems, nullptr);
+  if (s) return s;
+  for (uint32_t g = 0; g <= prm->G; ++g) {
+    s = launch_fitness_count(ctx, tiles, F, K, ds->n, n_problems, h.max_tiles, feat, tau, P, D, cnt);
+    if (s) return s;
+    s = launch_de_gen(ctx, de, prob_ids, 0, n_problems, g + 1, g == 0, pop, cost, trial, best,
+                      g < prm->G ? trial : nullptr, feat, tau, cnt, ctot, K, prm->n_min,
+                      prm->alpha);
+    if (s) return s;
+  }
+  return launch_decode(ctx, pop, P, D, F, ds->n_unique, feat_out, tau_out, n_problems, best);
+}
+
+// Algorithm 2.  flags: MH_SEQUENTIAL or MH_BATCHED.
+// solve_one(ctx, ds, node_of, t, depth, prm, &feat, &tau): the root of the
+// DEOCT subtree of node t (sequential form).
+mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
+                        const mh_de_params *prm, uint32_t flags, mh_tree *out,
+                        mh_status (*solve_one)(Ctx *, const mh_dataset *, const uint32_t *,
+                                               uint32_t, uint32_t, const mh_de_params *,
+                                               uint8_t *, uint32_t *)) {
+  hipStream_t st = ctx->stream;
+  const uint32_t n = ds->n, K = ds->K, SB = (1u << D) - 1u, SL = 1u << D;
+  const bool batched = (flags & MH_BATCHED) != 0;
+  uint32_t *node_of = (uint32_t *)arena_get(ctx, "mh_node_of", (size_t)(n ? n : 1) * 4);
+  uint32_t *sub_of = (uint32_t *)arena_get(ctx, "mh_sub_of", (size_t)(n ? n : 1) * 4);
+  uint8_t *tfeat = (uint8_t *)arena_get(ctx, "mh_feat", SB);
+  uint32_t *ttau = (uint32_t *)arena_get(ctx, "mh_tau", (size_t)SB * 4);
+  const uint32_t maxw = 1u << (D - 1);
+  uint32_t *hist = (uint32_t *)arena_get(ctx, "mh_hist", (size_t)maxw * K * 4);
+  uint32_t *smap = (uint32_t *)arena_get(ctx, "mh_smap", (size_t)maxw * 4);
+  uint64_t *pids = (uint64_t *)arena_get(ctx, "mh_pids", (size_t)maxw * 8);
+  uint32_t *nodes_d = (uint32_t *)arena_get(ctx, "mh_nodes", (size_t)maxw * 4);
+  uint8_t *rf = (uint8_t *)arena_get(ctx, "mh_rf", (size_t)maxw * 31);
+  uint32_t *rt = (uint32_t *)arena_get(ctx, "mh_rt", (size_t)maxw * 31 * 4);
+  uint32_t *scorr = (uint32_t *)arena_get(ctx, "mh_scorr", (size_t)maxw * 4);
+  uint32_t *idx = (uint32_t *)arena_get(ctx, "mh_idx", (size_t)(n ? n : 1) * 4);
+  if (!node_of || !sub_of || !tfeat || !ttau || !hist || !smap || !pids || !nodes_d || !rf || !rt ||
+      !scorr || !idx)
+    return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(tfeat, 0, SB, st));
+  MH_HIP(ctx, hipMemsetAsync(ttau, 0, (size_t)SB * 4, st));
+  if (n) {
+    k_fill_u32<<<nblk(n), 256, 0, st>>>(node_of, n, 1u);
+    MH_LAUNCHED(ctx, "k_fill_u32");
+  }
+  std::vector<uint32_t> hh((size_t)maxw * K);
+  for (uint32_t L = 0; L < D; ++L) {
+    const uint32_t t0 = 1u << L, width = 1u << L;
+    // class histogram of the level's nodes
+    MH_HIP(ctx, hipMemsetAsync(hist, 0, (size_t)width * K * 4, st));
+    if (n) {
+      const bool in_lds = (size_t)width * K * 4 <= 32768;
+      k_level_hist<<<nblk(n), 256, in_lds ? (size_t)width * K * 4 : 0, st>>>(
+          node_of, ds->labels, n, K, t0, width, hist, in_lds ? 1 : 0);
+      MH_LAUNCHED(ctx, "k_level_hist");
+    }
+    MH_HIP(ctx, hipMemcpyAsync(hh.data(), hist, (size_t)width * K * 4, hipMemcpyDeviceToHost, st));
+    MH_HIP(ctx, hipStreamSynchronize(st));
+    // which nodes are solved (more than n_min samples of more than one class)
+    std::vector<uint32_t> active, map(width, 0xFFFFFFFFu);
+    for (uint32_t w = 0; w < width; ++w) {
+      uint32_t size = 0, classes = 0;
+      for (uint32_t k = 0; k < K; ++k) {
+        size += hh[(size_t)w * K + k];
+        classes += hh[(size_t)w * K + k] ? 1u : 0u;
+      }
+      if (size > prm->n_min && classes > 1) {
+        map[w] = (uint32_t)active.size();
+        active.push_back(t0 + w);
+      }
+    }
+    const uint32_t De = std::min(D_MH, D - L);
+    const uint32_t na = (uint32_t)active.size();
+    if (na > 0) {
+      for (uint32_t w = 0; w < width; ++w)
+        if (map[w] == 0xFFFFFFFFu) map[w] = na;
+      MH_HIP(ctx, hipMemcpyAsync(smap, map.data(), (size_t)width * 4, hipMemcpyHostToDevice, st));
+      MH_HIP(ctx, hipMemcpyAsync(nodes_d, active.data(), (size_t)na * 4, hipMemcpyHostToDevice, st));
+      std::vector<uint64_t> pid(active.begin(), active.end());
+      MH_HIP(ctx, hipMemcpyAsync(pids, pid.data(), (size_t)na * 8, hipMemcpyHostToDevice, st));
+      MH_HIP(ctx, hipStreamSynchronize(st));  // map / pid host buffers are reused below
+      // roots land in rf/rt with stride SB1 (batched trees) or 1 (one root)
+      uint32_t SB1 = (De == 1 || !batched) ? 1u : (1u << De) - 1u;
+      if (batched || De == 1) {
+        k_assign_sub<<<nblk(n), 256, 0, st>>>(node_of, n, t0, width, smap, na, sub_of);
+        MH_LAUNCHED(ctx, "k_assign_sub");
+      }
+      if (De == 1) {
+        // exact split of every active node (one batched launch; the result of
+        // a node does not depend on the others)
+        std::vector<uint32_t> tot((size_t)na * K);
+        for (uint32_t a = 0; a < na; ++a)
+          for (uint32_t k = 0; k < K; ++k) tot[(size_t)a * K + k] = hh[(size_t)(active[a] - t0) * K + k];
+        MH_HIP(ctx, hipMemcpyAsync(hist, tot.data(), tot.size() * 4, hipMemcpyHostToDevice, st));
+        MH_HIP(ctx, hipStreamSynchronize(st));
+        mh_status s = launch_split1(ctx, ds, sub_of, na, hist, rf, rt, scorr);
+        if (s) return s;
+      } else if (batched) {
+        mh_status s = deoct_batched(ctx, ds, sub_of, na, pids, De, prm, rf, rt);
+        if (s) return s;
+      } else {
+        std::vector<uint8_t> hf(na);
+        std::vector<uint32_t> ht(na);
+        for (uint32_t a = 0; a < na; ++a) {
+          mh_status s = solve_one(ctx, ds, node_of, active[a], De, prm, &hf[a], &ht[a]);
+          if (s) return s;
+        }
+        MH_HIP(ctx, hipMemcpyAsync(rf, hf.data(), na, hipMemcpyHostToDevice, st));
+        MH_HIP(ctx, hipMemcpyAsync(rt, ht.data(), (size_t)na * 4, hipMemcpyHostToDevice, st));
+        MH_HIP(ctx, hipStreamSynchronize(st));  // host vectors go out of scope
+      }
+      k_put_roots<<<nblk(na), 256, 0, st>>>(rf, rt, SB1, nodes_d, na, tfeat, ttau);
+      MH_LAUNCHED(ctx, "k_put_roots");
+    }
+    if (L + 1 < D && n) {
+      k_route_level<<<nblk(n), 256, 0, st>>>(node_of, n, t0, width, tfeat, ttau, ds->ranks, ds->ld,
+                                             ds->F);
+      MH_LAUNCHED(ctx, "k_route_level");
+    }
+  }
+  // leaf classes and objective of the final tree over all training samples
+  uint8_t *lab = (uint8_t *)arena_get(ctx, "mh_lab", SL);
+  uint32_t *corr = (uint32_t *)arena_get(ctx, "mh_corr", 256);
+  double *cst = (double *)arena_get(ctx, "mh_cost", 256);
+  if (!lab || !corr || !cst) return MH_ENOMEM;
+  FitnessOut fo;
+  fo.label = lab;
+  fo.correct = corr;
+  fo.cost = cst;
+  mh_status s = launch_fitness_walk(ctx, ds, nullptr, n, tfeat, ttau, 1, D, prm->n_min, prm->alpha, fo);
+  if (s) return s;
+  std::memset(out, 0, sizeof(*out));
+  out->D = D;
+  MH_HIP(ctx, hipMemcpyAsync(out->feat, tfeat, SB, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(out->tau, ttau, (size_t)SB * 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(out->label, lab, SL, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(&out->correct, corr, 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(&out->cost, cst, 8, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipStreamSynchronize(st));
+  return MH_OK;
+}
+
+}  // namespace mh

@@ -203,6 +203,8 @@ __global__ void k_rank_write(const uint32_t *__restrict__ vals, const uint32_t *
   if (j == f * n + n - 1) n_unique[f] = U[j] - first + 1u;
 }
 
+}  // namespace
+
 mh_status scan_u32(Ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, bool inclusive) {
   uint32_t nb = (n + RS_CHUNK - 1) / RS_CHUNK;
   uint32_t *sums = (uint32_t *)arena_get(ctx, "scan_sums", (size_t)(nb ? nb : 1) * 4);
@@ -216,8 +218,6 @@ mh_status scan_u32(Ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, bool
   MH_LAUNCHED(ctx, "k_scan_apply");
   return MH_OK;
 }
-
-}  // namespace
 
 mh_status radix_sort_pairs(Ctx *ctx, uint64_t **keys, uint32_t **vals, uint64_t *keys_alt,
                            uint32_t *vals_alt, uint32_t count, uint32_t key_bits) {

@@ -61,13 +61,30 @@ __device__ __forceinline__ bool sample_ok(const uint8_t *__restrict__ labels,
   return true;
 }
 
-__global__ void k_tile_count(const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
-                             const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n,
-                             uint32_t K, uint32_t n_problems, uint32_t *__restrict__ ctot) {
-  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_sub) return;
+// Block-aggregated segment counts: LDS histogram when the segments fit,
+// then one global atomic per (block, segment).
+constexpr uint32_t LDS_SEGS = 2048;
+
+__global__ __launch_bounds__(256) void k_tile_count(
+    const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
+    const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n, uint32_t K,
+    uint32_t n_problems, uint32_t *__restrict__ ctot) {
+  __shared__ uint32_t h[LDS_SEGS];
+  const uint32_t nseg = n_problems * K;
+  const bool local = nseg <= LDS_SEGS;
+  if (local)
+    for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
+  __syncthreads();
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t i, seg;
-  if (sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) atomicAdd(&ctot[seg], 1u);
+  if (j < n_sub && sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) {
+    if (local) atomicAdd(&h[seg], 1u);
+    else atomicAdd(&ctot[seg], 1u);
+  }
+  __syncthreads();
+  if (local)
+    for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x)
+      if (h[s]) atomicAdd(&ctot[s], h[s]);
 }
 
 // Segment plan: tiles per (subproblem, class) segment, their first tile, and
@@ -120,21 +137,36 @@ __global__ void k_tile_plan(TileHdr *__restrict__ hdr, uint32_t nseg) {
   }
 }
 
-// Scatter sample ids into their tile slots.  The order inside a segment is
-// whatever the atomics give; counts do not depend on it.
-__global__ void k_tile_scatter(const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
-                               const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n,
-                               TileHdr *__restrict__ hdr) {
-  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_sub) return;
-  uint32_t i, s;
-  if (!sample_ok(labels, idx, sub_of, j, n, hdr->K, hdr->n_problems, i, s)) return;
+// Scatter sample ids into their tile slots.  Each block reserves one range
+// per segment with a single global atomic and fills it from LDS positions.
+// The order inside a segment is whatever the atomics give; counts do not
+// depend on it.
+__global__ __launch_bounds__(256) void k_tile_scatter(
+    const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
+    const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n, TileHdr *__restrict__ hdr) {
+  __shared__ uint32_t h[LDS_SEGS];
   uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
   const uint32_t *segoff = reinterpret_cast<const uint32_t *>(base + hdr->off_segoff);
   uint32_t *cursor = reinterpret_cast<uint32_t *>(base + hdr->off_cursor);
   uint32_t *order = reinterpret_cast<uint32_t *>(base + hdr->off_order);
-  uint32_t pos = atomicAdd(&cursor[s], 1u);
-  uint32_t tile = segoff[s] + pos / TILE_CAP;
+  const uint32_t K = hdr->K, n_problems = hdr->n_problems, nseg = n_problems * K;
+  const bool local = nseg <= LDS_SEGS;
+  if (local)
+    for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
+  __syncthreads();
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t i = 0, s = 0, pos = 0;
+  const bool ok = j < n_sub && sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, s);
+  if (ok) pos = local ? atomicAdd(&h[s], 1u) : atomicAdd(&cursor[s], 1u);
+  if (local) {
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < nseg; q += blockDim.x)
+      if (h[q]) h[q] = atomicAdd(&cursor[q], h[q]);
+    __syncthreads();
+    if (ok) pos += h[s];
+  }
+  if (!ok) return;
+  const uint32_t tile = segoff[s] + pos / TILE_CAP;
   order[tile * TILE_W + pos % TILE_CAP] = i;
 }
 

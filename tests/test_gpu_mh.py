@@ -1,0 +1,80 @@
+"""GPU parity of the exact depth-1 split and the moving-horizon trainer
+(Algorithm 2) against the oracle; the level-batched form must return the same
+tree as the node-by-node form.  Bar: bit-exact (integer trees and counts,
+exactly rounded f64 costs)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev
+from paper_2311_06952_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mh():
+    import paper_2311_06952_amd as m
+    return m
+
+
+@pytest.mark.parametrize("seed,n,F,K,levels", [(1, 1, 2, 2, None), (2, 40, 3, 2, None),
+                                               (3, 500, 4, 3, 7), (4, 5000, 6, 5, None),
+                                               (5, 3000, 3, 2, 2), (6, 200, 9, 4, 30)])
+def test_split1_all(mh, seed, n, F, K, levels):
+    X, y = synth.random_small(seed, n, F, K, levels)
+    want = oracle.split1(oracle.dataset_from_X(X, y, K))
+    assert mh.split1(mh.dataset(X, y, K)) == want
+
+
+def test_split1_subsets_and_pure(mh):
+    X, y = synth.random_small(7, 4000, 5, 3, 25)
+    ods = oracle.dataset_from_X(X, y, 3)
+    ds = mh.dataset(X, y, 3)
+    rng = np.random.default_rng(0)
+    for size in (1, 2, 17, 999, 3999):
+        idx = rng.choice(4000, size=size, replace=False).astype(np.uint32)
+        assert mh.split1(ds, idx=dev(idx)) == oracle.split1(ods, idx=idx)
+    pure = np.nonzero(y == 1)[0].astype(np.uint32)
+    assert mh.split1(ds, idx=dev(pure)) == oracle.split1(ods, idx=pure) == (0, 0, len(pure))
+
+
+def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9):
+    ods = oracle.dataset_from_X(X, y, K)
+    want = oracle.mh_train(ods, D, D_MH, oracle.de_params(P, G, M, CR, seed))
+    ds = mh.dataset(X, y, K)
+    prm = mh.de_params(P, G, M, CR, seed)
+    seq = mh.mh_train(ds, D, D_MH, prm, batched=False)
+    bat = mh.mh_train(ds, D, D_MH, prm, batched=True)
+    return want, seq, bat
+
+
+def _same(a, b):
+    np.testing.assert_array_equal(a["feat"], b["feat"])
+    np.testing.assert_array_equal(a["tau"], b["tau"])
+    np.testing.assert_array_equal(a["label"], b["label"])
+    assert a["correct"] == b["correct"] and a["cost"] == b["cost"]
+
+
+@pytest.mark.parametrize("seed,n,F,K,D,D_MH,P,G", [
+    (1, 2000, 5, 3, 3, 2, 16, 8),
+    (2, 3000, 4, 2, 4, 3, 12, 6),
+    (3, 1500, 6, 4, 2, 2, 10, 5),
+    (4, 2500, 5, 3, 5, 1, 8, 3),     # horizon 1: exact splits only
+    (5, 800, 3, 2, 6, 3, 8, 4),
+])
+def test_mh_train_matches_oracle(mh, seed, n, F, K, D, D_MH, P, G):
+    X, y = synth.random_small(seed, n, F, K, levels=40)
+    want, seq, bat = _mh_both(mh, X, y, K, D, D_MH, P, G, 100 + seed)
+    _same(seq, want)
+    _same(bat, want)
+
+
+def test_mh_train_gaussian_mixture_depth8(mh):
+    """Shape of the batched moving-horizon workload (Gaussian mixture, F = 20,
+    K = 3, depth 8, horizon 3) at n = 20,000 with P = 16, G = 5 so that the
+    oracle runs in seconds."""
+    w = synth.batched_mh(1, n=20_000)
+    want, seq, bat = _mh_both(mh, w.X, w.y, w.K, 8, 3, 16, 5, 1001)
+    _same(seq, want)
+    _same(bat, want)
