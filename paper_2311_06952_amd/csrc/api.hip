@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 
+#include "de_body.h"
 #include "device_common.h"
 #include "internal.h"
 
@@ -158,11 +159,11 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   if (!pop || !trial || !cost || !tcost || !feat || !tau || !best || !f1 || !t1 || !lab1 ||
       !corr1 || !cost1)
     return MH_ENOMEM;
-  DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique};
+  DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
   // g = 0: initialise, decode, evaluate
-  s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop);
+  s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop, true);
   if (s) return s;
-  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr);
+  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr, true);
   if (s) return s;
   if (es.tiles) {
     // tile path: per generation the counting kernel, then the epilogue fused
@@ -170,9 +171,27 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
     const TileHdr h = tile_layout(n_sub, ds->F, K, 1);
     const uint32_t *ctot =
         reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(es.tiles) + h.off_ctot);
+    // (a problem without samples has no block to finish it: separate step)
+    const bool fuse = ctx->fuse_de && fusable(P, D, ds->F) && n_sub > 0;
+    uint32_t *done = (uint32_t *)arena_get(ctx, "ss_done", 256);
+    if (!done) return MH_ENOMEM;
+    MH_HIP(ctx, hipMemsetAsync(done, 0, 4, st));
+    const uint32_t *segoff =
+        reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(es.tiles) + h.off_segoff);
     for (uint32_t g = 0; g <= prm->G; ++g) {
+      if (fuse) {
+        // one launch per generation: counting, then the DE step in the block
+        // that finishes last
+        FuseArgs fa = make_fuse(de, nullptr, prob, 1, g + 1, g == 0, pop, cost, trial, best,
+                                g < prm->G ? trial : nullptr, feat, tau, es.cnt, ctot, K,
+                                prm->n_min, prm->alpha, done, segoff);
+        s = launch_fitness_count(ctx, es.tiles, ds->F, K, n_sub, 1, es.max_tiles, feat, tau, P, D,
+                                 es.cnt, &fa);
+        if (s) return s;
+        continue;
+      }
       s = launch_fitness_count(ctx, es.tiles, ds->F, K, n_sub, 1, es.max_tiles, feat, tau, P, D,
-                               es.cnt);
+                               es.cnt, nullptr);
       if (s) return s;
       s = launch_de_gen(ctx, de, nullptr, prob, 1, g + 1, g == 0, pop, cost, trial, best,
                         g < prm->G ? trial : nullptr, feat, tau, es.cnt, ctot, K, prm->n_min,
@@ -199,7 +218,7 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
     }
   }
   // the best individual: decode and evaluate for its labels
-  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best);
+  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best, true);
   if (s) return s;
   FitnessOut fb;
   fb.label = lab1;
@@ -274,6 +293,7 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   // launch-shape overrides for tuning sweeps
   if (const char *v = std::getenv("MHDEOCT_FIT_BLOCKS_PER_CU")) c->c.fit_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FIT_MIN_TILES")) c->c.fit_min_tiles = (uint32_t)std::max(1, atoi(v));
+  if (const char *v = std::getenv("MHDEOCT_FUSE_DE")) c->c.fuse_de = atoi(v) != 0;
   if (hipEventCreate(&c->c.ev0) != hipSuccess || hipEventCreate(&c->c.ev1) != hipSuccess) {
     delete c;
     return fail(nullptr, MH_EDEVICE, "hipEventCreate failed");
@@ -334,7 +354,7 @@ mh_status tree_decode(mh_ctx *ctx, const double *genes, uint32_t P, uint32_t D, 
   if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
   if (F == 0 || F > MH_MAX_FEATURES) return fail(c, MH_EINVAL, "F must be in 1..255");
   if (P > 0 && (!genes || !n_unique || !feat || !tau)) return fail(c, MH_EINVAL, "null pointer");
-  return launch_decode(c, genes, P, D, F, n_unique, feat, tau, 1, nullptr);
+  return launch_decode(c, genes, P, D, F, n_unique, feat, tau, 1, nullptr, false);
 }
 
 mh_status mh_tileset_bytes(uint32_t n_sub, uint32_t F, uint32_t K, size_t *bytes) {
@@ -422,7 +442,7 @@ mh_status de_init(mh_ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed
   if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
   if (P > MH_MAX_POP || W > P) return fail(c, MH_EINVAL, "bad P or W");
   if (!pop || (W > 0 && !warm)) return fail(c, MH_EINVAL, "null pointer");
-  return launch_de_init(c, P, D, F, seed, nullptr, problem_id, 1, warm, W, pop);
+  return launch_de_init(c, P, D, F, seed, nullptr, problem_id, 1, warm, W, pop, false);
 }
 
 mh_status de_step(mh_ctx *ctx, const mh_de_params *prm, uint32_t D, uint32_t F,
@@ -436,7 +456,7 @@ mh_status de_step(mh_ctx *ctx, const mh_de_params *prm, uint32_t D, uint32_t F,
   if (!pop || !cost || !best) return fail(c, MH_EINVAL, "null pop, cost or best");
   if (trial && !trial_cost) return fail(c, MH_EINVAL, "trial without trial_cost");
   if (g >= (1u << 24)) return fail(c, MH_EINVAL, "g must be < 2^24");
-  DeDev de{prm->P, D, F, prm->G, prm->M, prm->CR, prm->seed, nullptr};
+  DeDev de{prm->P, D, F, prm->G, prm->M, prm->CR, prm->seed, nullptr, false};
   return launch_de_step(c, de, nullptr, problem_id, 1, g, pop, cost, trial, trial_cost, best,
                         next_trial, nullptr, nullptr);
 }

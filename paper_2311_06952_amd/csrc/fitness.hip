@@ -14,6 +14,7 @@
 //
 // Walk kernel (any depth 1..10): lane = sample, the Algorithm 1 walk of one
 // tree at a time with an LDS histogram per (leaf, class).
+#include "de_body.h"
 #include "device_common.h"
 #include "epilogue.h"
 #include "internal.h"
@@ -129,10 +130,68 @@ __device__ __forceinline__ void stage_chunk(uint8_t *__restrict__ lds, uint32_t 
   }
 }
 
+// After its last flush, a block of the fused kernel takes a ticket on every
+// problem its tiles touched; the block that completes a problem's count (all
+// blocks covering its tiles have flushed) runs that problem's epilogue and
+// DE step at once, with its threads as the individuals and the tile buffer as
+// scratch.  The counts are the only data that cross blocks inside a launch
+// and are device-coherent atomics: every wave waits for its atomics to
+// complete before the ticket is taken, and the finishing block reads the
+// counts with agent-scope loads (no L2 write-back or invalidate needed).
 template <int D, int WAVES>
+__device__ __forceinline__ void fused_tail(const FuseArgs &fa, const uint32_t *__restrict__ info,
+                                           uint32_t n_tiles, uint32_t t_begin, uint32_t t_end,
+                                           uint32_t K, uint8_t *lds) {
+  constexpr int SB = (1 << D) - 1;
+  constexpr uint32_t NT = WAVES * 64;
+  __shared__ uint32_t s_last;
+  const uint32_t P = fa.a.P, Ppad = pad64(P), nb = gridDim.x;
+  __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's atomics are done
+  __syncthreads();
+  const uint32_t s_lo = info[t_begin] >> 16, s_hi = info[t_end - 1] >> 16;
+  // scratch carved from the (now free) dynamic LDS
+  double *s_cost = reinterpret_cast<double *>(lds);
+  uint32_t *s_idx = reinterpret_cast<uint32_t *>(lds + NT * 8);
+  uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + NT * 12);
+  double *rows = fa.rows_in_lds ? reinterpret_cast<double *>(lds + NT * 12 + 1024) : nullptr;
+  for (uint32_t s = s_lo; s <= s_hi; ++s) {
+    if (threadIdx.x == 0) {
+      const uint32_t t0 = fa.segoff[s * K], t1 = fa.segoff[s * K + K];
+      // blocks covering tiles [t0, t1): block b covers [T b / nb, T (b + 1) / nb),
+      // at least one tile each when nb <= T, at most one when nb > T
+      uint32_t covering;
+      if (nb > n_tiles) {
+        covering = t1 - t0;
+      } else {
+        const uint32_t bf = (uint32_t)(((uint64_t)(t0 + 1) * nb - 1) / n_tiles);
+        const uint32_t bl = (uint32_t)(((uint64_t)t1 * nb - 1) / n_tiles);
+        covering = bl - bf + 1;
+      }
+      const uint32_t expected = covering * gridDim.y;
+      const uint32_t old = atomicAdd(&fa.done[s], 1u);
+      s_last = (old + 1 == expected) ? 1u : 0u;
+      if (s_last) fa.done[s] = 0;  // nobody else touches it in this launch
+    }
+    __syncthreads();
+    if (s_last) {
+      const uint32_t r = threadIdx.x;
+      double tc = 0.0;
+      if (r < P)
+        tc = epilogue_node_counts<D, CNT_REP, true>(
+                 fa.e.cnt + (size_t)s * SB * K * Ppad, fa.e.ctot + (size_t)s * K, K, Ppad, r,
+                 fa.a.feat + ((size_t)s * P + r) * SB, fa.e.n_min, fa.e.alpha, nullptr, nullptr,
+                 cnt_copy_elems(fa.e.n_problems, SB, K, P), 1)
+                 .cost;
+      de_step_body(fa.a, s, r, 0, 1, !fa.e.init, fa.e.init != 0, tc, s_cost, s_idx, rows, s_nu);
+    }
+    __syncthreads();
+  }
+}
+
+template <int D, int WAVES, bool FUSE>
 __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
     const TileHdr *__restrict__ hdr, const uint8_t *__restrict__ feat,
-    const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt) {
+    const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt, FuseArgs fa) {
   constexpr int SB = (1 << D) - 1;
   constexpr uint32_t NT = WAVES * 64;
   extern __shared__ __align__(16) uint8_t lds[];
@@ -224,6 +283,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
     eval_nodes<D, 1>(kmask, ns, R);
   }
   flush(cur_sub, cur_cls);
+  if constexpr (FUSE) {
+    __syncthreads();  // the tile buffer becomes DE scratch
+    fused_tail<D, WAVES>(fa, info, n_tiles, t_begin, t_end, K, lds);
+  }
 }
 
 // Epilogue from node left counts (tile path).  One thread per (sub, tree).
@@ -354,20 +417,29 @@ __global__ void k_epilogue_leaves(uint32_t *__restrict__ leafcnt, const uint8_t 
 template <int D, int WAVES>
 hipError_t launch_bits(const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
                        const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
-                       hipStream_t st) {
+                       const FuseArgs *fa, hipStream_t st) {
   size_t lds = (size_t)mask_region(F) + (size_t)F * MCOL;
-  k_fitness_bits<D, WAVES><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt);
+  if (fa) {
+    const size_t need = WAVES * 64 * 12 + 1024 +
+                        (fa->rows_in_lds ? (size_t)P * 2 * ((1u << D) - 1u) * 8 : 0);
+    lds = lds > need ? lds : need;
+    k_fitness_bits<D, WAVES, true><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt,
+                                                                          *fa);
+  } else {
+    k_fitness_bits<D, WAVES, false><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt,
+                                                                           FuseArgs{});
+  }
   return hipGetLastError();
 }
 
 template <int D>
 hipError_t launch_bits_w(uint32_t waves, const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
                          const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
-                         hipStream_t st) {
-  if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, st);
-  if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, st);
-  if (waves == 4) return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, st);
-  return launch_bits<D, 8>(hdr, F, gx, gy, feat, tau, P, cnt, st);
+                         const FuseArgs *fa, hipStream_t st) {
+  if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
+  if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
+  if (waves == 4) return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
+  return launch_bits<D, 8>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
 }
 
 template <int D>
@@ -381,10 +453,23 @@ void launch_epi(uint32_t *cnt, const uint32_t *ctot, const uint8_t *feat, uint32
 
 }  // namespace
 
+// Block threads of the fitness kernel for population P, and the power of two
+// (>= P, >= 64) the fused DE step needs.
+uint32_t fitness_block_threads(uint32_t P) {
+  uint32_t waves = pad64(P) / 64;
+  waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
+  return waves * 64;
+}
+uint32_t fused_threads(uint32_t P) {
+  uint32_t t = 64;
+  while (t < P) t <<= 1;
+  return t;
+}
+
 mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
                                uint32_t n_sub, uint32_t n_problems, uint32_t max_tiles,
                                const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
-                               uint32_t *cnt) {
+                               uint32_t *cnt, const FuseArgs *fa) {
   if (D < 1 || D > 5) return fail(ctx, MH_EINVAL, "tile fitness kernel supports depth 1..5");
   const TileHdr *hdr = reinterpret_cast<const TileHdr *>(tiles);
   hipStream_t st = ctx->stream;
@@ -401,14 +486,16 @@ mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   const uint32_t cap = (max_tiles + ctx->fit_min_tiles - 1) / ctx->fit_min_tiles;
   uint32_t gx = want < cap ? want : cap;
   if (gx == 0) gx = 1;
+  if (fa && (gy != 1 || fused_threads(P) > waves * 64))
+    return fail(ctx, MH_EINVAL, "fused fitness + DE needs one block per tile to hold every tree");
   if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
   hipError_t e = hipSuccess;
   switch (D) {
-    case 1: e = launch_bits_w<1>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
-    case 2: e = launch_bits_w<2>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
-    case 3: e = launch_bits_w<3>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
-    case 4: e = launch_bits_w<4>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
-    case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, st); break;
+    case 1: e = launch_bits_w<1>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
+    case 2: e = launch_bits_w<2>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
+    case 3: e = launch_bits_w<3>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
+    case 4: e = launch_bits_w<4>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
+    case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_fitness_bits");
   if (ctx->profile) {
@@ -451,7 +538,7 @@ mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
                                const uint32_t *tau, uint32_t P, uint32_t D, uint32_t n_min,
                                double alpha, uint32_t *cnt, const FitnessOut &out) {
   mh_status s = launch_fitness_count(ctx, tiles, F, K, n_sub, n_problems, max_tiles, feat, tau, P,
-                                     D, cnt);
+                                     D, cnt, nullptr);
   if (s) return s;
   return launch_fitness_epilogue(ctx, tiles, F, K, n_sub, n_problems, feat, P, D, n_min, alpha,
                                  cnt, out);

@@ -43,6 +43,7 @@ struct Ctx {
   // fitness-kernel launch shape (tunable)
   uint32_t fit_blocks_per_cu = 2;
   uint32_t fit_min_tiles = 1;
+  bool fuse_de = false;  // fitness and DE step in one launch per generation (MHDEOCT_FUSE_DE=1)
 };
 
 // Returns a device buffer of at least `bytes` for `name`, or nullptr (and
@@ -139,7 +140,7 @@ struct FitnessOut {
 // [n_problems][SB][K][Ppad]; fitness blocks add into copy blockIdx % CNT_REP
 // so that fewer blocks contend for the same cache lines, and the epilogue sums
 // the copies.
-constexpr uint32_t CNT_REP = 4;
+constexpr uint32_t CNT_REP = 1;
 __host__ __device__ inline size_t cnt_copy_elems(uint32_t n_problems, uint32_t SB, uint32_t K,
                                                  uint32_t P) {
   return (size_t)n_problems * SB * K * ((P + 63u) & ~63u);
@@ -155,10 +156,13 @@ mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
                                const FitnessOut &out);
 // The two halves of launch_fitness_tiles: the counting kernel (timed when
 // profiling) and the epilogue.
+struct FuseArgs;
 mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
                                uint32_t n_sub, uint32_t n_problems, uint32_t max_tiles,
                                const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
-                               uint32_t *cnt);
+                               uint32_t *cnt, const FuseArgs *fuse);
+uint32_t fitness_block_threads(uint32_t P);
+uint32_t fused_threads(uint32_t P);
 mh_status launch_fitness_epilogue(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
                                   uint32_t n_sub, uint32_t n_problems, const uint8_t *feat,
                                   uint32_t P, uint32_t D, uint32_t n_min, double alpha,
@@ -171,18 +175,21 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
                               const FitnessOut &out);
 
 // de.hip
+// Population layouts: row-major [P][m] (the C ABI) or gene-major [m][P]
+// (inside the DE loops, for coalesced access).
 struct DeDev {
   uint32_t P, D, F, G;
   double M, CR;
   uint64_t seed;
   const uint32_t *n_unique;
+  bool gene_major;
 };
 mh_status launch_de_init(Ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
                          const uint64_t *prob_ids, uint64_t prob_base, uint32_t n_problems,
-                         const double *warm, uint32_t W, double *pop);
+                         const double *warm, uint32_t W, double *pop, bool gene_major);
 mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
                         const uint32_t *n_unique, uint8_t *feat, uint32_t *tau,
-                        uint32_t n_problems, const uint32_t *row_sel);
+                        uint32_t n_problems, const uint32_t *row_sel, bool gene_major);
 // Fitness epilogue fused with the DE step (tile path, depth 1..5): the
 // population just evaluated (trial, or pop itself when init) gets its cost
 // from the node counts cnt, then selection, best and the next trial.
@@ -191,6 +198,14 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
                         const double *trial, uint32_t *best, double *next_trial, uint8_t *feat,
                         uint32_t *tau, uint32_t *cnt, const uint32_t *ctot, uint32_t K,
                         uint32_t n_min, double alpha);
+// Arguments of the fused fitness + DE launch (see fitness.hip), and whether
+// a population of P fits one fused block.
+FuseArgs make_fuse(const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base,
+                   uint32_t n_problems, uint32_t g, bool init, double *pop, double *cost,
+                   const double *trial, uint32_t *best, double *next_trial, uint8_t *feat,
+                   uint32_t *tau, uint32_t *cnt, const uint32_t *ctot, uint32_t K, uint32_t n_min,
+                   double alpha, uint32_t *done, const uint32_t *segoff);
+bool fusable(uint32_t P, uint32_t D, uint32_t F);
 // One DE step for n_problems problems (block per problem).  When feat/tau are
 // given, the new trial population is also decoded into them.
 mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <vector>
 
+#include "de_body.h"
 #include "device_common.h"
 #include "internal.h"
 
@@ -374,20 +375,38 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
   MH_HIP(ctx, hipMemsetAsync(cnt, 0, cb, st));
   const uint32_t *ctot =
       reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tiles) + h.off_ctot);
-  DeDev de{P, D, F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique};
-  s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop);
+  DeDev de{P, D, F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
+  s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop, true);
   if (s) return s;
-  s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat, tau, n_problems, nullptr);
+  s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat, tau, n_problems, nullptr, true);
   if (s) return s;
+  const bool fuse = ctx->fuse_de && fusable(P, D, F);
+  uint32_t *done = (uint32_t *)arena_get(ctx, "mb_done", (size_t)n_problems * 4);
+  if (!done) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(done, 0, (size_t)n_problems * 4, st));
+  const uint32_t *segoff =
+      reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tiles) + h.off_segoff);
   for (uint32_t g = 0; g <= prm->G; ++g) {
-    s = launch_fitness_count(ctx, tiles, F, K, ds->n, n_problems, h.max_tiles, feat, tau, P, D, cnt);
+    if (fuse) {
+      // one launch per generation for every problem of the level: the block
+      // that completes a problem's counts runs its DE step
+      FuseArgs fa = make_fuse(de, prob_ids, 0, n_problems, g + 1, g == 0, pop, cost, trial, best,
+                              g < prm->G ? trial : nullptr, feat, tau, cnt, ctot, K, prm->n_min,
+                              prm->alpha, done, segoff);
+      s = launch_fitness_count(ctx, tiles, F, K, ds->n, n_problems, h.max_tiles, feat, tau, P, D,
+                               cnt, &fa);
+      if (s) return s;
+      continue;
+    }
+    s = launch_fitness_count(ctx, tiles, F, K, ds->n, n_problems, h.max_tiles, feat, tau, P, D, cnt,
+                             nullptr);
     if (s) return s;
     s = launch_de_gen(ctx, de, prob_ids, 0, n_problems, g + 1, g == 0, pop, cost, trial, best,
                       g < prm->G ? trial : nullptr, feat, tau, cnt, ctot, K, prm->n_min,
                       prm->alpha);
     if (s) return s;
   }
-  return launch_decode(ctx, pop, P, D, F, ds->n_unique, feat_out, tau_out, n_problems, best);
+  return launch_decode(ctx, pop, P, D, F, ds->n_unique, feat_out, tau_out, n_problems, best, true);
 }
 
 // Algorithm 2.  flags: MH_SEQUENTIAL or MH_BATCHED.

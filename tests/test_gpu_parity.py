@@ -241,3 +241,21 @@ def test_subtree_solve_depth6_walk_path(mh):
     w.D = 6
     want, got, _ = _deoct_both(mh, w, 5, G=6, P=12)
     _same_tree(want, got)
+
+
+def test_fused_and_separate_de_step_agree(mh, monkeypatch):
+    """The fused launch (DE step run by the block that completes the counts)
+    and the separate DE-step launch give the same DEOCT run."""
+    from paper_2311_06952_amd import capi
+    w = synth.plain_small(8, n=5000)
+    monkeypatch.setenv("MHDEOCT_FUSE_DE", "0")
+    ctx_sep = capi.Context(0)
+    monkeypatch.delenv("MHDEOCT_FUSE_DE")
+    ctx_fus = capi.Context(0)
+    out = []
+    for ctx in (ctx_sep, ctx_fus):
+        ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
+        out.append(mh.subtree_solve(ds, w.D, mh.de_params(100, 30, 0.5, 0.9, 3), ctx=ctx))
+    _same_tree(out[0], out[1])
+    ctx_sep.close()
+    ctx_fus.close()
