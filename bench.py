@@ -48,6 +48,101 @@ def cpu_baseline(w, seconds=15.0):
                        f"workload, {evals:.3g} evals in {el:.1f} s, single thread")
 
 
+KERNEL = "k_fitness_bits<3,4,false>"
+KERNEL_SOURCES = ("fitness.hip", "epilogue.h", "de_body.h", "device_common.h", "internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fitness_bits_plain_scale_traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_06952_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fitness kernel from the committed counter
+    summary, or None when it is missing or the kernel sources changed since
+    the counters were taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def ds_of(mh, Xd, yd, w, ctx):
+    ranks, nu = mh.rank_encode(Xd, ctx)
+    return mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
+
+
+def fitness_kernel_loop(mh, ctx, ds, w, launches):
+    """Average duration (ms) of the fitness kernel over `launches` population
+    evaluations of a freshly initialised population on the tiled layout."""
+    import torch
+    ts = mh.TileSet(ds, ctx=ctx)
+    pop = mh.de_init(w.P, w.D, w.F, 1001, 0, ctx=ctx)
+    feat, tau = mh.tree_decode(pop, w.D, w.F, ds.n_unique, ctx)
+    out = (None, None, None, torch.zeros(w.P, dtype=torch.float64, device=pop.device))
+    ts.fitness(feat, tau, w.D, out=out)
+    ctx.stats(reset=True)
+    ctx.profile(True)
+    for _ in range(launches):
+        ts.fitness(feat, tau, w.D, out=out)
+    st = ctx.stats(reset=True)
+    ctx.profile(False)
+    return st["ms"] / max(st["launches"], 1), st
+
+
+def roofline(w, kernel_ms):
+    """The fitness kernel against the int32 VALU roof: D compare-and-descend
+    steps and one count per sample-tree evaluation (Algorithm 1)."""
+    evals_launch = w.P * w.n
+    ops_per_eval = w.D + 1
+    achieved = ops_per_eval * evals_launch / (kernel_ms * 1e-3)
+    bytes_eval = (4 * w.F + 1) / w.P
+    traffic = measured_traffic()
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
+            "kernel": KERNEL, "kernel_ms_avg": kernel_ms,
+            "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
+            "algorithmic_bytes_per_launch": bytes_eval * evals_launch,
+            "hbm_equiv": {"GB_s": bytes_eval * evals_launch / (kernel_ms * 1e-3) / 1e9,
+                          "frac": bytes_eval * evals_launch / (kernel_ms * 1e-3) / HBM_PEAK}}
+
+
+def kernel_only(args):
+    """Counter runs: one plain device copy of known size (the calibration for
+    the byte counters), then the fitness-kernel loop.  Prints one JSON line."""
+    import torch
+    import paper_2311_06952_amd as mh
+    from paper_2311_06952_amd import synth
+    w = synth.plain_scale(1)
+    ctx = mh.default_context(0)
+    dev = torch.device("cuda", 0)
+    copy_bytes = 256 << 20
+    a = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    Xd = torch.as_tensor(w.X).to(dev)
+    yd = torch.as_tensor(w.y).to(dev)
+    kernel_ms, st = fitness_kernel_loop(mh, ctx, ds_of(mh, Xd, yd, w, ctx), w, args.steps)
+    print(json.dumps({"kernel": KERNEL, "workload": w.name, "launches": int(st["launches"]),
+                      "kernel_ms_avg": kernel_ms, "copy_bytes": copy_bytes,
+                      "kernel_source_sha256_16": kernel_source_hash(),
+                      "roofline": roofline(w, kernel_ms)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,11 +150,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="time only the fitness kernel (for profiler runs)")
+                    help="only a calibration copy and --steps fitness-kernel launches "
+                         "(for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.kernel_only:
+        kernel_only(args)
+        return
 
     import torch
     import paper_2311_06952_amd as mh
@@ -89,27 +189,19 @@ def main():
     evals_per_step = w.P * w.n * (w.G + 1)
     value = evals_per_step * args.steps / el
 
-    # fitness-kernel duration with HIP events on the library's stream
-    ctx.profile(True)
+    # fitness-kernel duration: the same steps again with HIP events that the
+    # population-evaluation launches record themselves on the library's
+    # stream (read back after the region; kept out of the timed steps above
+    # because event-carrying launches cost about 3 us each)
     ctx.stats(reset=True)
-    ranks, nu = mh.rank_encode(Xd, ctx)
-    ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
-    mh.subtree_solve(ds, w.D, prm, ctx=ctx)
-    st = ctx.stats(reset=True)
+    ctx.profile(True)
+    for _ in range(args.steps):
+        step()
     ctx.profile(False)
-    # the last launch evaluates the single best tree; the others the population
-    pop_launches = st["launches"] - 1
+    st = ctx.stats(reset=True)
     kernel_ms = st["ms"] / max(st["launches"], 1)
-    evals_launch = w.P * w.n
-    ops_per_eval = w.D + 1          # D compare-and-descend steps + 1 count
-    achieved = ops_per_eval * evals_launch / (kernel_ms * 1e-3)
-    bytes_eval = (4 * w.F + 1) / w.P
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
-            "kernel": "k_fitness_bits<3,4>", "kernel_ms_avg": kernel_ms,
-            "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
-            "hbm_equiv": {"GB_s": bytes_eval * evals_launch / (kernel_ms * 1e-3) / 1e9,
-                          "frac": bytes_eval * evals_launch / (kernel_ms * 1e-3) / HBM_PEAK}}
+    roof = roofline(w, kernel_ms)
+    roof["timed_launches"] = int(st["launches"])
     out = {
         "metric": "sample-tree evals/s (fitness)",
         "value": value,
@@ -126,8 +218,8 @@ def main():
         "config": {"workload": w.name, "n": w.n, "F": w.F, "K": w.K, "D": w.D, "P": w.P,
                    "G": w.G, "M": w.M, "CR": w.CR, "form": "plain DEOCT, one launch per "
                    "population evaluation"},
-        "kernel_evals_per_s": evals_launch / (kernel_ms * 1e-3),
-        "fitness_launches_per_step": int(st["launches"]),
+        "kernel_evals_per_s": w.P * w.n / (kernel_ms * 1e-3),
+        "fitness_launches_per_step": w.G + 2,  # G + 1 population evaluations + the best tree
         "subtree_solves_per_s": args.steps / el,
         "best_correct": res["correct"],
         "roofline": roof,

@@ -29,6 +29,42 @@ mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what) {
   return fail(ctx, e == hipErrorOutOfMemory ? MH_ENOMEM : MH_EDEVICE, m);
 }
 
+constexpr size_t PROF_MAX_PAIRS = 4096;
+
+mh_status prof_collect(Ctx *ctx) {
+  MH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i + 1 < ctx->prof_used; i += 2) {
+    float ms = 0.f;
+    MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[i], ctx->prof_ev[i + 1]));
+    ctx->prof_ms += ms;
+  }
+  ctx->prof_used = 0;
+  return MH_OK;
+}
+
+bool prof_pair(Ctx *ctx, hipEvent_t *e0, hipEvent_t *e1) {
+  *e0 = *e1 = nullptr;
+  if (!ctx->profile) return false;
+  if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+    if (ctx->prof_ev.size() >= 2 * PROF_MAX_PAIRS) {
+      if (prof_collect(ctx) != MH_OK) return false;
+    } else {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess) return false;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return false;
+      }
+      ctx->prof_ev.push_back(a);
+      ctx->prof_ev.push_back(b);
+    }
+  }
+  *e0 = ctx->prof_ev[ctx->prof_used];
+  *e1 = ctx->prof_ev[ctx->prof_used + 1];
+  ctx->prof_used += 2;
+  return true;
+}
+
 void *arena_get(Ctx *ctx, const char *name, size_t bytes) {
   if (bytes == 0) bytes = 256;
   bytes = align256(bytes);
@@ -224,7 +260,11 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   fb.label = lab1;
   fb.correct = corr1;
   fb.cost = cost1;
+  // a single-tree evaluation: left out of the population-kernel timing
+  const bool prof = ctx->profile;
+  ctx->profile = false;
   s = eval_trees(ctx, es, f1, t1, 1, D, prm->n_min, prm->alpha, fb);
+  ctx->profile = prof;
   if (s) return s;
   std::memset(out, 0, sizeof(*out));
   out->D = D;
@@ -294,10 +334,6 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_FIT_BLOCKS_PER_CU")) c->c.fit_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FIT_MIN_TILES")) c->c.fit_min_tiles = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FUSE_DE")) c->c.fuse_de = atoi(v) != 0;
-  if (hipEventCreate(&c->c.ev0) != hipSuccess || hipEventCreate(&c->c.ev1) != hipSuccess) {
-    delete c;
-    return fail(nullptr, MH_EDEVICE, "hipEventCreate failed");
-  }
   *out = c;
   return MH_OK;
 }
@@ -307,8 +343,7 @@ void mh_ctx_destroy(mh_ctx *ctx) {
   (void)hipSetDevice(ctx->c.device);
   (void)hipStreamSynchronize(ctx->c.stream);
   for (auto &b : ctx->c.arena.bufs) (void)hipFree(b.ptr);
-  if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
-  if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
+  for (hipEvent_t e : ctx->c.prof_ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -325,7 +360,7 @@ mh_status mh_ctx_profile(mh_ctx *ctx, int enable) {
 mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms, uint64_t *evals,
                        uint64_t *tiles, int reset) {
   CTX_OR_FAIL(ctx);
-  MH_HIP(&ctx->c, hipStreamSynchronize(ctx->c.stream));
+  if (mh_status s = prof_collect(&ctx->c)) return s;
   if (launches) *launches = ctx->c.prof_launches;
   if (ms) *ms = ctx->c.prof_ms;
   if (evals) *evals = ctx->c.prof_evals;

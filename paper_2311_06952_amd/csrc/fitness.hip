@@ -14,6 +14,8 @@
 //
 // Walk kernel (any depth 1..10): lane = sample, the Algorithm 1 walk of one
 // tree at a time with an LDS histogram per (leaf, class).
+#include <hip/hip_ext.h>
+
 #include "de_body.h"
 #include "device_common.h"
 #include "epilogue.h"
@@ -414,20 +416,22 @@ __global__ void k_epilogue_leaves(uint32_t *__restrict__ leafcnt, const uint8_t 
   }
 }
 
+// Launches on st; when e0/e1 are given the launch records them at the
+// kernel's start and end.
 template <int D, int WAVES>
 hipError_t launch_bits(const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
                        const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
-                       const FuseArgs *fa, hipStream_t st) {
+                       const FuseArgs *fa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   size_t lds = (size_t)mask_region(F) + (size_t)F * MCOL;
   if (fa) {
     const size_t need = WAVES * 64 * 12 + 1024 +
                         (fa->rows_in_lds ? (size_t)P * 2 * ((1u << D) - 1u) * 8 : 0);
     lds = lds > need ? lds : need;
-    k_fitness_bits<D, WAVES, true><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt,
-                                                                          *fa);
+    hipExtLaunchKernelGGL((k_fitness_bits<D, WAVES, true>), dim3(gx, gy), dim3(WAVES * 64), lds,
+                          st, e0, e1, 0, hdr, feat, tau, P, cnt, *fa);
   } else {
-    k_fitness_bits<D, WAVES, false><<<dim3(gx, gy), WAVES * 64, lds, st>>>(hdr, feat, tau, P, cnt,
-                                                                           FuseArgs{});
+    hipExtLaunchKernelGGL((k_fitness_bits<D, WAVES, false>), dim3(gx, gy), dim3(WAVES * 64), lds,
+                          st, e0, e1, 0, hdr, feat, tau, P, cnt, FuseArgs{});
   }
   return hipGetLastError();
 }
@@ -435,11 +439,11 @@ hipError_t launch_bits(const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
 template <int D>
 hipError_t launch_bits_w(uint32_t waves, const TileHdr *hdr, uint32_t F, uint32_t gx, uint32_t gy,
                          const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t *cnt,
-                         const FuseArgs *fa, hipStream_t st) {
-  if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
-  if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
-  if (waves == 4) return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
-  return launch_bits<D, 8>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st);
+                         const FuseArgs *fa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (waves == 1) return launch_bits<D, 1>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1);
+  if (waves == 2) return launch_bits<D, 2>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1);
+  if (waves == 4) return launch_bits<D, 4>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1);
+  return launch_bits<D, 8>(hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1);
 }
 
 template <int D>
@@ -488,22 +492,18 @@ mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   if (gx == 0) gx = 1;
   if (fa && (gy != 1 || fused_threads(P) > waves * 64))
     return fail(ctx, MH_EINVAL, "fused fitness + DE needs one block per tile to hold every tree");
-  if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
+  hipEvent_t e0, e1;
+  const bool timed = prof_pair(ctx, &e0, &e1);
   hipError_t e = hipSuccess;
   switch (D) {
-    case 1: e = launch_bits_w<1>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
-    case 2: e = launch_bits_w<2>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
-    case 3: e = launch_bits_w<3>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
-    case 4: e = launch_bits_w<4>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
-    case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st); break;
+    case 1: e = launch_bits_w<1>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
+    case 2: e = launch_bits_w<2>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
+    case 3: e = launch_bits_w<3>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
+    case 4: e = launch_bits_w<4>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
+    case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_fitness_bits");
-  if (ctx->profile) {
-    MH_HIP(ctx, hipEventRecord(ctx->ev1, st));
-    MH_HIP(ctx, hipEventSynchronize(ctx->ev1));
-    float ms = 0.f;
-    MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->prof_ms += ms;
+  if (timed) {
     ctx->prof_launches += 1;
     ctx->prof_evals += (uint64_t)n_sub * P;
     ctx->prof_tiles += max_tiles;
@@ -558,17 +558,13 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   size_t lds = (size_t)(2 * SB + (in_lds ? hist_cells : 0u)) * 4;
   if (n_sub > 0) {
     uint32_t blocks = (n_sub + WALK_THREADS * WALK_ITEMS - 1) / (WALK_THREADS * WALK_ITEMS);
-    if (ctx->profile) MH_HIP(ctx, hipEventRecord(ctx->ev0, st));
-    k_fitness_walk<<<blocks, WALK_THREADS, lds, st>>>(ds->ranks, ds->ld, ds->labels, idx, n_sub,
-                                                      feat, tau, P, D, ds->F, ds->K, ds->n,
-                                                      leafcnt, in_lds);
+    hipEvent_t e0, e1;
+    const bool timed = prof_pair(ctx, &e0, &e1);
+    hipExtLaunchKernelGGL(k_fitness_walk, dim3(blocks), dim3(WALK_THREADS), lds, st, e0, e1, 0,
+                          ds->ranks, ds->ld, ds->labels, idx, n_sub, feat, tau, P, D, ds->F,
+                          ds->K, ds->n, leafcnt, in_lds);
     MH_LAUNCHED(ctx, "k_fitness_walk");
-    if (ctx->profile) {
-      MH_HIP(ctx, hipEventRecord(ctx->ev1, st));
-      MH_HIP(ctx, hipEventSynchronize(ctx->ev1));
-      float ms = 0.f;
-      MH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      ctx->prof_ms += ms;
+    if (timed) {
       ctx->prof_launches += 1;
       ctx->prof_evals += (uint64_t)n_sub * P;
     }

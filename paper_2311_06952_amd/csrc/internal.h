@@ -35,9 +35,13 @@ struct Ctx {
   int num_cu = 256;
   std::string err;
   Arena arena;
-  // fitness-kernel timing
+  // fitness-kernel timing: each timed launch takes a start/stop event pair
+  // that the launch itself records (hipExtLaunchKernelGGL), so the measured
+  // interval is the kernel's execution and nothing waits on it; the pairs
+  // are read back by mh_ctx_stats (or when the pool is full).
   bool profile = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
   uint64_t prof_launches = 0, prof_evals = 0, prof_tiles = 0;
   double prof_ms = 0.0;
   // fitness-kernel launch shape (tunable)
@@ -51,6 +55,13 @@ struct Ctx {
 void *arena_get(Ctx *ctx, const char *name, size_t bytes);
 
 mh_status fail(Ctx *ctx, mh_status code, const std::string &msg);
+
+// With profiling on, hands out the next event pair for a timed launch (and
+// returns true); with it off returns false and leaves *e0 = *e1 = nullptr.
+bool prof_pair(Ctx *ctx, hipEvent_t *e0, hipEvent_t *e1);
+// Waits for the stream and adds the elapsed time of every used pair to
+// prof_ms.
+mh_status prof_collect(Ctx *ctx);
 mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what);
 
 #define MH_HIP(ctx, call)                                  \
