@@ -105,11 +105,13 @@ const char *mh_last_error(const mh_ctx *ctx);
 /* Library version string (static). */
 const char *mh_version(void);
 
-/* Timing of the fitness kernel.  When enabled, the library brackets every
- * fitness-kernel launch with HIP events on the context's stream and adds up
- * their elapsed time.  mh_ctx_stats synchronises the stream and reports the
- * totals since the last reset: launches, milliseconds, sample-tree
- * evaluations (sum over launches of trees x samples) and scanned tiles. */
+/* Timing of the fitness kernel.  When enabled, every population-evaluation
+ * launch of the fitness kernel records a start and a stop HIP event itself
+ * on the context's stream (nothing waits on them; the single-tree
+ * evaluation at the end of subtree_solve is not timed).  mh_ctx_stats
+ * synchronises the stream and reports the totals since the last reset:
+ * launches, milliseconds, sample-tree evaluations (sum over launches of
+ * trees x samples) and scanned tiles. */
 mh_status mh_ctx_profile(mh_ctx *ctx, int enable);
 mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms,
                        uint64_t *evals, uint64_t *tiles, int reset);
@@ -236,6 +238,68 @@ mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
  * feat/tau/correct to host.  Synchronises. */
 mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                  uint32_t n_sub, uint8_t *feat, uint32_t *tau, uint32_t *correct);
+
+/* ---------------------------------------------------------------------- */
+/* a8. Served subtree solves: DEOCT (Algorithm 4) per request on the problem */
+/* of eq. opt_all, with continuous batching.                                 */
+/* ---------------------------------------------------------------------- */
+
+typedef struct mh_server mh_server;
+
+/* Result of one request (host struct). */
+typedef struct {
+  uint64_t req_id;
+  mh_status status;      /* MH_OK, or MH_EINVAL when the request's X held a NaN */
+  uint32_t n, F, K;
+  mh_tree tree;          /* equal to subtree_solve on the same data, problem id 0 */
+  uint64_t t_submit_ns;  /* host steady clock: mh_server_submit */
+  uint64_t t_admit_ns;   /* admission (device state allocated, work queued) */
+  uint64_t t_done_ns;    /* completion observed by mh_server_pump / _poll */
+} mh_result;
+
+/* A server on the context's device and stream.  hbm_budget bytes of device
+ * memory are allocated once, here, as the pool that holds the resident
+ * state of admitted requests (tile layout, population, counters); the
+ * context's arena additionally holds the rank-encoding scratch of the
+ * largest request.  At most max_slots (1..256) requests are resident at a
+ * time.  The context must not be used for other calls while the server
+ * exists (they would share its stream and arena). */
+mh_status mh_server_create(mh_ctx *ctx, uint64_t hbm_budget, uint32_t max_slots,
+                           mh_server **out);
+/* Waits for the server's queued work and frees its pool. */
+void mh_server_destroy(mh_server *srv);
+
+/* Queues a request: DEOCT of depth D (1..5) with parameters *prm
+ * (3 <= P <= 512) on the n samples of X (device, row-major [n][F] float32,
+ * F <= 80) with labels (device [n], < K, 2 <= K <= 255).  X and labels must
+ * stay valid and unchanged until the request's result has been returned by
+ * mh_server_poll.  Requests are admitted in submission order when a slot is
+ * free and the pool has room for the request's footprint (the head of the
+ * queue waits; later requests do not pass it).  Returns MH_ENOMEM when the
+ * footprint exceeds the whole pool, MH_EINVAL for invalid arguments.
+ * Host-only: queues nothing on the device. */
+mh_status mh_server_submit(mh_server *srv, uint64_t req_id, const float *X,
+                           const uint8_t *labels, uint32_t n, uint32_t F, uint32_t K,
+                           uint32_t D, const mh_de_params *prm);
+/* Device bytes of the pool a request of this shape occupies while resident. */
+mh_status mh_server_footprint(uint32_t n, uint32_t F, uint32_t K, uint32_t D,
+                              uint32_t P, uint64_t *bytes);
+/* Runs up to `ticks` scheduling rounds.  A round collects the requests
+ * whose device work has finished, admits queued requests while slots and
+ * pool allow (rank encoding, tile layout, initial population, queued on the
+ * stream), then queues one generation of every resident request: one
+ * fitness launch per depth for all of them together, and one DE launch per
+ * depth (epilogue, selection, best, next trial), each request at its own
+ * generation.  Requests that ran their G generations get their best tree
+ * evaluated and copied to pinned host memory.  At most a few rounds are in
+ * flight on the device; a round waits for older ones as needed.  Stops
+ * early when nothing is resident or queued.  *n_active / *n_queued (may be
+ * NULL) receive the counts after the last round. */
+mh_status mh_server_pump(mh_server *srv, uint32_t ticks, uint32_t *n_active,
+                         uint32_t *n_queued);
+/* Moves up to `max` completed results (in completion order) to out (host)
+ * and sets *n_done.  Does not wait. */
+mh_status mh_server_poll(mh_server *srv, mh_result *out, uint32_t max, uint32_t *n_done);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ MH_SEQUENTIAL, MH_BATCHED = 0, 1
 EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh_ctx_profile",
            "mh_ctx_stats", "mh_rank_encode", "tree_decode", "fitness_eval", "mh_tileset_bytes",
            "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
-           "mh_train", "split1")
+           "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
+           "mh_server_footprint", "mh_server_pump", "mh_server_poll")
 
 
 class MhError(RuntimeError):
@@ -48,6 +49,13 @@ class TreeC(C.Structure):
                 ("label", C.c_uint8 * 1024), ("correct", C.c_uint32), ("cost", C.c_double)]
 
 
+class ResultC(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int32), ("n", C.c_uint32),
+                ("F", C.c_uint32), ("K", C.c_uint32), ("tree", TreeC),
+                ("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64),
+                ("t_done_ns", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -58,6 +66,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; it must be the
+    # one loaded, so that the library and torch share one runtime
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     V, U32, U64, I32, D = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_double
     sig = {
@@ -82,6 +93,12 @@ def load_library(path: str = LIB_PATH):
                       C.POINTER(TreeC)], I32),
         "split1": ([V, C.POINTER(DatasetC), V, U32, C.POINTER(C.c_uint8), C.POINTER(U32),
                     C.POINTER(U32)], I32),
+        "mh_server_create": ([V, U64, U32, C.POINTER(V)], I32),
+        "mh_server_destroy": ([V], None),
+        "mh_server_submit": ([V, U64, V, V, U32, U32, U32, U32, C.POINTER(DEParamsC)], I32),
+        "mh_server_footprint": ([U32, U32, U32, U32, U32, C.POINTER(U64)], I32),
+        "mh_server_pump": ([V, U32, C.POINTER(U32), C.POINTER(U32)], I32),
+        "mh_server_poll": ([V, C.POINTER(ResultC), U32, C.POINTER(U32)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)  # AttributeError if a symbol is missing
@@ -343,3 +360,78 @@ def split1(ds: Dataset, idx=None, ctx: Context | None = None):
     ctx.check(ctx.lib.split1(ctx.h, C.byref(dsc), _ptr(idx), n_sub, C.byref(f), C.byref(t),
                              C.byref(c)))
     return int(f.value), int(t.value), int(c.value)
+
+
+def server_footprint(n: int, F: int, K: int, D: int, P: int) -> int:
+    """Device bytes a served request of this shape holds while resident."""
+    lib = load_library()
+    b = C.c_uint64()
+    rc = lib.mh_server_footprint(n, F, K, D, P, C.byref(b))
+    if rc != MH_OK:
+        raise MhError(rc, "invalid request shape")
+    return int(b.value)
+
+
+class Server:
+    """mh_server: continuous-batching DEOCT requests on one context.  The
+    context must not be used for other calls while the server lives."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        h = C.c_void_p()
+        self.ctx.check(self.ctx.lib.mh_server_create(self.ctx.h, int(hbm_budget), int(max_slots),
+                                                     C.byref(h)))
+        self.h = h
+        self._inputs = {}  # req_id -> (X, y): kept alive until the result is polled
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.mh_server_destroy(self.h)
+            self.h = None
+            self._inputs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req_id: int, X, y, K: int, D: int, prm: DEParamsC):
+        """X: float32 [n][F], y: uint8 [n], both torch tensors on the device."""
+        X = X.contiguous()
+        y = y.contiguous()
+        n, F = int(X.shape[0]), int(X.shape[1])
+        self.ctx.check(self.ctx.lib.mh_server_submit(self.h, int(req_id), _ptr(X), _ptr(y), n, F,
+                                                     int(K), int(D), C.byref(prm)))
+        self._inputs[int(req_id)] = (X, y)
+
+    def pump(self, ticks: int = 1):
+        """Runs up to `ticks` scheduling rounds; returns (resident, queued)."""
+        a, q = C.c_uint32(), C.c_uint32()
+        self.ctx.check(self.ctx.lib.mh_server_pump(self.h, int(ticks), C.byref(a), C.byref(q)))
+        return int(a.value), int(q.value)
+
+    def poll(self, max_results: int = 64) -> list:
+        buf = (ResultC * max_results)()
+        k = C.c_uint32()
+        self.ctx.check(self.ctx.lib.mh_server_poll(self.h, buf, max_results, C.byref(k)))
+        out = []
+        for i in range(k.value):
+            r = buf[i]
+            self._inputs.pop(int(r.req_id), None)
+            out.append(dict(req_id=int(r.req_id), status=int(r.status), n=int(r.n), F=int(r.F),
+                            K=int(r.K), tree=_tree_dict(r.tree), t_submit_ns=int(r.t_submit_ns),
+                            t_admit_ns=int(r.t_admit_ns), t_done_ns=int(r.t_done_ns)))
+        return out
+
+    def drain(self, max_rounds: int = 10_000_000) -> list:
+        """Pumps until nothing is resident or queued; returns every result."""
+        res = []
+        for _ in range(max_rounds):
+            a, q = self.pump(16)
+            res += self.poll(256)
+            if a == 0 and q == 0:
+                break
+        res += self.poll(256)
+        return res
+

@@ -10,9 +10,6 @@
 #include "device_common.h"
 #include "internal.h"
 
-struct mh_ctx {
-  mh::Ctx c;
-};
 
 namespace mh {
 
@@ -109,7 +106,7 @@ static mh_status check_dataset(Ctx *ctx, const mh_dataset *ds) {
   return MH_OK;
 }
 
-static mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D) {
+mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D) {
   if (!p) return fail(ctx, MH_EINVAL, "DE params are null");
   if (p->P < 3 || p->P > MH_MAX_POP) return fail(ctx, MH_EINVAL, "P must be in 3..1024");
   if (D < 1 || D > MH_MAX_DEPTH) return fail(ctx, MH_EINVAL, "D must be in 1..10");

@@ -101,6 +101,28 @@ __global__ __launch_bounds__(1024) void k_de_gen(StepArgs a, GenArgs e) {
                a.rows_in_lds ? rows : nullptr, s_nu);
 }
 
+// One block per job (problem), each with its own population, tile-set
+// counts and generation; threads r < P of the job are its individuals.
+template <int D>
+__global__ __launch_bounds__(1024) void k_de_jobs(const GenJob *__restrict__ jobs) {
+  constexpr int SB = (1 << D) - 1;
+  __shared__ double s_cost[1024];
+  __shared__ uint32_t s_idx[1024];
+  __shared__ uint32_t s_nu[256];
+  extern __shared__ double rows[];
+  const GenJob jb = jobs[blockIdx.x];
+  const uint32_t P = jb.a.P, Ppad = pad64(P), r = threadIdx.x;
+  double tc = 0.0;
+  if (r < P) {
+    tc = epilogue_node_counts<D, CNT_REP>(jb.e.cnt, jb.e.ctot, jb.e.K, Ppad, r,
+                                          jb.a.feat + (size_t)r * SB, jb.e.n_min, jb.e.alpha,
+                                          nullptr, nullptr, cnt_copy_elems(1, SB, jb.e.K, P), 1)
+             .cost;
+  }
+  de_step_body(jb.a, 0, r, 0, 1, !jb.e.init, jb.e.init != 0, tc, s_cost, s_idx,
+               jb.a.rows_in_lds ? rows : nullptr, s_nu);
+}
+
 }  // namespace
 
 mh_status launch_de_init(Ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
@@ -195,6 +217,37 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
     default: return fail(ctx, MH_EINVAL, "fused DE step supports depth 1..5");
   }
   MH_LAUNCHED(ctx, "k_de_gen");
+  return MH_OK;
+}
+
+GenJob make_gen_job(const DeDev &de, uint64_t prob, uint32_t g, bool init, double *pop,
+                    double *cost, const double *trial, uint32_t *best, double *next_trial,
+                    uint8_t *feat, uint32_t *tau, uint32_t *cnt, const uint32_t *ctot,
+                    uint32_t K, uint32_t n_min, double alpha, uint32_t P_max) {
+  GenJob j;
+  j.a = make_args(de, nullptr, prob, g, pop, cost, trial, nullptr, best, next_trial, feat, tau);
+  // every job of a launch shares the dynamic LDS sized for the largest one
+  j.a.rows_in_lds = rows_lds_bytes(P_max, de.D) > 0;
+  j.e = GenArgs{cnt, ctot, K, n_min, alpha, init ? 1 : 0, 1u, 1u};
+  return j;
+}
+
+mh_status launch_de_jobs(Ctx *ctx, uint32_t D, const GenJob *jobs, uint32_t n_jobs,
+                         uint32_t P_max) {
+  if (n_jobs == 0) return MH_OK;
+  if (P_max > 1024) return fail(ctx, MH_EINVAL, "DE jobs support P <= 1024");
+  const uint32_t threads = step_threads(P_max);
+  const size_t lds = rows_lds_bytes(P_max, D);
+  hipStream_t st = ctx->stream;
+  switch (D) {
+    case 1: k_de_jobs<1><<<n_jobs, threads, lds, st>>>(jobs); break;
+    case 2: k_de_jobs<2><<<n_jobs, threads, lds, st>>>(jobs); break;
+    case 3: k_de_jobs<3><<<n_jobs, threads, lds, st>>>(jobs); break;
+    case 4: k_de_jobs<4><<<n_jobs, threads, lds, st>>>(jobs); break;
+    case 5: k_de_jobs<5><<<n_jobs, threads, lds, st>>>(jobs); break;
+    default: return fail(ctx, MH_EINVAL, "DE jobs support depth 1..5");
+  }
+  MH_LAUNCHED(ctx, "k_de_jobs");
   return MH_OK;
 }
 

@@ -165,6 +165,13 @@ struct GenArgs {
   uint32_t n_problems;  // problems in the count buffer (replica stride)
 };
 
+// One problem's DE generation inside a multi-job launch (k_de_jobs): the
+// epilogue of its counts, then the DE step; e.n_problems is 1.
+struct GenJob {
+  StepArgs a;
+  GenArgs e;
+};
+
 // Everything the fused fitness + DE kernel needs besides the fitness inputs.
 struct FuseArgs {
   StepArgs a;               // prob_ids / prob_base select the problem ids

@@ -190,24 +190,29 @@ __device__ __forceinline__ void fused_tail(const FuseArgs &fa, const uint32_t *_
   }
 }
 
+// One block's share of a population evaluation on one tile set: block bx of
+// nbx takes tiles [n_tiles bx / nbx, n_tiles (bx + 1) / nbx) for the trees
+// by * NT .. by * NT + NT - 1.
 template <int D, int WAVES, bool FUSE>
-__global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
-    const TileHdr *__restrict__ hdr, const uint8_t *__restrict__ feat,
-    const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt, FuseArgs fa) {
+__device__ __forceinline__ void fitness_block(const TileHdr *__restrict__ hdr,
+                                              const uint8_t *__restrict__ feat,
+                                              const uint32_t *__restrict__ tau, uint32_t P,
+                                              uint32_t *__restrict__ cnt, const FuseArgs &fa,
+                                              uint32_t bx, uint32_t nbx, uint32_t by,
+                                              uint8_t *lds) {
   constexpr int SB = (1 << D) - 1;
   constexpr uint32_t NT = WAVES * 64;
-  extern __shared__ __align__(16) uint8_t lds[];
   const uint8_t *base = reinterpret_cast<const uint8_t *>(hdr);
   const uint32_t F = hdr->F, K = hdr->K;
   const uint32_t n_tiles = hdr->n_tiles;
-  const uint32_t t_begin = (uint32_t)((uint64_t)n_tiles * blockIdx.x / gridDim.x);
-  const uint32_t t_end = (uint32_t)((uint64_t)n_tiles * (blockIdx.x + 1) / gridDim.x);
+  const uint32_t t_begin = (uint32_t)((uint64_t)n_tiles * bx / nbx);
+  const uint32_t t_end = (uint32_t)((uint64_t)n_tiles * (bx + 1) / nbx);
   if (t_begin >= t_end) return;
   const uint32_t *__restrict__ info = reinterpret_cast<const uint32_t *>(base + hdr->off_info);
   const uint8_t *__restrict__ data = base + hdr->off_data;
   const size_t rec_bytes = tile_bytes(F);
   const uint32_t nchunk = 48u * F;
-  const uint32_t r = blockIdx.y * NT + threadIdx.x;
+  const uint32_t r = by * NT + threadIdx.x;
   const bool live = r < P;
   const uint32_t Ppad = pad64(P);
   const uint32_t mregion = mask_region(F);
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
   for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
 
   uint32_t *const cnt_rep =
-      cnt + (blockIdx.x % CNT_REP) * cnt_copy_elems(hdr->n_problems, SB, K, P);
+      cnt + (bx % CNT_REP) * cnt_copy_elems(hdr->n_problems, SB, K, P);
   auto flush = [&](uint32_t sub, uint32_t cls) {
     if (!live) return;
     uint32_t *c = cnt_rep + ((size_t)sub * SB * K + cls) * Ppad + r;
@@ -289,6 +294,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
     __syncthreads();  // the tile buffer becomes DE scratch
     fused_tail<D, WAVES>(fa, info, n_tiles, t_begin, t_end, K, lds);
   }
+}
+
+template <int D, int WAVES, bool FUSE>
+__global__ __launch_bounds__(WAVES * 64) void k_fitness_bits(
+    const TileHdr *__restrict__ hdr, const uint8_t *__restrict__ feat,
+    const uint32_t *__restrict__ tau, uint32_t P, uint32_t *__restrict__ cnt, FuseArgs fa) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  fitness_block<D, WAVES, FUSE>(hdr, feat, tau, P, cnt, fa, blockIdx.x, gridDim.x, blockIdx.y,
+                                lds);
+}
+
+// Several independent population evaluations (one per job, each on its own
+// tile set with its own trees and counters) in one launch: block b works for
+// job job_of[b] as its block b - blk0 of nblk.  Every job's population fits
+// one block (P <= WAVES * 64).
+template <int D, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_fitness_jobs(const FitJob *__restrict__ jobs,
+                                                             const uint16_t *__restrict__ job_of) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const FitJob jb = jobs[job_of[blockIdx.x]];
+  fitness_block<D, WAVES, false>(jb.hdr, jb.feat, jb.tau, jb.P, jb.cnt, FuseArgs{},
+                                 blockIdx.x - jb.blk0, jb.nblk, 0, lds);
 }
 
 // Epilogue from node left counts (tile path).  One thread per (sub, tree).
@@ -510,6 +537,33 @@ mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   }
   (void)K;
   (void)n_problems;
+  return MH_OK;
+}
+
+mh_status launch_fitness_jobs(Ctx *ctx, uint32_t D, uint32_t waves, uint32_t F_max,
+                              const FitJob *jobs, const uint16_t *job_of, uint32_t n_blocks) {
+  if (n_blocks == 0) return MH_OK;
+  const size_t lds = (size_t)mask_region(F_max) + (size_t)F_max * MCOL;
+  hipStream_t st = ctx->stream;
+  const dim3 grid(n_blocks), block(waves * 64);
+#define MH_JOBS_W(DD)                                                                       \
+  switch (waves) {                                                                          \
+    case 1: k_fitness_jobs<DD, 1><<<grid, block, lds, st>>>(jobs, job_of); break;           \
+    case 2: k_fitness_jobs<DD, 2><<<grid, block, lds, st>>>(jobs, job_of); break;           \
+    case 4: k_fitness_jobs<DD, 4><<<grid, block, lds, st>>>(jobs, job_of); break;           \
+    case 8: k_fitness_jobs<DD, 8><<<grid, block, lds, st>>>(jobs, job_of); break;           \
+    default: return fail(ctx, MH_EINVAL, "fitness jobs: waves must be 1, 2, 4 or 8");      \
+  }
+  switch (D) {
+    case 1: MH_JOBS_W(1) break;
+    case 2: MH_JOBS_W(2) break;
+    case 3: MH_JOBS_W(3) break;
+    case 4: MH_JOBS_W(4) break;
+    case 5: MH_JOBS_W(5) break;
+    default: return fail(ctx, MH_EINVAL, "fitness jobs support depth 1..5");
+  }
+#undef MH_JOBS_W
+  MH_LAUNCHED(ctx, "k_fitness_jobs");
   return MH_OK;
 }
 

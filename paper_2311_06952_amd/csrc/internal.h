@@ -50,6 +50,9 @@ struct Ctx {
   bool fuse_de = false;  // fitness and DE step in one launch per generation (MHDEOCT_FUSE_DE=1)
 };
 
+// Checks DE parameters for a depth-D problem (MH_EINVAL with a message).
+mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D);
+
 // Returns a device buffer of at least `bytes` for `name`, or nullptr (and
 // sets ctx->err) on allocation failure.
 void *arena_get(Ctx *ctx, const char *name, size_t bytes);
@@ -121,8 +124,12 @@ TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems)
 // Kernel launchers (one per .hip file)
 // ---------------------------------------------------------------------------
 // rank_encode.hip
+// With nan_out == nullptr it synchronises and fails with MH_EINVAL if X holds
+// a NaN; otherwise it stays asynchronous and sets *nan_out (device u32) to a
+// non-zero value when X holds a NaN.
 mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F,
-                             uint32_t ld, uint32_t *ranks, uint32_t *n_unique);
+                             uint32_t ld, uint32_t *ranks, uint32_t *n_unique,
+                             uint32_t *nan_out = nullptr);
 // Sorts (key, value) pairs by the low `key_bits` of key (stable LSD radix
 // sort, 8 bits per pass).  Buffers are ping-ponged; the sorted result ends in
 // (*keys, *vals) which may point at the alternate buffers on return.
@@ -178,6 +185,20 @@ mh_status launch_fitness_epilogue(Ctx *ctx, const void *tiles, uint32_t F, uint3
                                   uint32_t n_sub, uint32_t n_problems, const uint8_t *feat,
                                   uint32_t P, uint32_t D, uint32_t n_min, double alpha,
                                   uint32_t *cnt, const FitnessOut &out);
+// One population evaluation inside a multi-job launch (k_fitness_jobs):
+// trees feat/tau ([P][SB]) over the tile set hdr, counts into cnt ([SB][K]
+// [Ppad], zero on entry); the job owns blocks blk0 .. blk0 + nblk - 1.
+struct FitJob {
+  const TileHdr *hdr;
+  const uint8_t *feat;
+  const uint32_t *tau;
+  uint32_t *cnt;
+  uint32_t P, blk0, nblk, pad;
+};
+// Launches n_blocks blocks of waves * 64 threads; job_of[b] names block b's
+// job.  Every job needs P <= waves * 64 and a tile set with F <= F_max.
+mh_status launch_fitness_jobs(Ctx *ctx, uint32_t D, uint32_t waves, uint32_t F_max,
+                              const FitJob *jobs, const uint16_t *job_of, uint32_t n_blocks);
 // Direct per-sample walk for any depth (1..10): one tree at a time, leaf
 // counts per (tree, leaf, class), then the same epilogue.
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
@@ -217,6 +238,18 @@ FuseArgs make_fuse(const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base
                    uint32_t *tau, uint32_t *cnt, const uint32_t *ctot, uint32_t K, uint32_t n_min,
                    double alpha, uint32_t *done, const uint32_t *segoff);
 bool fusable(uint32_t P, uint32_t D, uint32_t F);
+// A DE generation for one problem inside a multi-job launch: the epilogue of
+// cnt (then re-zeroed), selection unless init, best, and the trial of
+// generation g into next_trial (decoded into feat/tau) unless it is null.
+// P_max is the largest population of the launch.
+struct GenJob;
+GenJob make_gen_job(const DeDev &de, uint64_t prob, uint32_t g, bool init, double *pop,
+                    double *cost,
+                    const double *trial, uint32_t *best, double *next_trial, uint8_t *feat,
+                    uint32_t *tau, uint32_t *cnt, const uint32_t *ctot, uint32_t K,
+                    uint32_t n_min, double alpha, uint32_t P_max);
+mh_status launch_de_jobs(Ctx *ctx, uint32_t D, const GenJob *jobs, uint32_t n_jobs,
+                         uint32_t P_max);
 // One DE step for n_problems problems (block per problem).  When feat/tau are
 // given, the new trial population is also decoded into them.
 mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
@@ -252,3 +285,8 @@ mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_M
                                                uint8_t *, uint32_t *));
 
 }  // namespace mh
+
+// The C ABI's context handle.
+struct mh_ctx {
+  mh::Ctx c;
+};

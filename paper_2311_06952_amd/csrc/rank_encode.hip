@@ -249,12 +249,13 @@ mh_status radix_sort_pairs(Ctx *ctx, uint64_t **keys, uint32_t **vals, uint64_t 
 }
 
 mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
-                             uint32_t *ranks, uint32_t *n_unique) {
+                             uint32_t *ranks, uint32_t *n_unique, uint32_t *nan_out) {
   uint64_t total64 = (uint64_t)n * F;
   if (total64 >= 0xFFFFFFFFull) return fail(ctx, MH_EINVAL, "n * F too large");
   uint32_t total = (uint32_t)total64;
   if (total == 0) {
     MH_HIP(ctx, hipMemsetAsync(n_unique, 0, (size_t)F * 4, ctx->stream));
+    if (nan_out) MH_HIP(ctx, hipMemsetAsync(nan_out, 0, 4, ctx->stream));
     return MH_OK;
   }
   uint64_t *ka = (uint64_t *)arena_get(ctx, "re_keys_a", (size_t)total * 8);
@@ -263,7 +264,7 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
   uint32_t *vb = (uint32_t *)arena_get(ctx, "re_vals_b", (size_t)total * 4);
   uint32_t *flags = (uint32_t *)arena_get(ctx, "re_flags", (size_t)total * 4 + 256);
   if (!ka || !kb || !va || !vb || !flags) return MH_ENOMEM;
-  uint32_t *nan_flag = flags + ((total + 63u) & ~63u);
+  uint32_t *nan_flag = nan_out ? nan_out : flags + ((total + 63u) & ~63u);
   hipStream_t st = ctx->stream;
   MH_HIP(ctx, hipMemsetAsync(nan_flag, 0, 4, st));
   uint32_t blocks = (total + 255) / 256;
@@ -282,6 +283,7 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
   if (s) return s;
   k_rank_write<<<blocks, 256, 0, st>>>(vals, flags, n, total, ld, ranks, n_unique);
   MH_LAUNCHED(ctx, "k_rank_write");
+  if (nan_out) return MH_OK;
   uint32_t h_nan = 0;
   MH_HIP(ctx, hipMemcpyAsync(&h_nan, nan_flag, 4, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipStreamSynchronize(st));
