@@ -143,12 +143,122 @@ def kernel_only(args):
                       "roofline": roofline(w, kernel_ms)}), flush=True)
 
 
+def _device_requests(torch, reqs):
+    """Request datasets generated on the device: a Gaussian mixture with K
+    class means ~ N(0, 2I), y uniform, x ~ N(mu_y, I), from torch's Philox
+    generator seeded with the request's seed."""
+    out = []
+    for q in reqs:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(q.seed)
+        mu = torch.randn((q.K, q.F), generator=g, device="cuda") * (2.0 ** 0.5)
+        y = torch.randint(q.K, (q.n,), generator=g, device="cuda")
+        X = (mu[y] + torch.randn((q.n, q.F), generator=g, device="cuda")).contiguous()
+        out.append((X, y.to(torch.uint8)))
+    torch.cuda.synchronize()
+    return out
+
+
+def serving(mh, count=96, seed=11, n_hi=1e7):
+    """Served subtree solves: `count` requests (n log-uniform in [1e3, n_hi],
+    F in 4..32, K in 2..10, D in 2..4, P = 128, G = 100).  The same requests
+    are solved (1) one after another with subtree_solve, (2) through the
+    server all submitted at once (its capacity), (3) through the server with
+    Poisson arrivals at 0.8x that capacity (latency)."""
+    import torch
+    from paper_2311_06952_amd import capi, synth
+    reqs = synth.request_stream(seed, count, 1.0, n_hi=n_hi)
+    data = _device_requests(torch, reqs)
+    evals = sum(q.n * q.P * (q.G + 1) for q in reqs)
+    prm = [mh.de_params(q.P, q.G, 0.5, 0.9, 5000 + q.rid) for q in reqs]
+
+    # (1) plain: one request at a time on one context
+    ctx = capi.Context(0)
+    t0 = time.perf_counter()
+    for q, (X, y), p in zip(reqs, data, prm):
+        ranks, nu = mh.rank_encode(X, ctx)
+        mh.subtree_solve(mh.Dataset(ranks, y, nu, q.n, q.F, q.K), q.D, p, ctx=ctx)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ctx.close()
+
+    budget = 96 << 30
+    slots = 64
+
+    def run(arrivals):
+        sctx = capi.Context(0)
+        srv = mh.Server(budget, slots, ctx=sctx)
+        t0 = time.monotonic_ns()
+        nxt, done = 0, []
+        while len(done) < count:
+            now = time.monotonic_ns() - t0
+            while nxt < count and arrivals[nxt] <= now:
+                q = reqs[nxt]
+                srv.submit(q.rid, data[nxt][0], data[nxt][1], q.K, q.D, prm[nxt])
+                nxt += 1
+            act, queued = srv.pump(1)
+            done += srv.poll(256)
+            if act == 0 and queued == 0 and nxt < count:
+                time.sleep(max(0.0, (arrivals[nxt] - (time.monotonic_ns() - t0)) * 1e-9))
+        el = (time.monotonic_ns() - t0) * 1e-9
+        srv.close()
+        sctx.close()
+        lat = sorted((r["t_done_ns"] - (t0 + arrivals[r["req_id"]])) * 1e-6 for r in done)
+        bad = [r["req_id"] for r in done if r["status"] != 0]
+        return el, lat, bad
+
+    el_c, _, bad_c = run([0] * count)
+    cap = count / el_c
+    rate = 0.8 * cap
+    arr = [int(q.arrival / rate * 1e9) for q in reqs]   # the unit-rate stream rescaled
+    el_o, lat, bad_o = run(arr)
+    pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100 * (len(lat) - 1))))]
+    return {
+        "workload": f"{count} requests, n log-uniform [1e3, {n_hi:.0e}], F 4..32, K 2..10, "
+                    f"D 2..4, P 128, G 100, Gaussian mixtures generated on the device",
+        "evals": evals,
+        "plain": {"s": t_plain, "evals_per_s": evals / t_plain, "solves_per_s": count / t_plain},
+        "served_all_at_once": {"s": el_c, "evals_per_s": evals / el_c, "solves_per_s": cap},
+        "served_poisson": {"rate_per_s": rate, "s": el_o, "evals_per_s": evals / el_o,
+                           "solves_per_s": count / el_o, "p50_ms": pct(50), "p99_ms": pct(99),
+                           "max_ms": lat[-1]},
+        "failed": bad_c + bad_o,
+    }
+
+
+def moving_horizon(mh, ctx):
+    """Moving-horizon training of a depth-8 tree with horizon 3 on n = 10^6,
+    F = 20, K = 3 (P = 128, G = 100): the level-batched form against the
+    node-by-node form; both build the identical tree."""
+    import torch
+    from paper_2311_06952_amd import synth
+    w = synth.batched_mh(1)
+    ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
+    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    out = {"workload": w.name}
+    trees = {}
+    for name, batched in (("batched", True), ("sequential", False)):
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trees[name] = mh.mh_train(ds, w.D, w.D_MH, prm, batched=batched, ctx=ctx)
+        el = time.perf_counter() - t0
+        st = ctx.stats(reset=True)
+        out[name] = {"s": el, "evals": int(st["evals"]), "evals_per_s": st["evals"] / el}
+    out["same_tree"] = bool(all((trees["batched"][k] == trees["sequential"][k]).all()
+                                for k in ("feat", "tau", "label")))
+    out["correct"] = trees["batched"]["correct"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the serving and moving-horizon measurements")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps fitness-kernel launches "
                          "(for counter runs)")
@@ -224,6 +334,9 @@ def main():
         "best_correct": res["correct"],
         "roofline": roof,
     }
+    if not args.no_extra:
+        out["serving"] = serving(mh)
+        out["moving_horizon"] = moving_horizon(mh, ctx)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -110,8 +110,9 @@ const char *mh_version(void);
  * on the context's stream (nothing waits on them; the single-tree
  * evaluation at the end of subtree_solve is not timed).  mh_ctx_stats
  * synchronises the stream and reports the totals since the last reset:
- * launches, milliseconds, sample-tree evaluations (sum over launches of
- * trees x samples) and scanned tiles. */
+ * timed launches and their milliseconds, and, over every fitness launch of
+ * the context whether timed or not, sample-tree evaluations (trees x
+ * samples) and scanned tiles. */
 mh_status mh_ctx_profile(mh_ctx *ctx, int enable);
 mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms,
                        uint64_t *evals, uint64_t *tiles, int reset);

@@ -530,11 +530,9 @@ mh_status launch_fitness_count(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
     case 5: e = launch_bits_w<5>(waves, hdr, F, gx, gy, feat, tau, P, cnt, fa, st, e0, e1); break;
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_fitness_bits");
-  if (timed) {
-    ctx->prof_launches += 1;
-    ctx->prof_evals += (uint64_t)n_sub * P;
-    ctx->prof_tiles += max_tiles;
-  }
+  if (timed) ctx->prof_launches += 1;
+  ctx->prof_evals += (uint64_t)n_sub * P;
+  ctx->prof_tiles += max_tiles;
   (void)K;
   (void)n_problems;
   return MH_OK;
@@ -618,10 +616,8 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
                           ds->ranks, ds->ld, ds->labels, idx, n_sub, feat, tau, P, D, ds->F,
                           ds->K, ds->n, leafcnt, in_lds);
     MH_LAUNCHED(ctx, "k_fitness_walk");
-    if (timed) {
-      ctx->prof_launches += 1;
-      ctx->prof_evals += (uint64_t)n_sub * P;
-    }
+    if (timed) ctx->prof_launches += 1;
+    ctx->prof_evals += (uint64_t)n_sub * P;
   }
   k_epilogue_leaves<<<(P + 127) / 128, 128, 0, st>>>(leafcnt, feat, P, D, ds->K, n_min, alpha, out);
   MH_LAUNCHED(ctx, "k_epilogue_leaves");
