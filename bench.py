@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the serving and moving-horizon measurements")
+    ap.add_argument("--extra-only", action="store_true",
+                    help="only the serving and moving-horizon measurements (for profiler runs)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps fitness-kernel launches "
                          "(for counter runs)")
@@ -269,6 +271,12 @@ def main():
 
     if args.kernel_only:
         kernel_only(args)
+        return
+    if args.extra_only:
+        import paper_2311_06952_amd as mh
+        print(json.dumps({"serving": serving(mh),
+                          "moving_horizon": moving_horizon(mh, mh.default_context(0))}),
+              flush=True)
         return
 
     import torch
