@@ -78,49 +78,31 @@ __global__ __launch_bounds__(1024) void k_de_step(StepArgs a) {
                s_nu);
 }
 
-template <int D>
-__global__ __launch_bounds__(1024) void k_de_gen(StepArgs a, GenArgs e) {
+template <int D, int LB>
+__global__ __launch_bounds__(LB) void k_de_gen(StepArgs a, GenArgs e) {
   constexpr int SB = (1 << D) - 1;
   __shared__ double s_cost[1024];
   __shared__ uint32_t s_idx[1024];
   __shared__ uint32_t s_nu[256];
   extern __shared__ double rows[];
-  const uint32_t P = a.P, Ppad = pad64(P), sub = blockIdx.x;
-  const uint32_t tpi = e.tpi, r = threadIdx.x / tpi, j = threadIdx.x % tpi;
-  double tc = 0.0;
-  // the tpi lanes of a tree's group are all active or all idle, so the
-  // epilogue's shuffles stay inside active groups
-  if (r < P) {
-    tc = epilogue_node_counts<D, CNT_REP>(
-             e.cnt + (size_t)sub * SB * e.K * Ppad, e.ctot + (size_t)sub * e.K, e.K, Ppad, r,
-             a.feat + ((size_t)sub * P + r) * SB, e.n_min, e.alpha, nullptr, nullptr,
-             cnt_copy_elems(gridDim.x, SB, e.K, P), tpi)
-             .cost;
-  }
-  de_step_body(a, sub, r, j, tpi, !e.init, e.init != 0, tc, s_cost, s_idx,
-               a.rows_in_lds ? rows : nullptr, s_nu);
+  (void)SB;
+  de_gen_body<D, CNT_REP, false, (LB <= 256)>(a, e, blockIdx.x, s_cost, s_idx,
+                                              a.rows_in_lds ? rows : nullptr, s_nu);
 }
 
 // One block per job (problem), each with its own population, tile-set
 // counts and generation; threads r < P of the job are its individuals.
-template <int D>
-__global__ __launch_bounds__(1024) void k_de_jobs(const GenJob *__restrict__ jobs) {
+template <int D, int LB>
+__global__ __launch_bounds__(LB) void k_de_jobs(const GenJob *__restrict__ jobs) {
   constexpr int SB = (1 << D) - 1;
   __shared__ double s_cost[1024];
   __shared__ uint32_t s_idx[1024];
   __shared__ uint32_t s_nu[256];
   extern __shared__ double rows[];
+  (void)SB;
   const GenJob jb = jobs[blockIdx.x];
-  const uint32_t P = jb.a.P, Ppad = pad64(P), r = threadIdx.x;
-  double tc = 0.0;
-  if (r < P) {
-    tc = epilogue_node_counts<D, CNT_REP>(jb.e.cnt, jb.e.ctot, jb.e.K, Ppad, r,
-                                          jb.a.feat + (size_t)r * SB, jb.e.n_min, jb.e.alpha,
-                                          nullptr, nullptr, cnt_copy_elems(1, SB, jb.e.K, P), 1)
-             .cost;
-  }
-  de_step_body(jb.a, 0, r, 0, 1, !jb.e.init, jb.e.init != 0, tc, s_cost, s_idx,
-               jb.a.rows_in_lds ? rows : nullptr, s_nu);
+  de_gen_body<D, CNT_REP, false, (LB <= 256)>(jb.a, jb.e, 0, s_cost, s_idx,
+                                              jb.a.rows_in_lds ? rows : nullptr, s_nu);
 }
 
 }  // namespace
@@ -208,14 +190,20 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
   const uint32_t threads = rp * tpi;
   const size_t lds = rows_lds_bytes(de.P, de.D);
   hipStream_t st = ctx->stream;
+#define MH_GEN(DD)                                                            \
+  if (threads <= 256)                                                         \
+    k_de_gen<DD, 256><<<n_problems, threads, lds, st>>>(a, e);                \
+  else                                                                        \
+    k_de_gen<DD, 1024><<<n_problems, threads, lds, st>>>(a, e);
   switch (de.D) {
-    case 1: k_de_gen<1><<<n_problems, threads, lds, st>>>(a, e); break;
-    case 2: k_de_gen<2><<<n_problems, threads, lds, st>>>(a, e); break;
-    case 3: k_de_gen<3><<<n_problems, threads, lds, st>>>(a, e); break;
-    case 4: k_de_gen<4><<<n_problems, threads, lds, st>>>(a, e); break;
-    case 5: k_de_gen<5><<<n_problems, threads, lds, st>>>(a, e); break;
+    case 1: MH_GEN(1) break;
+    case 2: MH_GEN(2) break;
+    case 3: MH_GEN(3) break;
+    case 4: MH_GEN(4) break;
+    case 5: MH_GEN(5) break;
     default: return fail(ctx, MH_EINVAL, "fused DE step supports depth 1..5");
   }
+#undef MH_GEN
   MH_LAUNCHED(ctx, "k_de_gen");
   return MH_OK;
 }
@@ -239,14 +227,20 @@ mh_status launch_de_jobs(Ctx *ctx, uint32_t D, const GenJob *jobs, uint32_t n_jo
   const uint32_t threads = step_threads(P_max);
   const size_t lds = rows_lds_bytes(P_max, D);
   hipStream_t st = ctx->stream;
+#define MH_JOBS(DD)                                                           \
+  if (threads <= 256)                                                         \
+    k_de_jobs<DD, 256><<<n_jobs, threads, lds, st>>>(jobs);                   \
+  else                                                                        \
+    k_de_jobs<DD, 1024><<<n_jobs, threads, lds, st>>>(jobs);
   switch (D) {
-    case 1: k_de_jobs<1><<<n_jobs, threads, lds, st>>>(jobs); break;
-    case 2: k_de_jobs<2><<<n_jobs, threads, lds, st>>>(jobs); break;
-    case 3: k_de_jobs<3><<<n_jobs, threads, lds, st>>>(jobs); break;
-    case 4: k_de_jobs<4><<<n_jobs, threads, lds, st>>>(jobs); break;
-    case 5: k_de_jobs<5><<<n_jobs, threads, lds, st>>>(jobs); break;
+    case 1: MH_JOBS(1) break;
+    case 2: MH_JOBS(2) break;
+    case 3: MH_JOBS(3) break;
+    case 4: MH_JOBS(4) break;
+    case 5: MH_JOBS(5) break;
     default: return fail(ctx, MH_EINVAL, "DE jobs support depth 1..5");
   }
+#undef MH_JOBS
   MH_LAUNCHED(ctx, "k_de_jobs");
   return MH_OK;
 }

@@ -175,17 +175,7 @@ __device__ __forceinline__ void fused_tail(const FuseArgs &fa, const uint32_t *_
       if (s_last) fa.done[s] = 0;  // nobody else touches it in this launch
     }
     __syncthreads();
-    if (s_last) {
-      const uint32_t r = threadIdx.x;
-      double tc = 0.0;
-      if (r < P)
-        tc = epilogue_node_counts<D, CNT_REP, true>(
-                 fa.e.cnt + (size_t)s * SB * K * Ppad, fa.e.ctot + (size_t)s * K, K, Ppad, r,
-                 fa.a.feat + ((size_t)s * P + r) * SB, fa.e.n_min, fa.e.alpha, nullptr, nullptr,
-                 cnt_copy_elems(fa.e.n_problems, SB, K, P), 1)
-                 .cost;
-      de_step_body(fa.a, s, r, 0, 1, !fa.e.init, fa.e.init != 0, tc, s_cost, s_idx, rows, s_nu);
-    }
+    if (s_last) de_gen_body<D, CNT_REP, true, false>(fa.a, fa.e, s, s_cost, s_idx, rows, s_nu);
     __syncthreads();
   }
 }
