@@ -193,12 +193,25 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
       !corr1 || !cost1)
     return MH_ENOMEM;
   DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
+  uint32_t *err = (uint32_t *)arena_get(ctx, "ss_err", 256);
+  if (!err) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(err, 0, 4, st));
   // g = 0: initialise, decode, evaluate
   s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop, true);
   if (s) return s;
-  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr, true);
-  if (s) return s;
-  if (es.tiles) {
+  bool persisted = false;
+  if (es.tiles && ctx->persist) {
+    s = launch_deoct_persist(ctx, es.tiles, ds->F, K, n_sub, D, prm, prob, ds->n_unique, pop, cost,
+                             best, err, &persisted);
+    if (s) return s;
+  }
+  if (!persisted) {
+    s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr, true);
+    if (s) return s;
+  }
+  if (persisted) {
+    // the whole run happened in the cooperative launch
+  } else if (es.tiles) {
     // tile path: per generation the counting kernel, then the epilogue fused
     // with selection, best and the next trial
     const TileHdr h = tile_layout(n_sub, ds->F, K, 1);
@@ -270,7 +283,10 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   MH_HIP(ctx, hipMemcpyAsync(out->label, lab1, SL, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipMemcpyAsync(&out->correct, corr1, 4, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipMemcpyAsync(&out->cost, cost1, 8, hipMemcpyDeviceToHost, st));
+  uint32_t h_err = 0;
+  MH_HIP(ctx, hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipStreamSynchronize(st));
+  if (h_err) return fail(ctx, MH_EDEVICE, "DEOCT grid barrier: a wait gave up");
   (void)K;
   return MH_OK;
 }
@@ -331,6 +347,10 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_FIT_BLOCKS_PER_CU")) c->c.fit_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FIT_MIN_TILES")) c->c.fit_min_tiles = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FUSE_DE")) c->c.fuse_de = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_PERSIST")) c->c.persist = atoi(v) != 0;
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
+    c->c.coop = coop != 0;
   *out = c;
   return MH_OK;
 }

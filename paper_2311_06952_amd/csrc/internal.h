@@ -48,6 +48,8 @@ struct Ctx {
   uint32_t fit_blocks_per_cu = 2;
   uint32_t fit_min_tiles = 1;
   bool fuse_de = false;  // fitness and DE step in one launch per generation (MHDEOCT_FUSE_DE=1)
+  bool persist = true;   // whole DEOCT runs as one cooperative launch (MHDEOCT_PERSIST=0 turns off)
+  bool coop = false;     // the device supports cooperative launches
 };
 
 // Checks DE parameters for a depth-D problem (MH_EINVAL with a message).
@@ -256,6 +258,19 @@ mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
                          uint64_t prob_base, uint32_t n_problems, uint32_t g, double *pop,
                          double *cost, const double *trial, const double *trial_cost,
                          uint32_t *best, double *next_trial, uint8_t *feat, uint32_t *tau);
+
+// persist.hip
+// A whole DEOCT run of one problem (tile set `tiles`, n_sub samples) as one
+// cooperative launch: pop (gene-major [m][P]) holds the initial population
+// on entry and the final one on exit, with cost ([P]) and best ([1]).  err
+// (device u32) becomes non-zero if a grid-barrier wait gave up.  Sets *used
+// to false, queuing nothing, when the shape does not fit the kernel (depth
+// above 5, P above 512, F above 80, LDS, co-residency); the caller then runs
+// the per-generation kernels.
+mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                               uint32_t n_sub, uint32_t D, const mh_de_params *prm, uint64_t prob,
+                               const uint32_t *n_unique, double *pop, double *cost,
+                               uint32_t *best, uint32_t *err, bool *used);
 
 // mh.hip
 // Exact best depth-1 split (Algorithm 2, horizon-1 branch) of every subset

@@ -124,17 +124,30 @@ __global__ void k_tile_plan(TileHdr *__restrict__ hdr, uint32_t nseg) {
     segoff[nseg] = carry;
     hdr->n_tiles = carry;
   }
-  __syncthreads();
-  // info words
-  for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) {
-    uint32_t c = ctot[s];
-    uint32_t t0 = segoff[s];
-    uint32_t sub = s / K, cls = s % K;
-    for (uint32_t q = 0; q * TILE_CAP < c; ++q) {
-      uint32_t cnt = min(TILE_CAP, c - q * TILE_CAP);
-      info[t0 + q] = (sub << 16) | (cls << 8) | cnt;
-    }
+  (void)info;
+  (void)K;
+}
+
+// Info word of every tile: thread per tile, its segment found by binary
+// search over the segment offsets.
+__global__ void k_tile_info(TileHdr *__restrict__ hdr, uint32_t nseg) {
+  uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
+  const uint32_t *ctot = reinterpret_cast<const uint32_t *>(base + hdr->off_ctot);
+  const uint32_t *segoff = reinterpret_cast<const uint32_t *>(base + hdr->off_segoff);
+  uint32_t *info = reinterpret_cast<uint32_t *>(base + hdr->off_info);
+  const uint32_t K = hdr->K, n_tiles = hdr->n_tiles;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  // the last segment s with segoff[s] <= t (empty segments share offsets)
+  uint32_t lo = 0, hi = nseg;  // segoff[lo] <= t < segoff[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segoff[mid] <= t) lo = mid;
+    else hi = mid;
   }
+  const uint32_t q = t - segoff[lo];
+  const uint32_t cnt = min(TILE_CAP, ctot[lo] - q * TILE_CAP);
+  info[t] = ((lo / K) << 16) | ((lo % K) << 8) | cnt;
 }
 
 // Scatter sample ids into their tile slots.  Each block reserves one range
@@ -240,6 +253,8 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   }
   k_tile_plan<<<1, 1024, 0, st>>>(dh, nseg);
   MH_LAUNCHED(ctx, "k_tile_plan");
+  k_tile_info<<<(h.max_tiles + 255) / 256, 256, 0, st>>>(dh, nseg);
+  MH_LAUNCHED(ctx, "k_tile_info");
   if (n_sub > 0) {
     uint32_t nb = (n_sub + 255) / 256;
     k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, dh);

@@ -259,3 +259,27 @@ def test_fused_and_separate_de_step_agree(mh, monkeypatch):
     _same_tree(out[0], out[1])
     ctx_sep.close()
     ctx_fus.close()
+
+
+@pytest.mark.parametrize("D,P,K,M", [(1, 12, 2, 0.5), (2, 64, 5, -1.0), (3, 300, 3, 0.5),
+                                     (4, 128, 7, 0.5), (5, 40, 4, 0.5)])
+def test_persistent_and_per_generation_deoct_agree(mh, monkeypatch, D, P, K, M):
+    """The whole-run cooperative kernel and the per-generation kernels give the
+    same DEOCT run (and the oracle's)."""
+    from paper_2311_06952_amd import capi
+    X, y = synth.random_small(40 + D, 6000, 9, K)
+    monkeypatch.setenv("MHDEOCT_PERSIST", "0")
+    ctx_gen = capi.Context(0)
+    monkeypatch.setenv("MHDEOCT_PERSIST", "1")
+    ctx_per = capi.Context(0)
+    out = []
+    for ctx in (ctx_gen, ctx_per):
+        ds = mh.dataset(X, y, K, ctx=ctx)
+        out.append(mh.subtree_solve(ds, D, mh.de_params(P, 12, M, 0.9, 5 + D), prob=3, ctx=ctx))
+    _same_tree(out[0], out[1])
+    want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 12, M, 0.9, 5 + D),
+                        prob=3)
+    _same_tree(want, out[1])
+    ctx_gen.close()
+    ctx_per.close()
+
