@@ -48,9 +48,9 @@ def cpu_baseline(w, seconds=15.0):
                        f"workload, {evals:.3g} evals in {el:.1f} s, single thread")
 
 
-KERNEL = "k_fitness_bits<3,4,false>"
-KERNEL_SOURCES = ("fitness.hip", "epilogue.h", "de_body.h", "device_common.h", "internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fitness_bits_plain_scale_traffic.txt")
+KERNEL = "k_deoct_persist<3,4>"
+KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_deoct_persist_plain_scale_traffic.txt")
 
 
 def kernel_source_hash():
@@ -63,7 +63,7 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the fitness kernel from the committed counter
+    """HBM bytes per launch of the DEOCT kernel from the committed counter
     summary, or None when it is missing or the kernel sources changed since
     the counters were taken."""
     try:
@@ -85,44 +85,29 @@ def ds_of(mh, Xd, yd, w, ctx):
     return mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
 
 
-def fitness_kernel_loop(mh, ctx, ds, w, launches):
-    """Average duration (ms) of the fitness kernel over `launches` population
-    evaluations of a freshly initialised population on the tiled layout."""
-    import torch
-    ts = mh.TileSet(ds, ctx=ctx)
-    pop = mh.de_init(w.P, w.D, w.F, 1001, 0, ctx=ctx)
-    feat, tau = mh.tree_decode(pop, w.D, w.F, ds.n_unique, ctx)
-    out = (None, None, None, torch.zeros(w.P, dtype=torch.float64, device=pop.device))
-    ts.fitness(feat, tau, w.D, out=out)
-    ctx.stats(reset=True)
-    ctx.profile(True)
-    for _ in range(launches):
-        ts.fitness(feat, tau, w.D, out=out)
-    st = ctx.stats(reset=True)
-    ctx.profile(False)
-    return st["ms"] / max(st["launches"], 1), st
-
-
-def roofline(w, kernel_ms):
-    """The fitness kernel against the int32 VALU roof: D compare-and-descend
-    steps and one count per sample-tree evaluation (Algorithm 1)."""
-    evals_launch = w.P * w.n
+def roofline(w, kernel_ms, launches_per_step):
+    """The dominant kernel against the int32 VALU roof: D compare-and-descend
+    steps and one count per sample-tree evaluation (Algorithm 1).  With the
+    whole run in one launch, a launch covers all G + 1 population
+    evaluations."""
+    evals_launch = w.P * w.n * (w.G + 1) // launches_per_step
     ops_per_eval = w.D + 1
     achieved = ops_per_eval * evals_launch / (kernel_ms * 1e-3)
-    bytes_eval = (4 * w.F + 1) / w.P
-    traffic = measured_traffic()
+    bytes_launch = (4 * w.F + 1) / w.P * evals_launch
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
-            "kernel": KERNEL, "kernel_ms_avg": kernel_ms,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+            "kernel": KERNEL if launches_per_step == 1 else "k_fitness_bits<3,4,false>",
+            "kernel_ms_avg": kernel_ms, "launches_per_step": launches_per_step,
             "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
-            "algorithmic_bytes_per_launch": bytes_eval * evals_launch,
-            "hbm_equiv": {"GB_s": bytes_eval * evals_launch / (kernel_ms * 1e-3) / 1e9,
-                          "frac": bytes_eval * evals_launch / (kernel_ms * 1e-3) / HBM_PEAK}}
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "hbm_equiv": {"GB_s": bytes_launch / (kernel_ms * 1e-3) / 1e9,
+                          "frac": bytes_launch / (kernel_ms * 1e-3) / HBM_PEAK}}
 
 
 def kernel_only(args):
     """Counter runs: one plain device copy of known size (the calibration for
-    the byte counters), then the fitness-kernel loop.  Prints one JSON line."""
+    the byte counters), then --steps DEOCT runs on the resident plain-scale
+    dataset.  Prints one JSON line."""
     import torch
     import paper_2311_06952_amd as mh
     from paper_2311_06952_amd import synth
@@ -136,11 +121,20 @@ def kernel_only(args):
     torch.cuda.synchronize()
     Xd = torch.as_tensor(w.X).to(dev)
     yd = torch.as_tensor(w.y).to(dev)
-    kernel_ms, st = fitness_kernel_loop(mh, ctx, ds_of(mh, Xd, yd, w, ctx), w, args.steps)
+    ds = ds_of(mh, Xd, yd, w, ctx)
+    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    ctx.stats(reset=True)
+    ctx.profile(True)
+    for _ in range(args.steps):
+        mh.subtree_solve(ds, w.D, prm, ctx=ctx)
+    ctx.profile(False)
+    st = ctx.stats(reset=True)
+    kernel_ms = st["ms"] / max(st["launches"], 1)
+    lps = max(1, round(st["launches"] / args.steps))
     print(json.dumps({"kernel": KERNEL, "workload": w.name, "launches": int(st["launches"]),
                       "kernel_ms_avg": kernel_ms, "copy_bytes": copy_bytes,
                       "kernel_source_sha256_16": kernel_source_hash(),
-                      "roofline": roofline(w, kernel_ms)}), flush=True)
+                      "roofline": roofline(w, kernel_ms, lps)}), flush=True)
 
 
 def _device_requests(torch, reqs):
@@ -318,7 +312,8 @@ def main():
     ctx.profile(False)
     st = ctx.stats(reset=True)
     kernel_ms = st["ms"] / max(st["launches"], 1)
-    roof = roofline(w, kernel_ms)
+    lps = max(1, round(st["launches"] / args.steps))
+    roof = roofline(w, kernel_ms, lps)
     roof["timed_launches"] = int(st["launches"])
     out = {
         "metric": "sample-tree evals/s (fitness)",
@@ -334,10 +329,9 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "F": w.F, "K": w.K, "D": w.D, "P": w.P,
-                   "G": w.G, "M": w.M, "CR": w.CR, "form": "plain DEOCT, one launch per "
-                   "population evaluation"},
-        "kernel_evals_per_s": w.P * w.n / (kernel_ms * 1e-3),
-        "fitness_launches_per_step": w.G + 2,  # G + 1 population evaluations + the best tree
+                   "G": w.G, "M": w.M, "CR": w.CR, "form": "plain DEOCT, the whole run in "
+                   "one cooperative launch"},
+        "kernel_evals_per_s": roof["evals_per_launch"] / (kernel_ms * 1e-3),
         "subtree_solves_per_s": args.steps / el,
         "best_correct": res["correct"],
         "roofline": roof,

@@ -49,6 +49,7 @@ struct Ctx {
   uint32_t fit_min_tiles = 1;
   bool fuse_de = false;  // fitness and DE step in one launch per generation (MHDEOCT_FUSE_DE=1)
   bool persist = true;   // whole DEOCT runs as one cooperative launch (MHDEOCT_PERSIST=0 turns off)
+  uint32_t persist_blocks_per_cu = 0;  // its blocks per CU; 0 = by size (MHDEOCT_PERSIST_BLOCKS_PER_CU)
   bool coop = false;     // the device supports cooperative launches
 };
 

@@ -328,15 +328,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   }
 }
 
+// Blocks per CU: the per-generation exchange (count atomics, barrier, count
+// reads) grows with the block count, the tile work shrinks with it.  Measured
+// at depth 3 (F = 16, P = 128 and 256, n = 5e4 .. 4e6): about 4 waves per CU
+// while a CU has up to 8 tiles, then 4 more waves per further 8 tiles, up to
+// 16 waves.
+uint32_t persist_bpc(uint32_t max_tiles, uint32_t num_cu, uint32_t waves) {
+  const uint32_t per_cu = (max_tiles + num_cu - 1) / num_cu;
+  uint32_t target = 4u * ((per_cu + 7u) / 8u);
+  target = target < 4u ? 4u : (target > 16u ? 16u : target);
+  const uint32_t bpc = target / waves;
+  return bpc ? bpc : 1u;
+}
+
 template <int D, int WAVES>
-mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, bool *used) {
+mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles, bool *used) {
   auto kern = k_deoct_persist<D, WAVES>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, lds) != hipSuccess ||
       per_cu < 1)
     return MH_OK;  // not co-resident: the caller takes the per-generation kernels
-  uint32_t bpc = (uint32_t)per_cu < ctx->fit_blocks_per_cu ? (uint32_t)per_cu
-                                                            : ctx->fit_blocks_per_cu;
+  uint32_t bpc = ctx->persist_blocks_per_cu
+                     ? ctx->persist_blocks_per_cu
+                     : persist_bpc(max_tiles, (uint32_t)ctx->num_cu, WAVES);
+  bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
   bpc = bpc > 8u ? 8u : bpc;
   const uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
   PersistArgs a = pa;
@@ -349,12 +364,13 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, bool *used) {
 }
 
 template <int D>
-mh_status launch_d(Ctx *ctx, uint32_t waves, const PersistArgs &pa, uint32_t lds, bool *used) {
+mh_status launch_d(Ctx *ctx, uint32_t waves, const PersistArgs &pa, uint32_t lds,
+                   uint32_t max_tiles, bool *used) {
   switch (waves) {
-    case 1: return launch_w<D, 1>(ctx, pa, lds, used);
-    case 2: return launch_w<D, 2>(ctx, pa, lds, used);
-    case 4: return launch_w<D, 4>(ctx, pa, lds, used);
-    default: return launch_w<D, 8>(ctx, pa, lds, used);
+    case 1: return launch_w<D, 1>(ctx, pa, lds, max_tiles, used);
+    case 2: return launch_w<D, 2>(ctx, pa, lds, max_tiles, used);
+    case 4: return launch_w<D, 4>(ctx, pa, lds, max_tiles, used);
+    default: return launch_w<D, 8>(ctx, pa, lds, max_tiles, used);
   }
 }
 
@@ -405,12 +421,13 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   const bool timed = prof_pair(ctx, &e0, &e1);
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));
   mh_status s = MH_OK;
+  const uint32_t max_tiles = tile_layout(n_sub, F, K, 1).max_tiles;
   switch (D) {
-    case 1: s = launch_d<1>(ctx, waves, pa, lds, used); break;
-    case 2: s = launch_d<2>(ctx, waves, pa, lds, used); break;
-    case 3: s = launch_d<3>(ctx, waves, pa, lds, used); break;
-    case 4: s = launch_d<4>(ctx, waves, pa, lds, used); break;
-    default: s = launch_d<5>(ctx, waves, pa, lds, used); break;
+    case 1: s = launch_d<1>(ctx, waves, pa, lds, max_tiles, used); break;
+    case 2: s = launch_d<2>(ctx, waves, pa, lds, max_tiles, used); break;
+    case 3: s = launch_d<3>(ctx, waves, pa, lds, max_tiles, used); break;
+    case 4: s = launch_d<4>(ctx, waves, pa, lds, max_tiles, used); break;
+    default: s = launch_d<5>(ctx, waves, pa, lds, max_tiles, used); break;
   }
   if (s) return s;
   if (timed) {
