@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <type_traits>
 
 #include "device_common.h"
 #include "epilogue.h"
@@ -64,24 +65,30 @@ __host__ __device__ __forceinline__ uint32_t barrier_words(uint32_t blocks) {
   return 128 + 64 * ((blocks + BAR_GROUP - 1) / BAR_GROUP);
 }
 
-// Barrier number k (0-based) of a launch with gridDim.x blocks.
-__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t k, uint32_t *err) {
+// Barrier number k (0-based) of a launch with gridDim.x blocks, in two parts
+// so that a block can do independent work between arriving and waiting.
+// Arrival: every wave's atomics are complete, then thread 0 arrives.
+__device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t k) {
   __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's atomics are done
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t grp = blockIdx.x / BAR_GROUP;
     const uint32_t gsize = min(BAR_GROUP, gridDim.x - grp * BAR_GROUP);
     const uint32_t ngroups = (gridDim.x + BAR_GROUP - 1) / BAR_GROUP;
-    uint32_t *top = bar, *rel = bar + 64;
     const uint32_t old = __hip_atomic_fetch_add(bar + 128 + 64 * grp, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
     if (old == (k + 1) * gsize - 1) {
-      const uint32_t o2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t o2 = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (o2 == (k + 1) * ngroups - 1)
-        __hip_atomic_store(rel, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bar + 64, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+}
+// Wait: thread 0 polls the release word, then the block proceeds together.
+__device__ __forceinline__ void barrier_wait(uint32_t *bar, uint32_t k, uint32_t *err) {
+  if (threadIdx.x == 0) {
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
+    while (__hip_atomic_load(bar + 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
           wall_clock64() - t0 > WAIT_LIMIT_TICKS) {
         __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -95,20 +102,72 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t k, uint32_t
 
 __host__ __device__ __forceinline__ uint32_t align16u(uint32_t x) { return (x + 15u) & ~15u; }
 
-// LDS: staged tile | rows [m][P] f64 | n_unique [F] | argmin scratch
-__host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint32_t P, uint32_t m) {
-  const uint32_t tile = align16u(mask_region(F) + F * MCOL);
-  return tile + align16u(m * P * 8) + align16u(F * 4) + 16 * 8 + 16 * 4;
+// (cost, index) of the wave's smallest cost, ties to the lower index: DPP
+// row shifts (1, 2, 4, 8) reduce each row of 16 lanes into its last lane,
+// two row broadcasts fold the four rows into lane 63, which is read back.
+// A lane with no source in a step sees the (largest cost, largest index)
+// sentinel, which never wins.
+__device__ __forceinline__ void wave_argmin(double &c, uint32_t &i) {
+  auto step = [&](auto ctrl_tag, auto mask_tag) {
+    constexpr int ctrl = decltype(ctrl_tag)::value, rmask = decltype(mask_tag)::value;
+    const uint32_t lo = (uint32_t)__double2loint(c), hi = (uint32_t)__double2hiint(c);
+    const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)lo, ctrl,
+                                                               rmask, 0xF, false);
+    const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp((int)0x7FEFFFFFu, (int)hi, ctrl,
+                                                               rmask, 0xF, false);
+    const uint32_t ni = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)i, ctrl,
+                                                              rmask, 0xF, false);
+    const double cn = __hiloint2double((int)nhi, (int)nlo);
+    const bool better = (cn < c) | ((cn == c) & (ni < i));
+    c = better ? cn : c;
+    i = better ? ni : i;
+  };
+  step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});  // row_shr:1
+  step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});  // row_shr:2
+  step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});  // row_shr:4
+  step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xF>{});  // row_shr:8
+  step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});  // row_bcast:15
+  step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(c), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(c), 63);
+  c = __hiloint2double(hi, lo);
+  i = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
 }
 
-template <int D, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
+// LDS: H staged tiles | rows [m][P] f64 | n_unique [F] | argmin scratch.
+// The trees' decoded nodes and the second half's left counts pass through
+// the first tile buffer while no tile is staged.
+__host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint32_t P, uint32_t m,
+                                                              uint32_t H) {
+  const uint32_t tile = align16u(mask_region(F) + F * MCOL);
+  return H * tile + align16u(m * P * 8) + align16u(F * 4) + 32 * 8 + 32 * 4;
+}
+// Bytes of the first tile buffer the exchanges need: decoded nodes (feature
+// byte and threshold per node and tree), or the second half's class and
+// counts per tree.
+__host__ __device__ __forceinline__ uint32_t persist_exchange_bytes(uint32_t SB, uint32_t P) {
+  const uint32_t nodes = align16u(SB * P) + SB * P * 4;
+  const uint32_t counts = P * 4 + SB * P * 4;
+  return nodes > counts ? nodes : counts;
+}
+
+// Two-wave-group layout (H = 2): the block holds two copies of the
+// population's lanes; half h (threads h * NTH ..) counts every other tile
+// of the block's range in its own staging buffer, so two tiles are in flight
+// per block, and in the DE phase half h makes the genes of its share of the
+// nodes (half 0 the first (SB + 1) / 2 nodes, half 1 the rest).  Decoded
+// nodes are exchanged through LDS so that both halves evaluate whole trees.
+template <int D, int WAVES, int H>
+__global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   constexpr int SB = (1 << D) - 1, SL = 1 << D, m = 2 * SB;
-  constexpr uint32_t NT = WAVES * 64;
+  constexpr uint32_t NTH = WAVES * 64, NT = H * NTH;
+  constexpr int NA = H == 1 ? SB : (SB + 1) / 2;  // nodes of half 0
   extern __shared__ __align__(16) uint8_t lds[];
-  const uint32_t P = pa.P, Ppad = pad64(P), K = pa.K, F = pa.F, r = threadIdx.x;
+  const uint32_t P = pa.P, Ppad = pad64(P), K = pa.K, F = pa.F;
+  const uint32_t h = threadIdx.x / NTH, r = threadIdx.x % NTH;
   const bool live = r < P;
   const uint32_t rr = live ? r : 0u;
+  const int n_lo = h == 0 ? 0 : NA, n_hi = h == 0 ? NA : SB;  // this half's nodes
 
   const uint8_t *base = reinterpret_cast<const uint8_t *>(pa.hdr);
   const uint32_t n_tiles = pa.hdr->n_tiles;
@@ -119,34 +178,55 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   const uint32_t nchunk = 48u * F;
   const uint32_t t_begin = (uint32_t)((uint64_t)n_tiles * blockIdx.x / gridDim.x);
   const uint32_t t_end = (uint32_t)((uint64_t)n_tiles * (blockIdx.x + 1) / gridDim.x);
+  const uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
 
   const uint32_t mregion = mask_region(F);
   const uint32_t tile_lds = align16u(mregion + F * MCOL);
-  double *rows = reinterpret_cast<double *>(lds + tile_lds);
-  uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + tile_lds + align16u(m * P * 8));
+  uint8_t *my_tile = lds + h * tile_lds;
+  double *rows = reinterpret_cast<double *>(lds + H * tile_lds);
+  uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + H * tile_lds + align16u(m * P * 8));
   double *s_cost = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(s_nu) + align16u(F * 4));
-  uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_cost + 16);
-  const uint32_t s0 = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds);
+  uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_cost + 32);
+  // exchanges in the first tile buffer
+  uint8_t *x_feat = lds;                                              // [SB][P]
+  uint32_t *x_thr = reinterpret_cast<uint32_t *>(lds + align16u(SB * P));  // [SB][P]
+  uint32_t *x_cls = reinterpret_cast<uint32_t *>(lds);                // [P]
+  uint32_t *x_acc = reinterpret_cast<uint32_t *>(lds + P * 4);         // [SB][P]
+  const uint32_t s0 =
+      (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds) + h * tile_lds;
   const uint32_t kmask = s0 + mregion - 2u * s0;
 
   for (uint32_t f = threadIdx.x; f < F; f += NT) s_nu[f] = pa.n_unique[f];
   double gp[m], gt[m];
 #pragma unroll
-  for (int q = 0; q < m; ++q) gp[q] = pa.pop[(size_t)q * P + rr];
+  for (int q = 0; q < m; ++q) gt[q] = gp[q] = pa.pop[(size_t)q * P + rr];
   __syncthreads();
 
   NodeState<D> ns;
   uint32_t nsplit = 0;
+  // decode this half's nodes of `gen`, publish them, then take the whole tree
+  // (callers: every thread; contains barriers)
   auto set_tree = [&](const double (&gen)[m]) {
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      if (t >= n_lo && t < n_hi && live) {
+        uint32_t f = 0, th = 0;
+        decode_node(gen[t], gen[SB + t], F, s_nu, f, th);
+        x_feat[t * P + r] = (uint8_t)f;
+        x_thr[t * P + r] = th;
+      }
+    }
+    __syncthreads();
     nsplit = 0;
 #pragma unroll
     for (int t = 0; t < SB; ++t) {
-      uint32_t f = 0, th = 0;
-      if (live) decode_node(gen[t], gen[SB + t], F, s_nu, f, th);
+      const uint32_t f = live ? x_feat[t * P + r] : 0u;
+      const uint32_t th = live ? x_thr[t * P + r] : 0u;
       ns.col[t] = s0 + (f ? f - 1u : 0u) * SCOL;
       ns.thr[t] = f ? th : 0u;
       nsplit += f != 0;
     }
+    __syncthreads();  // the exchange area is a tile buffer again
   };
   set_tree(gp);
 
@@ -158,11 +238,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
     const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-      const uint32_t c = threadIdx.x + k * NT;
+      const uint32_t c = r + k * NTH;
       if (c < nchunk) pf[k] = src[c];
     }
   };
-  if (t_begin < t_end) prefetch(t_begin);
+  if (t_begin + h < t_end) prefetch(t_begin + h);
 
   for (uint32_t g = 0; g <= pa.G; ++g) {
     uint32_t *cnt = pa.cnt + (size_t)(g % 3) * cstride;
@@ -172,12 +252,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
         __hip_atomic_store(z + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    // ---- counts of this block's tiles
+    // ---- counts of this block's tiles (half h: tiles t_begin + h, + H, ...)
 #pragma unroll
     for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
     uint32_t cur_cls = 0xFFFFFFFFu;
     auto flush = [&]() {
-      if (!live) return;
+      if (!live || cur_cls == 0xFFFFFFFFu) return;
       uint32_t *c = cnt + (size_t)cur_cls * Ppad + r;
 #pragma unroll
       for (int t = 0; t < SB; ++t) {
@@ -185,55 +265,144 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
         ns.acc[t] = 0;
       }
     };
-    for (uint32_t tile = t_begin; tile < t_end; ++tile) {
-      const uint32_t inf = info[tile];
-      const uint32_t cls = (inf >> 8) & 0xFFu, count = inf & 0xFFu;
-      if (cls != cur_cls) {
-        if (cur_cls != 0xFFFFFFFFu) flush();
-        cur_cls = cls;
+    for (uint32_t i = 0; i < rounds; ++i) {
+      const uint32_t tile = t_begin + i * H + h;
+      const bool act = tile < t_end;
+      uint32_t count = 0;
+      if (act) {
+        const uint32_t inf = info[tile];
+        const uint32_t cls = (inf >> 8) & 0xFFu;
+        count = inf & 0xFFu;
+        if (cls != cur_cls) {
+          flush();
+          cur_cls = cls;
+        }
       }
-      __syncthreads();  // the previous tile is no longer read
+      __syncthreads();  // the previous tiles are no longer read
+      if (act) {
 #pragma unroll
-      for (int k = 0; k < PF; ++k) {
-        const uint32_t c = threadIdx.x + k * NT;
-        if (c < nchunk) stage_chunk(lds, mregion, F, c, pf[k]);
-      }
-      if (nchunk > PF * NT) {
-        const uint4 *__restrict__ src =
-            reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
-        for (uint32_t c = threadIdx.x + PF * NT; c < nchunk; c += NT)
-          stage_chunk(lds, mregion, F, c, src[c]);
+        for (int k = 0; k < PF; ++k) {
+          const uint32_t c = r + k * NTH;
+          if (c < nchunk) stage_chunk(my_tile, mregion, F, c, pf[k]);
+        }
+        if (nchunk > PF * NTH) {
+          const uint4 *__restrict__ src =
+              reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+          for (uint32_t c = r + PF * NTH; c < nchunk; c += NTH)
+            stage_chunk(my_tile, mregion, F, c, src[c]);
+        }
       }
       __syncthreads();
-      // the next tile, or this block's first tile again for the next
-      // generation (the layout does not change)
-      prefetch(tile + 1 < t_end ? tile + 1 : t_begin);
-      uint64_t R[1 << D];
-      R[1] = (1ull << count) - 1ull;  // count <= 63
-      eval_nodes<D, 1>(kmask, ns, R);
+      if (act) {
+        // the next tile, or this half's first tile again for the next
+        // generation (the layout does not change)
+        prefetch(tile + H < t_end ? tile + H : t_begin + h);
+        uint64_t R[1 << D];
+        R[1] = (1ull << count) - 1ull;  // count <= 63
+        eval_nodes<D, 1>(kmask, ns, R);
+      }
     }
-    if (cur_cls != 0xFFFFFFFFu) flush();
-    grid_barrier(pa.bar, g, pa.err);
+    if constexpr (H == 2) {
+      // merge the second half's open counts into the first half's when both
+      // end on the same class (the usual case: tiles are grouped by class)
+      __syncthreads();
+      if (h == 1 && live) {
+        x_cls[r] = cur_cls;
+#pragma unroll
+        for (int t = 0; t < SB; ++t) x_acc[t * P + r] = ns.acc[t];
+      }
+      __syncthreads();
+      if (h == 0 && live) {
+        const uint32_t c1 = x_cls[r];
+        if (c1 == cur_cls || cur_cls == 0xFFFFFFFFu) {
+          cur_cls = c1;
+#pragma unroll
+          for (int t = 0; t < SB; ++t) ns.acc[t] += x_acc[t * P + r];
+        } else {
+          flush();
+          cur_cls = c1;
+#pragma unroll
+          for (int t = 0; t < SB; ++t) ns.acc[t] = x_acc[t * P + r];
+        }
+      }
+      if (h == 1) {
+#pragma unroll
+        for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
+        cur_cls = 0xFFFFFFFFu;
+      }
+    }
+    flush();
+    barrier_arrive(pa.bar, g);
 
-    // ---- epilogue (eq. opt_all and the soft-constraint fitness)
+    // ---- the random draws of generation g + 1 (they depend only on the
+    // seed, the generation, the individual and the slot), made while the
+    // other blocks finish: M_r, r1, r2, q_rand, and one crossover decision
+    // per gene of this half's nodes
+    const uint32_t gg = g + 1;
+    double Mr = pa.M;
+    uint32_t r1 = 0, r2 = 0, qr = 0;
+    uint64_t cross = 0;
+    if (live && g < pa.G) {
+      // draw (gg, r, slot) is SplitMix64 output (base counter + slot)
+      const uint64_t cbase =
+          key + ((((uint64_t)gg << 40) | ((uint64_t)r << 20)) + 1ull) * 0x9E3779B97F4A7C15ull;
+      auto draw = [&](uint32_t slot) {
+        return sm64_fmix(cbase + (uint64_t)slot * 0x9E3779B97F4A7C15ull);
+      };
+      if (pa.M < 0.0) Mr = to_unit(draw(0));
+      r1 = to_below(draw(1), P - 1u);
+      r1 += (r1 >= r) ? 1u : 0u;
+      r2 = to_below(draw(2), P - 2u);
+      const uint32_t lo = r < r1 ? r : r1, hi = r < r1 ? r1 : r;
+      r2 += (r2 >= lo) ? 1u : 0u;
+      r2 += (r2 >= hi) ? 1u : 0u;
+      qr = to_below(draw(3), m);
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        if (t < n_lo || t >= n_hi) continue;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int q = t + (hh ? SB : 0);
+          const double u = to_unit(draw(4u + q));
+          if (u <= pa.CR || (uint32_t)q == qr) cross |= 1ull << q;
+        }
+      }
+    }
+    barrier_wait(pa.bar, g, pa.err);
+
+    // ---- epilogue (eq. opt_all and the soft-constraint fitness); the counts
+    // of up to KB classes are loaded together
+    constexpr uint32_t KB = SB <= 7 ? 4u : (SB <= 15 ? 2u : 1u);
     uint32_t nl[SL], bl[SL], n_sub = 0;
 #pragma unroll
     for (int l = 0; l < SL; ++l) nl[l] = bl[l] = 0;
-    for (uint32_t k = 0; k < K; ++k) {
-      uint32_t reach[2 * SL];
-      reach[1] = ctot[k];
-      n_sub += reach[1];
+    for (uint32_t k0 = 0; k0 < K; k0 += KB) {
+      uint32_t left[KB][SB], tot[KB];
 #pragma unroll
-      for (int t = 1; t <= SB; ++t) {
-        const uint32_t left = cnt_load<true>(cnt + ((size_t)(t - 1) * K + k) * Ppad + rr);
-        reach[2 * t] = left;
-        reach[2 * t + 1] = reach[t] - left;
+      for (uint32_t kk = 0; kk < KB; ++kk) {
+        const uint32_t k = k0 + kk < K ? k0 + kk : K - 1u;
+        tot[kk] = ctot[k];
+#pragma unroll
+        for (int t = 0; t < SB; ++t)
+          left[kk][t] = cnt_load<true>(cnt + ((size_t)t * K + k) * Ppad + rr);
       }
 #pragma unroll
-      for (int l = 0; l < SL; ++l) {
-        const uint32_t v = reach[SL + l];
-        nl[l] += v;
-        bl[l] = v > bl[l] ? v : bl[l];
+      for (uint32_t kk = 0; kk < KB; ++kk) {
+        if (k0 + kk >= K) continue;
+        uint32_t reach[2 * SL];
+        reach[1] = tot[kk];
+        n_sub += reach[1];
+#pragma unroll
+        for (int t = 1; t <= SB; ++t) {
+          reach[2 * t] = left[kk][t - 1];
+          reach[2 * t + 1] = reach[t] - left[kk][t - 1];
+        }
+#pragma unroll
+        for (int l = 0; l < SL; ++l) {
+          const uint32_t v = reach[SL + l];
+          nl[l] += v;
+          bl[l] = v > bl[l] ? v : bl[l];
+        }
       }
     }
     uint32_t correct = 0, nviol = 0;
@@ -256,21 +425,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
     }
     if (live) {
 #pragma unroll
-      for (int q = 0; q < m; ++q) rows[(size_t)q * P + r] = gp[q];
+      for (int t = 0; t < SB; ++t)
+        if (t >= n_lo && t < n_hi) {
+          rows[(size_t)t * P + r] = gp[t];
+          rows[(size_t)(SB + t) * P + r] = gp[SB + t];
+        }
     }
 
-    // ---- best: lowest index of the minimum cost
+    // ---- best: lowest index of the minimum cost (both halves hold every
+    // individual's cost; duplicates do not change the result)
     double bc = live ? cost_r : DBL_MAX;
     uint32_t bi = r;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double c2 = __shfl_xor(bc, o, 64);
-      const uint32_t i2 = __shfl_xor(bi, o, 64);
-      if (c2 < bc || (c2 == bc && i2 < bi)) {
-        bc = c2;
-        bi = i2;
-      }
-    }
+    wave_argmin(bc, bi);
     if ((threadIdx.x & 63u) == 0) {
       s_cost[threadIdx.x >> 6] = bc;
       s_idx[threadIdx.x >> 6] = bi;
@@ -279,52 +445,48 @@ __global__ __launch_bounds__(WAVES * 64) void k_deoct_persist(PersistArgs pa) {
     bc = s_cost[0];
     bi = s_idx[0];
 #pragma unroll
-    for (uint32_t x = 1; x < WAVES; ++x) {
+    for (uint32_t x = 1; x < NT / 64; ++x) {
       const double c2 = s_cost[x];
       const uint32_t i2 = s_idx[x];
-      if (c2 < bc || (c2 == bc && i2 < bi)) {
-        bc = c2;
-        bi = i2;
-      }
+      const bool better = (c2 < bc) | ((c2 == bc) & (i2 < bi));
+      bc = better ? c2 : bc;
+      bi = better ? i2 : bi;
     }
     const uint32_t bst = bi;
     if (g == pa.G) {
-      if (blockIdx.x == 0) {
-        if (live) {
+      if (blockIdx.x == 0 && live) {
 #pragma unroll
-          for (int q = 0; q < m; ++q) pa.pop[(size_t)q * P + r] = gp[q];
-          pa.cost[r] = cost_r;
-        }
-        if (threadIdx.x == 0) pa.best[0] = bst;
+        for (int t = 0; t < SB; ++t)
+          if (t >= n_lo && t < n_hi) {
+            pa.pop[(size_t)t * P + r] = gp[t];
+            pa.pop[(size_t)(SB + t) * P + r] = gp[SB + t];
+          }
+        if (h == 0) pa.cost[r] = cost_r;
       }
+      if (blockIdx.x == 0 && threadIdx.x == 0) pa.best[0] = bst;
       break;
     }
 
-    // ---- DE/best/1 mutation and binomial crossover of generation g + 1
+    // ---- DE/best/1 mutation and binomial crossover of generation g + 1,
+    // this half's nodes (the feature gene t and the threshold gene SB + t)
     if (live) {
-      const uint32_t gg = g + 1;
-      const double Mr = pa.M >= 0.0 ? pa.M : to_unit(de_draw(key, gg, r, 0));
-      uint32_t r1 = to_below(de_draw(key, gg, r, 1), P - 1u);
-      r1 += (r1 >= r) ? 1u : 0u;
-      uint32_t r2 = to_below(de_draw(key, gg, r, 2), P - 2u);
-      const uint32_t lo = r < r1 ? r : r1, hi = r < r1 ? r1 : r;
-      r2 += (r2 >= lo) ? 1u : 0u;
-      r2 += (r2 >= hi) ? 1u : 0u;
-      const uint32_t qr = to_below(de_draw(key, gg, r, 3), m);
       const double Fp1 = (double)F + 1.0;
 #pragma unroll
-      for (int q = 0; q < m; ++q) {
-        const double d = __dsub_rn(rows[(size_t)q * P + r1], rows[(size_t)q * P + r2]);
-        double v = __dadd_rn(rows[(size_t)q * P + bst], __dmul_rn(Mr, d));
-        const double hiq = q >= SB ? 1.0 : Fp1;
-        if (!(v >= 0.0)) v = 0.0;
-        if (v > hiq) v = hiq;
-        const double u = to_unit(de_draw(key, gg, r, 4u + q));
-        gt[q] = (u <= pa.CR || (uint32_t)q == qr) ? v : gp[q];
+      for (int t = 0; t < SB; ++t) {
+        if (t < n_lo || t >= n_hi) continue;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int q = t + (hh ? SB : 0);
+          const double d = __dsub_rn(rows[(size_t)q * P + r1], rows[(size_t)q * P + r2]);
+          double v = __dadd_rn(rows[(size_t)q * P + bst], __dmul_rn(Mr, d));
+          const double hiq = hh ? 1.0 : Fp1;
+          if (!(v >= 0.0)) v = 0.0;
+          if (v > hiq) v = hiq;
+          gt[q] = ((cross >> q) & 1ull) ? v : gp[q];
+        }
       }
     }
     set_tree(gt);
-    __syncthreads();  // rows and the argmin scratch are rewritten next generation
   }
 }
 
@@ -341,37 +503,45 @@ uint32_t persist_bpc(uint32_t max_tiles, uint32_t num_cu, uint32_t waves) {
   return bpc ? bpc : 1u;
 }
 
-template <int D, int WAVES>
+template <int D, int WAVES, int H>
 mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles, bool *used) {
-  auto kern = k_deoct_persist<D, WAVES>;
+  auto kern = k_deoct_persist<D, WAVES, H>;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, lds) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, H * WAVES * 64, lds) !=
+          hipSuccess ||
       per_cu < 1)
     return MH_OK;  // not co-resident: the caller takes the per-generation kernels
   uint32_t bpc = ctx->persist_blocks_per_cu
                      ? ctx->persist_blocks_per_cu
-                     : persist_bpc(max_tiles, (uint32_t)ctx->num_cu, WAVES);
+                     : persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
   bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
   bpc = bpc > 8u ? 8u : bpc;
   const uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
   PersistArgs a = pa;
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
-                                            dim3(WAVES * 64), args, lds, ctx->stream);
+                                            dim3(H * WAVES * 64), args, lds, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "k_deoct_persist");
   *used = true;
   return MH_OK;
 }
 
-template <int D>
+template <int D, int H>
 mh_status launch_d(Ctx *ctx, uint32_t waves, const PersistArgs &pa, uint32_t lds,
                    uint32_t max_tiles, bool *used) {
   switch (waves) {
-    case 1: return launch_w<D, 1>(ctx, pa, lds, max_tiles, used);
-    case 2: return launch_w<D, 2>(ctx, pa, lds, max_tiles, used);
-    case 4: return launch_w<D, 4>(ctx, pa, lds, max_tiles, used);
-    default: return launch_w<D, 8>(ctx, pa, lds, max_tiles, used);
+    case 1: return launch_w<D, 1, H>(ctx, pa, lds, max_tiles, used);
+    case 2: return launch_w<D, 2, H>(ctx, pa, lds, max_tiles, used);
+    case 4: return launch_w<D, 4, H>(ctx, pa, lds, max_tiles, used);
+    default: return launch_w<D, (H == 2 ? 4 : 8), H>(ctx, pa, lds, max_tiles, used);
   }
+}
+
+template <int D>
+mh_status launch_dh(Ctx *ctx, uint32_t waves, uint32_t H, const PersistArgs &pa, uint32_t lds,
+                    uint32_t max_tiles, bool *used) {
+  return H == 2 ? launch_d<D, 2>(ctx, waves, pa, lds, max_tiles, used)
+                : launch_d<D, 1>(ctx, waves, pa, lds, max_tiles, used);
 }
 
 }  // namespace
@@ -385,10 +555,18 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   if (!ctx->coop || D < 1 || D > 5 || P > 512 || F > 80) return MH_OK;
   // barrier targets (G + 1) * blocks must fit the 32-bit arrival counters
   if ((uint64_t)(prm->G + 1) * (uint64_t)ctx->num_cu * 8u >= (1ull << 31)) return MH_OK;
-  const uint32_t lds = persist_lds_bytes(F, P, m);
-  if (lds > 64u * 1024u) return MH_OK;
   uint32_t waves = pad64(P) / 64;
   waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
+  // two tile streams per block when the LDS and the 1024-thread limit allow
+  const uint32_t tile_lds = align16u(mask_region(F) + F * MCOL);
+  uint32_t H = (ctx->persist_halves != 1 && waves <= 4 &&
+                persist_lds_bytes(F, P, m, 2) <= 64u * 1024u &&
+                persist_exchange_bytes(SB, P) <= tile_lds)
+                   ? 2u
+                   : 1u;
+  if (H == 1 && persist_exchange_bytes(SB, P) > tile_lds) return MH_OK;
+  const uint32_t lds = persist_lds_bytes(F, P, m, H);
+  if (lds > 64u * 1024u) return MH_OK;
   const size_t cstride = (size_t)SB * K * pad64(P);
   uint32_t *cnt = (uint32_t *)arena_get(ctx, "ps_cnt", 3 * cstride * 4);
   const size_t bar_bytes = (size_t)barrier_words((uint32_t)ctx->num_cu * 8u) * 4;
@@ -423,11 +601,11 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   mh_status s = MH_OK;
   const uint32_t max_tiles = tile_layout(n_sub, F, K, 1).max_tiles;
   switch (D) {
-    case 1: s = launch_d<1>(ctx, waves, pa, lds, max_tiles, used); break;
-    case 2: s = launch_d<2>(ctx, waves, pa, lds, max_tiles, used); break;
-    case 3: s = launch_d<3>(ctx, waves, pa, lds, max_tiles, used); break;
-    case 4: s = launch_d<4>(ctx, waves, pa, lds, max_tiles, used); break;
-    default: s = launch_d<5>(ctx, waves, pa, lds, max_tiles, used); break;
+    case 1: s = launch_dh<1>(ctx, waves, H, pa, lds, max_tiles, used); break;
+    case 2: s = launch_dh<2>(ctx, waves, H, pa, lds, max_tiles, used); break;
+    case 3: s = launch_dh<3>(ctx, waves, H, pa, lds, max_tiles, used); break;
+    case 4: s = launch_dh<4>(ctx, waves, H, pa, lds, max_tiles, used); break;
+    default: s = launch_dh<5>(ctx, waves, H, pa, lds, max_tiles, used); break;
   }
   if (s) return s;
   if (timed) {
