@@ -283,3 +283,16 @@ def test_persistent_and_per_generation_deoct_agree(mh, monkeypatch, D, P, K, M):
     ctx_gen.close()
     ctx_per.close()
 
+
+@pytest.mark.parametrize("D,P,K,n", [(1, 3, 2, 1), (2, 3, 20, 500), (3, 65, 9, 0), (2, 200, 3, 64),
+                                     (4, 256, 2, 6300), (3, 129, 255, 3000)])
+def test_persistent_deoct_edge_shapes(mh, D, P, K, n):
+    """Smallest population, many classes, empty and single-sample data, ragged
+    populations: the whole-run kernel agrees with the oracle."""
+    X, y = synth.random_small(70 + D + n, n, 5, K)
+    ds = mh.dataset(X, y, K)
+    got = mh.subtree_solve(ds, D, mh.de_params(P, 7, 0.5, 0.9, 11), prob=1)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 7, 0.5, 0.9, 11),
+                        prob=1)
+    _same_tree(want, got)
+
