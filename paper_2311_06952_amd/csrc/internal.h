@@ -274,6 +274,19 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
                                const uint32_t *n_unique, double *pop, double *cost,
                                uint32_t *best, uint32_t *err, bool *used);
 
+// The same for the n_problems problems of a multi-problem tile set: each
+// problem gets its own group of blocks (in proportion to its tiles), its own
+// counters and barrier, and its DE state at problem stride in pop ([m][P]
+// per problem), cost ([P] per problem) and best ([n_problems]).
+// class_counts: HOST [n_problems][K] samples per class (as in the layout);
+// prob_ids: device [n_problems].
+mh_status launch_deoct_persist_multi(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                                     uint32_t n_sub, uint32_t n_problems,
+                                     const uint32_t *class_counts, uint32_t D,
+                                     const mh_de_params *prm, const uint64_t *prob_ids,
+                                     const uint32_t *n_unique, double *pop, double *cost,
+                                     uint32_t *best, uint32_t *err, bool *used);
+
 // mh.hip
 // Exact best depth-1 split (Algorithm 2, horizon-1 branch) of every subset
 // {i : sub_of[i] == s}, s < nsub (samples with sub_of >= nsub are ignored;
@@ -285,9 +298,12 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
 // samples assigned by sub_of (device [n], >= n_problems = not in any).
 // Writes the decoded best tree of each problem to feat_out/tau_out (device,
 // [n_problems][SB]) and its cost to cost_out (device [n_problems]).
+// class_counts (HOST [n_problems][K], may be null) lets the whole run go to
+// one cooperative launch.
 mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
                         uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
-                        const mh_de_params *prm, uint8_t *feat_out, uint32_t *tau_out);
+                        const mh_de_params *prm, const uint32_t *class_counts,
+                        uint8_t *feat_out, uint32_t *tau_out);
 
 // Sequential-form helpers: the samples at node t (device idx, atomics
 // order), the exact split of an explicit subset (host outputs), and the

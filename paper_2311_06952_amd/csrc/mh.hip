@@ -355,7 +355,8 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
 // one fused epilogue + DE step (a block per problem) per generation.
 mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
                         uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
-                        const mh_de_params *prm, uint8_t *feat_out, uint32_t *tau_out) {
+                        const mh_de_params *prm, const uint32_t *class_counts,
+                        uint8_t *feat_out, uint32_t *tau_out) {
   const uint32_t P = prm->P, SB = (1u << D) - 1u, m = 2 * SB, K = ds->K, F = ds->F;
   if (D > 5 || F > 80) return fail(ctx, MH_EINVAL, "batched DEOCT needs depth <= 5 and F <= 80");
   hipStream_t st = ctx->stream;
@@ -378,6 +379,25 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
   DeDev de{P, D, F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
   s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop, true);
   if (s) return s;
+  if (class_counts && ctx->persist) {
+    // every problem's whole run in one cooperative launch (a block group
+    // per problem)
+    uint32_t *err = (uint32_t *)arena_get(ctx, "mb_err", 256);
+    if (!err) return MH_ENOMEM;
+    bool used = false;
+    s = launch_deoct_persist_multi(ctx, tiles, F, K, ds->n, n_problems, class_counts, D, prm,
+                                   prob_ids, ds->n_unique, pop, cost, best, err, &used);
+    if (s) return s;
+    if (used) {
+      s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat_out, tau_out, n_problems, best, true);
+      if (s) return s;
+      uint32_t h_err = 0;
+      MH_HIP(ctx, hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st));
+      MH_HIP(ctx, hipStreamSynchronize(st));
+      if (h_err) return fail(ctx, MH_EDEVICE, "batched DEOCT grid barrier: a wait gave up");
+      return MH_OK;
+    }
+  }
   s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat, tau, n_problems, nullptr, true);
   if (s) return s;
   const bool fuse = ctx->fuse_de && fusable(P, D, F);
@@ -495,7 +515,10 @@ mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_M
         mh_status s = launch_split1(ctx, ds, sub_of, na, hist, rf, rt, scorr);
         if (s) return s;
       } else if (batched) {
-        mh_status s = deoct_batched(ctx, ds, sub_of, na, pids, De, prm, rf, rt);
+        std::vector<uint32_t> cc((size_t)na * K);
+        for (uint32_t a = 0; a < na; ++a)
+          for (uint32_t k = 0; k < K; ++k) cc[(size_t)a * K + k] = hh[(size_t)(active[a] - t0) * K + k];
+        mh_status s = deoct_batched(ctx, ds, sub_of, na, pids, De, prm, cc.data(), rf, rt);
         if (s) return s;
       } else {
         std::vector<uint8_t> hf(na);

@@ -27,6 +27,7 @@
 
 #include <cfloat>
 #include <type_traits>
+#include <vector>
 
 #include "device_common.h"
 #include "epilogue.h"
@@ -48,6 +49,13 @@ struct PersistArgs {
   double M, CR, alpha;
   uint64_t seed, prob;
   uint32_t P, G, n_min, F, K;
+  // several problems of one multi-problem tile set (null for one problem):
+  // problem of each block, and per problem {first tile, end tile, first
+  // block, blocks}; pop, cost, best, cnt and bar hold one area per problem
+  const uint16_t *prob_of_block;
+  const uint4 *ranges;
+  const uint64_t *prob_ids;  // [problems]
+  uint32_t bar_stride;       // barrier words per problem
 };
 
 // A barrier wait gives up after this many ticks of the device wall clock
@@ -65,16 +73,17 @@ __host__ __device__ __forceinline__ uint32_t barrier_words(uint32_t blocks) {
   return 128 + 64 * ((blocks + BAR_GROUP - 1) / BAR_GROUP);
 }
 
-// Barrier number k (0-based) of a launch with gridDim.x blocks, in two parts
+// Barrier number k (0-based) among the nb blocks of a problem (block b of
+// them), in two parts
 // so that a block can do independent work between arriving and waiting.
 // Arrival: every wave's atomics are complete, then thread 0 arrives.
-__device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t k) {
+__device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t k, uint32_t b, uint32_t nb) {
   __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's atomics are done
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t grp = blockIdx.x / BAR_GROUP;
-    const uint32_t gsize = min(BAR_GROUP, gridDim.x - grp * BAR_GROUP);
-    const uint32_t ngroups = (gridDim.x + BAR_GROUP - 1) / BAR_GROUP;
+    const uint32_t grp = b / BAR_GROUP;
+    const uint32_t gsize = min(BAR_GROUP, nb - grp * BAR_GROUP);
+    const uint32_t ngroups = (nb + BAR_GROUP - 1) / BAR_GROUP;
     const uint32_t old = __hip_atomic_fetch_add(bar + 128 + 64 * grp, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
     if (old == (k + 1) * gsize - 1) {
@@ -170,14 +179,24 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   const int n_lo = h == 0 ? 0 : NA, n_hi = h == 0 ? NA : SB;  // this half's nodes
 
   const uint8_t *base = reinterpret_cast<const uint8_t *>(pa.hdr);
-  const uint32_t n_tiles = pa.hdr->n_tiles;
+  uint32_t s_prob = 0, b = blockIdx.x, nb = gridDim.x, T0 = 0, T1 = pa.hdr->n_tiles;
+  if (pa.prob_of_block) {
+    s_prob = pa.prob_of_block[blockIdx.x];
+    const uint4 rg = pa.ranges[s_prob];
+    // the ranges come from host-side counts; never past the built tiles
+    T0 = rg.x < T1 ? rg.x : T1;
+    T1 = rg.y < T1 ? rg.y : T1;
+    b = blockIdx.x - rg.z;
+    nb = rg.w;
+  }
   const uint32_t *__restrict__ info = reinterpret_cast<const uint32_t *>(base + pa.hdr->off_info);
   const uint8_t *__restrict__ data = base + pa.hdr->off_data;
-  const uint32_t *__restrict__ ctot = reinterpret_cast<const uint32_t *>(base + pa.hdr->off_ctot);
+  const uint32_t *__restrict__ ctot =
+      reinterpret_cast<const uint32_t *>(base + pa.hdr->off_ctot) + (size_t)s_prob * pa.K;
   const size_t rec_bytes = tile_bytes(F);
   const uint32_t nchunk = 48u * F;
-  const uint32_t t_begin = (uint32_t)((uint64_t)n_tiles * blockIdx.x / gridDim.x);
-  const uint32_t t_end = (uint32_t)((uint64_t)n_tiles * (blockIdx.x + 1) / gridDim.x);
+  const uint32_t t_begin = T0 + (uint32_t)((uint64_t)(T1 - T0) * b / nb);
+  const uint32_t t_end = T0 + (uint32_t)((uint64_t)(T1 - T0) * (b + 1) / nb);
   const uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
 
   const uint32_t mregion = mask_region(F);
@@ -198,8 +217,9 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 
   for (uint32_t f = threadIdx.x; f < F; f += NT) s_nu[f] = pa.n_unique[f];
   double gp[m], gt[m];
+  double *pop_s = pa.pop + (size_t)s_prob * P * m;
 #pragma unroll
-  for (int q = 0; q < m; ++q) gt[q] = gp[q] = pa.pop[(size_t)q * P + rr];
+  for (int q = 0; q < m; ++q) gt[q] = gp[q] = pop_s[(size_t)q * P + rr];
   __syncthreads();
 
   NodeState<D> ns;
@@ -231,7 +251,9 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   set_tree(gp);
 
   const size_t cstride = (size_t)SB * K * Ppad;
-  const uint64_t key = de_key(pa.seed, pa.prob);
+  const uint64_t key = de_key(pa.seed, pa.prob_ids ? pa.prob_ids[s_prob] : pa.prob);
+  uint32_t *cnt3 = pa.cnt + (size_t)s_prob * 3 * cstride;
+  uint32_t *bar = pa.bar + (size_t)s_prob * pa.bar_stride;
   double cost_r = 0.0;
   uint4 pf[PF];
   auto prefetch = [&](uint32_t tile) {
@@ -245,10 +267,10 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   if (t_begin + h < t_end) prefetch(t_begin + h);
 
   for (uint32_t g = 0; g <= pa.G; ++g) {
-    uint32_t *cnt = pa.cnt + (size_t)(g % 3) * cstride;
+    uint32_t *cnt = cnt3 + (size_t)(g % 3) * cstride;
     {
-      uint32_t *z = pa.cnt + (size_t)((g + 1) % 3) * cstride;
-      for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < cstride; i += (size_t)gridDim.x * NT)
+      uint32_t *z = cnt3 + (size_t)((g + 1) % 3) * cstride;
+      for (size_t i = (size_t)b * NT + threadIdx.x; i < cstride; i += (size_t)nb * NT)
         __hip_atomic_store(z + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
@@ -332,7 +354,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       }
     }
     flush();
-    barrier_arrive(pa.bar, g);
+    barrier_arrive(bar, g, b, nb);
 
     // ---- the random draws of generation g + 1 (they depend only on the
     // seed, the generation, the individual and the slot), made while the
@@ -368,7 +390,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         }
       }
     }
-    barrier_wait(pa.bar, g, pa.err);
+    barrier_wait(bar, g, pa.err);
 
     // ---- epilogue (eq. opt_all and the soft-constraint fitness); the counts
     // of up to KB classes are loaded together
@@ -454,16 +476,16 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     }
     const uint32_t bst = bi;
     if (g == pa.G) {
-      if (blockIdx.x == 0 && live) {
+      if (b == 0 && live) {
 #pragma unroll
         for (int t = 0; t < SB; ++t)
           if (t >= n_lo && t < n_hi) {
-            pa.pop[(size_t)t * P + r] = gp[t];
-            pa.pop[(size_t)(SB + t) * P + r] = gp[SB + t];
+            pop_s[(size_t)t * P + r] = gp[t];
+            pop_s[(size_t)(SB + t) * P + r] = gp[SB + t];
           }
-        if (h == 0) pa.cost[r] = cost_r;
+        if (h == 0) pa.cost[(size_t)s_prob * P + r] = cost_r;
       }
-      if (blockIdx.x == 0 && threadIdx.x == 0) pa.best[0] = bst;
+      if (b == 0 && threadIdx.x == 0) pa.best[s_prob] = bst;
       break;
     }
 
@@ -503,8 +525,17 @@ uint32_t persist_bpc(uint32_t max_tiles, uint32_t num_cu, uint32_t waves) {
   return bpc ? bpc : 1u;
 }
 
+// Problems of a multi-problem launch: tiles per problem (host) and the
+// device buffers for the block map and the per-problem ranges.
+struct Groups {
+  const std::vector<uint32_t> *tiles;  // null: one problem
+  uint16_t *prob_of_block;
+  uint4 *ranges;
+};
+
 template <int D, int WAVES, int H>
-mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles, bool *used) {
+mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles,
+                   const Groups &gr, bool *used) {
   auto kern = k_deoct_persist<D, WAVES, H>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, H * WAVES * 64, lds) !=
@@ -516,8 +547,36 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
                      : persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
   bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
   bpc = bpc > 8u ? 8u : bpc;
-  const uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
+  uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
   PersistArgs a = pa;
+  if (gr.tiles) {
+    // blocks in proportion to each problem's tiles, at least one each
+    const std::vector<uint32_t> &tl = *gr.tiles;
+    const uint32_t np = (uint32_t)tl.size();
+    uint64_t total = 0;
+    for (uint32_t t : tl) total += t;
+    std::vector<uint4> rg(np);
+    std::vector<uint16_t> pob;
+    uint32_t t0 = 0;
+    for (uint32_t i = 0; i < np; ++i) {
+      uint64_t nbk = total ? (uint64_t)grid * tl[i] / total : 1;
+      nbk = nbk < 1 ? 1 : nbk;
+      nbk = tl[i] && nbk > tl[i] ? tl[i] : nbk;
+      rg[i] = make_uint4(t0, t0 + tl[i], (uint32_t)pob.size(), (uint32_t)nbk);
+      pob.insert(pob.end(), (size_t)nbk, (uint16_t)i);
+      t0 += tl[i];
+    }
+    if (pob.size() > (size_t)per_cu * (size_t)ctx->num_cu || pob.size() > (size_t)ctx->num_cu * 8u)
+      return MH_OK;  // more blocks than can be co-resident
+    grid = (uint32_t)pob.size();
+    MH_HIP(ctx, hipMemcpyAsync(gr.ranges, rg.data(), np * sizeof(uint4), hipMemcpyHostToDevice,
+                               ctx->stream));
+    MH_HIP(ctx, hipMemcpyAsync(gr.prob_of_block, pob.data(), pob.size() * 2,
+                               hipMemcpyHostToDevice, ctx->stream));
+    MH_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the host vectors go out of scope
+    a.prob_of_block = gr.prob_of_block;
+    a.ranges = gr.ranges;
+  }
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
                                             dim3(H * WAVES * 64), args, lds, ctx->stream);
@@ -528,31 +587,34 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
 
 template <int D, int H>
 mh_status launch_d(Ctx *ctx, uint32_t waves, const PersistArgs &pa, uint32_t lds,
-                   uint32_t max_tiles, bool *used) {
+                   uint32_t max_tiles, const Groups &gr, bool *used) {
   switch (waves) {
-    case 1: return launch_w<D, 1, H>(ctx, pa, lds, max_tiles, used);
-    case 2: return launch_w<D, 2, H>(ctx, pa, lds, max_tiles, used);
-    case 4: return launch_w<D, 4, H>(ctx, pa, lds, max_tiles, used);
-    default: return launch_w<D, (H == 2 ? 4 : 8), H>(ctx, pa, lds, max_tiles, used);
+    case 1: return launch_w<D, 1, H>(ctx, pa, lds, max_tiles, gr, used);
+    case 2: return launch_w<D, 2, H>(ctx, pa, lds, max_tiles, gr, used);
+    case 4: return launch_w<D, 4, H>(ctx, pa, lds, max_tiles, gr, used);
+    default: return launch_w<D, (H == 2 ? 4 : 8), H>(ctx, pa, lds, max_tiles, gr, used);
   }
 }
 
 template <int D>
 mh_status launch_dh(Ctx *ctx, uint32_t waves, uint32_t H, const PersistArgs &pa, uint32_t lds,
-                    uint32_t max_tiles, bool *used) {
-  return H == 2 ? launch_d<D, 2>(ctx, waves, pa, lds, max_tiles, used)
-                : launch_d<D, 1>(ctx, waves, pa, lds, max_tiles, used);
+                    uint32_t max_tiles, const Groups &gr, bool *used) {
+  return H == 2 ? launch_d<D, 2>(ctx, waves, pa, lds, max_tiles, gr, used)
+                : launch_d<D, 1>(ctx, waves, pa, lds, max_tiles, gr, used);
 }
 
-}  // namespace
-
-mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
-                               uint32_t n_sub, uint32_t D, const mh_de_params *prm, uint64_t prob,
-                               const uint32_t *n_unique, double *pop, double *cost,
-                               uint32_t *best, uint32_t *err, bool *used) {
+// One problem (ptiles == null) or the problems of a multi-problem tile set.
+mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint32_t n_sub,
+                      uint64_t n_eval, uint32_t n_problems, uint32_t D, const mh_de_params *prm,
+                      uint64_t prob,
+                      const uint64_t *prob_ids, const std::vector<uint32_t> *ptiles,
+                      const uint32_t *n_unique, double *pop, double *cost, uint32_t *best,
+                      uint32_t *err, bool *used) {
   *used = false;
   const uint32_t P = prm->P, SB = (1u << D) - 1u, m = 2 * SB;
-  if (!ctx->coop || D < 1 || D > 5 || P > 512 || F > 80) return MH_OK;
+  if (!ctx->coop || D < 1 || D > 5 || P > 512 || F > 80 || n_problems == 0 ||
+      n_problems > 65535)
+    return MH_OK;
   // barrier targets (G + 1) * blocks must fit the 32-bit arrival counters
   if ((uint64_t)(prm->G + 1) * (uint64_t)ctx->num_cu * 8u >= (1ull << 31)) return MH_OK;
   uint32_t waves = pad64(P) / 64;
@@ -568,13 +630,19 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   const uint32_t lds = persist_lds_bytes(F, P, m, H);
   if (lds > 64u * 1024u) return MH_OK;
   const size_t cstride = (size_t)SB * K * pad64(P);
-  uint32_t *cnt = (uint32_t *)arena_get(ctx, "ps_cnt", 3 * cstride * 4);
-  const size_t bar_bytes = (size_t)barrier_words((uint32_t)ctx->num_cu * 8u) * 4;
-  uint32_t *bar = (uint32_t *)arena_get(ctx, "ps_bar", bar_bytes);
+  const uint32_t bar_words = barrier_words((uint32_t)ctx->num_cu * 8u);
+  uint32_t *cnt = (uint32_t *)arena_get(ctx, "ps_cnt", (size_t)n_problems * 3 * cstride * 4);
+  uint32_t *bar = (uint32_t *)arena_get(ctx, "ps_bar", (size_t)n_problems * bar_words * 4);
   if (!cnt || !bar) return MH_ENOMEM;
+  Groups gr{ptiles, nullptr, nullptr};
+  if (ptiles) {
+    gr.prob_of_block = (uint16_t *)arena_get(ctx, "ps_pob", (size_t)ctx->num_cu * 8u * 2);
+    gr.ranges = (uint4 *)arena_get(ctx, "ps_ranges", (size_t)n_problems * sizeof(uint4));
+    if (!gr.prob_of_block || !gr.ranges) return MH_ENOMEM;
+  }
   hipStream_t st = ctx->stream;
-  MH_HIP(ctx, hipMemsetAsync(cnt, 0, 3 * cstride * 4, st));
-  MH_HIP(ctx, hipMemsetAsync(bar, 0, bar_bytes, st));
+  MH_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n_problems * 3 * cstride * 4, st));
+  MH_HIP(ctx, hipMemsetAsync(bar, 0, (size_t)n_problems * bar_words * 4, st));
   MH_HIP(ctx, hipMemsetAsync(err, 0, 4, st));
   PersistArgs pa;
   pa.hdr = reinterpret_cast<const TileHdr *>(tiles);
@@ -595,25 +663,57 @@ mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
   pa.n_min = prm->n_min;
   pa.F = F;
   pa.K = K;
+  pa.prob_of_block = nullptr;
+  pa.ranges = nullptr;
+  pa.prob_ids = prob_ids;
+  pa.bar_stride = bar_words;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof_pair(ctx, &e0, &e1);
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));
   mh_status s = MH_OK;
-  const uint32_t max_tiles = tile_layout(n_sub, F, K, 1).max_tiles;
+  const uint32_t max_tiles = tile_layout(n_sub, F, K, n_problems).max_tiles;
   switch (D) {
-    case 1: s = launch_dh<1>(ctx, waves, H, pa, lds, max_tiles, used); break;
-    case 2: s = launch_dh<2>(ctx, waves, H, pa, lds, max_tiles, used); break;
-    case 3: s = launch_dh<3>(ctx, waves, H, pa, lds, max_tiles, used); break;
-    case 4: s = launch_dh<4>(ctx, waves, H, pa, lds, max_tiles, used); break;
-    default: s = launch_dh<5>(ctx, waves, H, pa, lds, max_tiles, used); break;
+    case 1: s = launch_dh<1>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
+    case 2: s = launch_dh<2>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
+    case 3: s = launch_dh<3>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
+    case 4: s = launch_dh<4>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
+    default: s = launch_dh<5>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
   }
   if (s) return s;
   if (timed) {
     MH_HIP(ctx, hipEventRecord(e1, st));
     if (*used) ctx->prof_launches += 1;
   }
-  if (*used) ctx->prof_evals += (uint64_t)(prm->G + 1) * n_sub * P;
+  if (*used) ctx->prof_evals += (uint64_t)(prm->G + 1) * n_eval * P;
   return MH_OK;
+}
+
+}  // namespace
+
+mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                               uint32_t n_sub, uint32_t D, const mh_de_params *prm, uint64_t prob,
+                               const uint32_t *n_unique, double *pop, double *cost,
+                               uint32_t *best, uint32_t *err, bool *used) {
+  return persist_run(ctx, tiles, F, K, n_sub, n_sub, 1, D, prm, prob, nullptr, nullptr, n_unique,
+                     pop, cost, best, err, used);
+}
+
+mh_status launch_deoct_persist_multi(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
+                                     uint32_t n_sub, uint32_t n_problems,
+                                     const uint32_t *class_counts, uint32_t D,
+                                     const mh_de_params *prm, const uint64_t *prob_ids,
+                                     const uint32_t *n_unique, double *pop, double *cost,
+                                     uint32_t *best, uint32_t *err, bool *used) {
+  // tiles per problem, in the layout's order (problem-major, then class)
+  std::vector<uint32_t> tl(n_problems, 0);
+  uint64_t n_eval = 0;
+  for (uint32_t i = 0; i < n_problems; ++i)
+    for (uint32_t k = 0; k < K; ++k) {
+      tl[i] += (class_counts[(size_t)i * K + k] + TILE_CAP - 1) / TILE_CAP;
+      n_eval += class_counts[(size_t)i * K + k];
+    }
+  return persist_run(ctx, tiles, F, K, n_sub, n_eval, n_problems, D, prm, 0, prob_ids, &tl,
+                     n_unique, pop, cost, best, err, used);
 }
 
 }  // namespace mh
