@@ -153,7 +153,7 @@ def _device_requests(torch, reqs):
     return out
 
 
-def serving(mh, count=96, seed=11, n_hi=1e7):
+def serving(mh, count=96, seed=11, n_hi=1e7, slots=64):
     """Served subtree solves: `count` requests (n log-uniform in [1e3, n_hi],
     F in 4..32, K in 2..10, D in 2..4, P = 128, G = 100).  The same requests
     are solved (1) one after another with subtree_solve, (2) through the
@@ -177,7 +177,6 @@ def serving(mh, count=96, seed=11, n_hi=1e7):
     ctx.close()
 
     budget = 96 << 30
-    slots = 64
 
     def run(arrivals):
         sctx = capi.Context(0)
@@ -210,6 +209,7 @@ def serving(mh, count=96, seed=11, n_hi=1e7):
     return {
         "workload": f"{count} requests, n log-uniform [1e3, {n_hi:.0e}], F 4..32, K 2..10, "
                     f"D 2..4, P 128, G 100, Gaussian mixtures generated on the device",
+        "server": {"hbm_budget_bytes": budget, "max_slots": slots},
         "evals": evals,
         "plain": {"s": t_plain, "evals_per_s": evals / t_plain, "solves_per_s": count / t_plain},
         "served_all_at_once": {"s": el_c, "evals_per_s": evals / el_c, "solves_per_s": cap},
@@ -269,6 +269,7 @@ def main():
     if args.extra_only:
         import paper_2311_06952_amd as mh
         print(json.dumps({"serving": serving(mh),
+                          "serving_small": serving(mh, count=256, seed=12, n_hi=2e4, slots=256),
                           "moving_horizon": moving_horizon(mh, mh.default_context(0))}),
               flush=True)
         return
@@ -338,6 +339,9 @@ def main():
     }
     if not args.no_extra:
         out["serving"] = serving(mh)
+        # the same forms on a stream of small requests (n log-uniform in
+        # [1e3, 2e4]), where a request alone cannot fill the GPU
+        out["serving_small"] = serving(mh, count=256, seed=12, n_hi=2e4, slots=256)
         out["moving_horizon"] = moving_horizon(mh, ctx)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
