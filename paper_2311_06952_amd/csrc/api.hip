@@ -355,6 +355,11 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   int coop = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
     c->c.coop = coop != 0;
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess &&
+      lds_max >= 64 * 1024)
+    c->c.max_lds = (uint32_t)std::min(lds_max, 160 * 1024);
   *out = c;
   return MH_OK;
 }

@@ -52,6 +52,7 @@ struct Ctx {
   uint32_t persist_blocks_per_cu = 0;  // its blocks per CU; 0 = by size (MHDEOCT_PERSIST_BLOCKS_PER_CU)
   uint32_t persist_halves = 2;         // tile streams per block, 1 or 2 (MHDEOCT_PERSIST_HALVES)
   bool coop = false;     // the device supports cooperative launches
+  uint32_t max_lds = 64u * 1024u;  // dynamic LDS one block may use
 };
 
 // Checks DE parameters for a depth-D problem (MH_EINVAL with a message).

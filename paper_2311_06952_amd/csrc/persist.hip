@@ -143,21 +143,27 @@ __device__ __forceinline__ void wave_argmin(double &c, uint32_t &i) {
   i = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
 }
 
-// LDS: H staged tiles | rows [m][P] f64 | n_unique [F] | argmin scratch.
-// The trees' decoded nodes and the second half's left counts pass through
-// the first tile buffer while no tile is staged.
-__host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint32_t P, uint32_t m,
-                                                              uint32_t H) {
-  const uint32_t tile = align16u(mask_region(F) + F * MCOL);
-  return H * tile + align16u(m * P * 8) + align16u(F * 4) + 32 * 8 + 32 * 4;
-}
-// Bytes of the first tile buffer the exchanges need: decoded nodes (feature
+// Bytes the exchanges need in the first tile buffer: decoded nodes (feature
 // byte and threshold per node and tree), or the second half's class and
 // counts per tree.
 __host__ __device__ __forceinline__ uint32_t persist_exchange_bytes(uint32_t SB, uint32_t P) {
   const uint32_t nodes = align16u(SB * P) + SB * P * 4;
   const uint32_t counts = P * 4 + SB * P * 4;
   return nodes > counts ? nodes : counts;
+}
+// The first tile buffer, large enough for the exchanges.
+__host__ __device__ __forceinline__ uint32_t persist_slot_a(uint32_t F, uint32_t SB, uint32_t P) {
+  const uint32_t tile = align16u(mask_region(F) + F * MCOL);
+  const uint32_t x = align16u(persist_exchange_bytes(SB, P));
+  return tile > x ? tile : x;
+}
+// LDS: first tile buffer (also the exchange area) | second tile buffer
+// (H = 2) | rows [m][P] f64 | n_unique [F] | argmin scratch.
+__host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint32_t P, uint32_t SB,
+                                                              uint32_t H) {
+  const uint32_t tile = align16u(mask_region(F) + F * MCOL);
+  return persist_slot_a(F, SB, P) + (H - 1) * tile + align16u(2 * SB * P * 8) + align16u(F * 4) +
+         32 * 8 + 32 * 4;
 }
 
 // Two-wave-group layout (H = 2): the block holds two copies of the
@@ -201,9 +207,12 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 
   const uint32_t mregion = mask_region(F);
   const uint32_t tile_lds = align16u(mregion + F * MCOL);
-  uint8_t *my_tile = lds + h * tile_lds;
-  double *rows = reinterpret_cast<double *>(lds + H * tile_lds);
-  uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + H * tile_lds + align16u(m * P * 8));
+  const uint32_t slot_a = persist_slot_a(F, SB, P);
+  const uint32_t tile_off = h == 0 ? 0u : slot_a;
+  uint8_t *my_tile = lds + tile_off;
+  const uint32_t rows_off = slot_a + (H - 1) * tile_lds;
+  double *rows = reinterpret_cast<double *>(lds + rows_off);
+  uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + rows_off + align16u(m * P * 8));
   double *s_cost = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(s_nu) + align16u(F * 4));
   uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_cost + 32);
   // exchanges in the first tile buffer
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   uint32_t *x_cls = reinterpret_cast<uint32_t *>(lds);                // [P]
   uint32_t *x_acc = reinterpret_cast<uint32_t *>(lds + P * 4);         // [SB][P]
   const uint32_t s0 =
-      (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds) + h * tile_lds;
+      (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds) + tile_off;
   const uint32_t kmask = s0 + mregion - 2u * s0;
 
   for (uint32_t f = threadIdx.x; f < F; f += NT) s_nu[f] = pa.n_unique[f];
@@ -542,9 +551,15 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
           hipSuccess ||
       per_cu < 1)
     return MH_OK;  // not co-resident: the caller takes the per-generation kernels
-  uint32_t bpc = ctx->persist_blocks_per_cu
-                     ? ctx->persist_blocks_per_cu
-                     : persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
+  const uint32_t want = persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
+  // with many tiles per CU and fewer co-resident waves than wanted (large
+  // LDS), the per-generation kernels keep more waves busy: measured at
+  // n = 1e6, P = 512, depth 4 (one 512-thread block per CU) 355 against
+  // 281 us per generation
+  if (!ctx->persist_blocks_per_cu && want > (uint32_t)per_cu &&
+      max_tiles > 16u * (uint32_t)ctx->num_cu)
+    return MH_OK;
+  uint32_t bpc = ctx->persist_blocks_per_cu ? ctx->persist_blocks_per_cu : want;
   bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
   bpc = bpc > 8u ? 8u : bpc;
   uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
@@ -580,6 +595,13 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
                                             dim3(H * WAVES * 64), args, lds, ctx->stream);
+  if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
+      e == hipErrorInvalidConfiguration) {
+    // a shape the launch refuses (LDS, block count): the per-generation
+    // kernels take the run
+    (void)hipGetLastError();
+    return MH_OK;
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_deoct_persist");
   *used = true;
   return MH_OK;
@@ -620,15 +642,14 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   uint32_t waves = pad64(P) / 64;
   waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
   // two tile streams per block when the LDS and the 1024-thread limit allow
-  const uint32_t tile_lds = align16u(mask_region(F) + F * MCOL);
+  const uint32_t max_lds = ctx->max_lds;
   uint32_t H = (ctx->persist_halves != 1 && waves <= 4 &&
-                persist_lds_bytes(F, P, m, 2) <= 64u * 1024u &&
-                persist_exchange_bytes(SB, P) <= tile_lds)
+                persist_lds_bytes(F, P, SB, 2) <= max_lds)
                    ? 2u
                    : 1u;
-  if (H == 1 && persist_exchange_bytes(SB, P) > tile_lds) return MH_OK;
-  const uint32_t lds = persist_lds_bytes(F, P, m, H);
-  if (lds > 64u * 1024u) return MH_OK;
+  const uint32_t lds = persist_lds_bytes(F, P, SB, H);
+  if (lds > max_lds) return MH_OK;
+  (void)m;
   const size_t cstride = (size_t)SB * K * pad64(P);
   const uint32_t bar_words = barrier_words((uint32_t)ctx->num_cu * 8u);
   uint32_t *cnt = (uint32_t *)arena_get(ctx, "ps_cnt", (size_t)n_problems * 3 * cstride * 4);

@@ -296,3 +296,22 @@ def test_persistent_deoct_edge_shapes(mh, D, P, K, n):
                         prob=1)
     _same_tree(want, got)
 
+
+@pytest.mark.parametrize("D,P,F,K", [(4, 512, 32, 4), (4, 128, 4, 6), (5, 200, 30, 3)])
+def test_persistent_large_lds_shapes(mh, monkeypatch, D, P, F, K):
+    """Populations whose DE rows need more than 64 KiB of LDS, and narrow
+    data whose tile buffer is smaller than the node exchange: whole-run kernel
+    (where the device allows it) and per-generation kernels agree with the
+    oracle."""
+    from paper_2311_06952_amd import capi
+    X, y = synth.random_small(90 + D + F, 4000, F, K)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 6, 0.5, 0.9, 13),
+                        prob=2)
+    for persist in ("1", "0"):
+        monkeypatch.setenv("MHDEOCT_PERSIST", persist)
+        ctx = capi.Context(0)
+        ds = mh.dataset(X, y, K, ctx=ctx)
+        got = mh.subtree_solve(ds, D, mh.de_params(P, 6, 0.5, 0.9, 13), prob=2, ctx=ctx)
+        _same_tree(want, got)
+        ctx.close()
+
