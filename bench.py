@@ -48,7 +48,7 @@ def cpu_baseline(w, seconds=15.0):
                        f"workload, {evals:.3g} evals in {el:.1f} s, single thread")
 
 
-KERNEL = "k_deoct_persist<3,4>"
+KERNEL = "k_deoct_persist<3,4,2>"
 KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_deoct_persist_plain_scale_traffic.txt")
 
@@ -85,7 +85,7 @@ def ds_of(mh, Xd, yd, w, ctx):
     return mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
 
 
-def roofline(w, kernel_ms, launches_per_step):
+def roofline(w, kernel_ms, launches_per_step, kernel=None):
     """The dominant kernel against the int32 VALU roof: D compare-and-descend
     steps and one count per sample-tree evaluation (Algorithm 1).  With the
     whole run in one launch, a launch covers all G + 1 population
@@ -96,7 +96,7 @@ def roofline(w, kernel_ms, launches_per_step):
     bytes_launch = (4 * w.F + 1) / w.P * evals_launch
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
             "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
-            "kernel": KERNEL if launches_per_step == 1 else "k_fitness_bits<3,4,false>",
+            "kernel": kernel or (KERNEL if launches_per_step == 1 else "k_fitness_bits<3,4,false>"),
             "kernel_ms_avg": kernel_ms, "launches_per_step": launches_per_step,
             "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
             "algorithmic_bytes_per_launch": bytes_launch,
@@ -290,6 +290,10 @@ def main():
         ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
         return mh.subtree_solve(ds, w.D, prm, ctx=ctx)
 
+    # launch configuration for this shape, timed on short runs (before the
+    # warm-up; it changes timing only)
+    tuned = mh.autotune(ds_of(mh, Xd, yd, w, ctx), w.D, prm, generations=20, ctx=ctx)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -314,7 +318,9 @@ def main():
     st = ctx.stats(reset=True)
     kernel_ms = st["ms"] / max(st["launches"], 1)
     lps = max(1, round(st["launches"] / args.steps))
-    roof = roofline(w, kernel_ms, lps)
+    kname = (f"k_deoct_persist<3,4,{tuned['halves']}>" if lps == 1
+             else "k_fitness_bits<3,4,false>")
+    roof = roofline(w, kernel_ms, lps, kname)
     roof["timed_launches"] = int(st["launches"])
     out = {
         "metric": "sample-tree evals/s (fitness)",
@@ -336,6 +342,8 @@ def main():
         "subtree_solves_per_s": args.steps / el,
         "best_correct": res["correct"],
         "roofline": roof,
+        "launch_config": {k: tuned[k] for k in ("persist", "halves", "persist_blocks_per_cu",
+                                                "fit_blocks_per_cu")},
     }
     if not args.no_extra:
         out["serving"] = serving(mh)

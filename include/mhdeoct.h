@@ -217,6 +217,24 @@ mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                         const double *warm, uint32_t W, uint64_t problem_id,
                         mh_tree *out);
 
+/* Launch-configuration autotuning for DEOCT runs on a dataset shape: times
+ * short runs (G = generations, on all of ds) of each candidate (the whole-run
+ * cooperative kernel with one or two tile streams per block and 1, 2 or 4
+ * blocks per CU; the per-generation kernels with 1, 2 or 4 fitness blocks per
+ * CU) and keeps the fastest in the context for this shape (depth, P, F, K and
+ * the power-of-two bucket of tiles per CU); later subtree_solve calls of that
+ * shape use it.  Configurations change timing only: results are identical.
+ * Fills *out (host).  Synchronises. */
+typedef struct {
+  uint32_t persist, halves, persist_blocks_per_cu, fit_blocks_per_cu;  /* the winner */
+  double ms_per_generation;   /* its time per generation */
+  uint32_t n_candidates;
+  double ms[16];              /* median run time of each candidate, ms */
+} mh_tune_result;
+mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D,
+                      const mh_de_params *prm, uint32_t generations,
+                      mh_tune_result *out);
+
 /* ---------------------------------------------------------------------- */
 /* a7. Moving-horizon DEOCT (Algorithm 2; Section 4).                       */
 /* ---------------------------------------------------------------------- */

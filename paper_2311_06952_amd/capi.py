@@ -25,7 +25,7 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_ctx_stats", "mh_rank_encode", "tree_decode", "fitness_eval", "mh_tileset_bytes",
            "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
-           "mh_server_footprint", "mh_server_pump", "mh_server_poll")
+           "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune")
 
 
 class MhError(RuntimeError):
@@ -47,6 +47,13 @@ class DEParamsC(C.Structure):
 class TreeC(C.Structure):
     _fields_ = [("D", C.c_uint32), ("feat", C.c_uint8 * 1023), ("tau", C.c_uint32 * 1023),
                 ("label", C.c_uint8 * 1024), ("correct", C.c_uint32), ("cost", C.c_double)]
+
+
+class TuneC(C.Structure):
+    _fields_ = [("persist", C.c_uint32), ("halves", C.c_uint32),
+                ("persist_blocks_per_cu", C.c_uint32), ("fit_blocks_per_cu", C.c_uint32),
+                ("ms_per_generation", C.c_double), ("n_candidates", C.c_uint32),
+                ("ms", C.c_double * 16)]
 
 
 class ResultC(C.Structure):
@@ -99,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "mh_server_footprint": ([U32, U32, U32, U32, U32, C.POINTER(U64)], I32),
         "mh_server_pump": ([V, U32, C.POINTER(U32), C.POINTER(U32)], I32),
         "mh_server_poll": ([V, C.POINTER(ResultC), U32, C.POINTER(U32)], I32),
+        "mh_autotune": ([V, C.POINTER(DatasetC), U32, C.POINTER(DEParamsC), U32, C.POINTER(TuneC)],
+                        I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)  # AttributeError if a symbol is missing
@@ -340,6 +349,22 @@ def subtree_solve(ds: Dataset, D: int, prm: DEParamsC, idx=None, warm=None, prob
     ctx.check(ctx.lib.subtree_solve(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp, W,
                                     prob, C.byref(out)))
     return _tree_dict(out)
+
+
+def autotune(ds: Dataset, D: int, prm: DEParamsC, generations: int = 20,
+             ctx: Context | None = None) -> dict:
+    """mh_autotune: time the launch configurations on short runs and keep the
+    fastest for this shape in the context."""
+    ctx = ctx or default_context()
+    out = TuneC()
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.mh_autotune(ctx.h, C.byref(dsc), D, C.byref(prm), generations,
+                                  C.byref(out)))
+    return dict(persist=int(out.persist), halves=int(out.halves),
+                persist_blocks_per_cu=int(out.persist_blocks_per_cu),
+                fit_blocks_per_cu=int(out.fit_blocks_per_cu),
+                ms_per_generation=float(out.ms_per_generation),
+                ms=[float(out.ms[i]) for i in range(out.n_candidates)])
 
 
 def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParamsC, batched: bool = False,

@@ -1,6 +1,7 @@
 // api.hip -- the C ABI (include/mhdeoct.h): context, arena, argument checks
 // and the host-side orchestration of the device kernels.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -24,6 +25,15 @@ mh_status fail(Ctx *ctx, mh_status code, const std::string &msg) {
 mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return fail(ctx, e == hipErrorOutOfMemory ? MH_ENOMEM : MH_EDEVICE, m);
+}
+
+uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu) {
+  uint32_t per_cu = num_cu ? max_tiles / num_cu : max_tiles, b = 0;
+  while (per_cu) {
+    ++b;
+    per_cu >>= 1;
+  }
+  return b;
 }
 
 constexpr size_t PROF_MAX_PAIRS = 4096;
@@ -522,6 +532,32 @@ mh_status de_step(mh_ctx *ctx, const mh_de_params *prm, uint32_t D, uint32_t F,
                         next_trial, nullptr, nullptr);
 }
 
+// Runs deoct with the launch configuration mh_autotune chose for this shape,
+// if any (the configuration changes timing only, never results).
+static mh_status deoct_tuned(Ctx *c, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                             uint32_t D, const mh_de_params *prm, const double *warm, uint32_t W,
+                             uint64_t prob, mh_tree *out) {
+  const uint32_t tb = tiles_bucket(tile_layout(n_sub, ds->F, ds->K, 1).max_tiles, (uint32_t)c->num_cu);
+  for (const Ctx::Tuned &t : c->tuned) {
+    if (t.D == D && t.P == prm->P && t.F == ds->F && t.K == ds->K && t.tiles_bucket == tb) {
+      const bool p0 = c->persist;
+      const uint32_t h0 = c->persist_halves, b0 = c->persist_blocks_per_cu,
+                     f0 = c->fit_blocks_per_cu;
+      c->persist = t.persist != 0;
+      c->persist_halves = t.halves;
+      c->persist_blocks_per_cu = t.persist_bpc;
+      c->fit_blocks_per_cu = t.fit_bpc;
+      const mh_status s = deoct(c, ds, idx, n_sub, D, prm, warm, W, prob, out);
+      c->persist = p0;
+      c->persist_halves = h0;
+      c->persist_blocks_per_cu = b0;
+      c->fit_blocks_per_cu = f0;
+      return s;
+    }
+  }
+  return deoct(c, ds, idx, n_sub, D, prm, warm, W, prob, out);
+}
+
 mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                         uint32_t D, const mh_de_params *prm, const double *warm, uint32_t W,
                         uint64_t problem_id, mh_tree *out) {
@@ -534,7 +570,82 @@ mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, 
   if (!out) return fail(c, MH_EINVAL, "out is null");
   if (W > prm->P || (W > 0 && !warm)) return fail(c, MH_EINVAL, "bad warm starts");
   if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
-  return deoct(c, ds, idx, n_sub, D, prm, warm, W, problem_id, out);
+  return deoct_tuned(c, ds, idx, n_sub, D, prm, warm, W, problem_id, out);
+}
+
+mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, const mh_de_params *prm,
+                      uint32_t generations, mh_tune_result *out) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  s = check_de(c, prm, D);
+  if (s) return s;
+  if (!out) return fail(c, MH_EINVAL, "out is null");
+  if (generations == 0) return fail(c, MH_EINVAL, "generations must be >= 1");
+  // candidates: the whole-run kernel with one or two tile streams per block
+  // and 1, 2 or 4 blocks per CU, and the per-generation kernels with 1, 2 or
+  // 4 fitness blocks per CU
+  struct Cand {
+    uint32_t persist, halves, persist_bpc, fit_bpc;
+  };
+  std::vector<Cand> cands;
+  for (uint32_t hv : {2u, 1u})
+    for (uint32_t b : {1u, 2u, 4u}) cands.push_back({1u, hv, b, c->fit_blocks_per_cu});
+  for (uint32_t b : {1u, 2u, 4u}) cands.push_back({0u, 2u, 0u, b});
+  mh_de_params p = *prm;
+  p.G = generations;
+  const bool p0 = c->persist;
+  const uint32_t h0 = c->persist_halves, b0 = c->persist_blocks_per_cu, f0 = c->fit_blocks_per_cu;
+  std::memset(out, 0, sizeof(*out));
+  out->n_candidates = (uint32_t)std::min<size_t>(cands.size(), 16);
+  double best_ms = 1e300;
+  Cand best = cands.back();
+  mh_tree tr;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const Cand &cd = cands[i];
+    c->persist = cd.persist != 0;
+    c->persist_halves = cd.halves;
+    c->persist_blocks_per_cu = cd.persist_bpc;
+    c->fit_blocks_per_cu = cd.fit_bpc;
+    // one untimed run, then the median of three timed ones (each run
+    // synchronises when it fills the host result)
+    s = deoct(c, ds, nullptr, ds->n, D, &p, nullptr, 0, 0, &tr);
+    double t[3];
+    for (int k = 0; s == MH_OK && k < 3; ++k) {
+      const auto t0 = std::chrono::steady_clock::now();
+      s = deoct(c, ds, nullptr, ds->n, D, &p, nullptr, 0, 0, &tr);
+      t[k] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (s) break;
+    std::sort(t, t + 3);
+    if (i < 16) out->ms[i] = t[1];
+    if (t[1] < best_ms) {
+      best_ms = t[1];
+      best = cd;
+    }
+  }
+  c->persist = p0;
+  c->persist_halves = h0;
+  c->persist_blocks_per_cu = b0;
+  c->fit_blocks_per_cu = f0;
+  if (s) return s;
+  const uint32_t tb = tiles_bucket(tile_layout(ds->n, ds->F, ds->K, 1).max_tiles, (uint32_t)c->num_cu);
+  Ctx::Tuned e{D, prm->P, ds->F, ds->K, tb, best.persist, best.halves, best.persist_bpc,
+               best.fit_bpc};
+  bool replaced = false;
+  for (Ctx::Tuned &t : c->tuned)
+    if (t.D == e.D && t.P == e.P && t.F == e.F && t.K == e.K && t.tiles_bucket == e.tiles_bucket) {
+      t = e;
+      replaced = true;
+    }
+  if (!replaced) c->tuned.push_back(e);
+  out->persist = best.persist;
+  out->halves = best.halves;
+  out->persist_blocks_per_cu = best.persist_bpc;
+  out->fit_blocks_per_cu = best.fit_bpc;
+  out->ms_per_generation = best_ms / (generations + 1);
+  return MH_OK;
 }
 
 mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,

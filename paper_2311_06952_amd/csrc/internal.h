@@ -53,7 +53,15 @@ struct Ctx {
   uint32_t persist_halves = 2;         // tile streams per block, 1 or 2 (MHDEOCT_PERSIST_HALVES)
   bool coop = false;     // the device supports cooperative launches
   uint32_t max_lds = 64u * 1024u;  // dynamic LDS one block may use
+  // launch configurations chosen by mh_autotune, by problem shape
+  struct Tuned {
+    uint32_t D, P, F, K, tiles_bucket;  // shape key
+    uint32_t persist, halves, persist_bpc, fit_bpc;
+  };
+  std::vector<Tuned> tuned;
 };
+// Shape key bucket of a tile count: floor(log2(tiles per CU)) + 1 (0 for none).
+uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu);
 
 // Checks DE parameters for a depth-D problem (MH_EINVAL with a message).
 mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D);

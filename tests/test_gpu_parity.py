@@ -315,3 +315,21 @@ def test_persistent_large_lds_shapes(mh, monkeypatch, D, P, F, K):
         _same_tree(want, got)
         ctx.close()
 
+
+def test_autotune_keeps_results(mh):
+    """The autotuner picks a launch configuration for the shape; runs with it
+    still equal the oracle."""
+    from paper_2311_06952_amd import capi
+    w = synth.plain_small(3, n=30000)
+    ctx = capi.Context(0)
+    ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
+    prm = mh.de_params(64, 15, 0.5, 0.9, 21)
+    tuned = mh.autotune(ds, w.D, prm, generations=5, ctx=ctx)
+    assert tuned["persist"] in (0, 1) and tuned["halves"] in (1, 2)
+    assert len(tuned["ms"]) == 9 and all(t > 0 for t in tuned["ms"])
+    got = mh.subtree_solve(ds, w.D, prm, ctx=ctx)
+    want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D, oracle.de_params(64, 15, 0.5,
+                                                                                     0.9, 21))
+    _same_tree(want, got)
+    ctx.close()
+
