@@ -135,10 +135,12 @@ __device__ __forceinline__ void fitness_block(const TileHdr *__restrict__ hdr,
       if (c < nchunk) pf[k] = src[c];
     }
   };
+  // the next tile's info word travels with its prefetch
   prefetch(t_begin);
+  uint32_t inf_next = info[t_begin];
 
   for (uint32_t tile = t_begin; tile < t_end; ++tile) {
-    const uint32_t inf = info[tile];
+    const uint32_t inf = inf_next;
     const uint32_t sub = inf >> 16, cls = (inf >> 8) & 0xFFu, count = inf & 0xFFu;
     if (sub != cur_sub || cls != cur_cls) {
       if (cur_sub != 0xFFFFFFFFu) flush(cur_sub, cur_cls);
@@ -172,7 +174,10 @@ __device__ __forceinline__ void fitness_block(const TileHdr *__restrict__ hdr,
         stage_chunk(lds, mregion, F, c, src[c]);
     }
     __syncthreads();
-    if (tile + 1 < t_end) prefetch(tile + 1);
+    if (tile + 1 < t_end) {
+      prefetch(tile + 1);
+      inf_next = info[tile + 1];
+    }
     uint64_t R[1 << D];
     R[1] = (1ull << count) - 1ull;  // count <= 63
     eval_nodes<D, 1>(kmask, ns, R);

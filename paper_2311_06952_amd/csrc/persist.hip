@@ -273,7 +273,13 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       if (c < nchunk) pf[k] = src[c];
     }
   };
-  if (t_begin + h < t_end) prefetch(t_begin + h);
+  // the next tile's info word travels with its prefetch, so that the loop
+  // never waits on it
+  uint32_t inf_next = 0;
+  if (t_begin + h < t_end) {
+    prefetch(t_begin + h);
+    inf_next = info[t_begin + h];
+  }
 
   for (uint32_t g = 0; g <= pa.G; ++g) {
     uint32_t *cnt = cnt3 + (size_t)(g % 3) * cstride;
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       const bool act = tile < t_end;
       uint32_t count = 0;
       if (act) {
-        const uint32_t inf = info[tile];
+        const uint32_t inf = inf_next;
         const uint32_t cls = (inf >> 8) & 0xFFu;
         count = inf & 0xFFu;
         if (cls != cur_cls) {
@@ -327,7 +333,9 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       if (act) {
         // the next tile, or this half's first tile again for the next
         // generation (the layout does not change)
-        prefetch(tile + H < t_end ? tile + H : t_begin + h);
+        const uint32_t nxt = tile + H < t_end ? tile + H : t_begin + h;
+        prefetch(nxt);
+        inf_next = info[nxt];
         uint64_t R[1 << D];
         R[1] = (1ull << count) - 1ull;  // count <= 63
         eval_nodes<D, 1>(kmask, ns, R);
