@@ -358,6 +358,8 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_FIT_MIN_TILES")) c->c.fit_min_tiles = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_FUSE_DE")) c->c.fuse_de = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_PERSIST")) c->c.persist = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_PERSIST_RESIDENT"))
+    c->c.persist_resident = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_PERSIST_HALVES"))
     c->c.persist_halves = atoi(v) == 1 ? 1u : 2u;
   if (const char *v = std::getenv("MHDEOCT_PERSIST_BLOCKS_PER_CU"))

@@ -48,13 +48,17 @@ __device__ __forceinline__ uint64_t lds_rd64(uint32_t addr) {
   return *reinterpret_cast<lds_u64_t *>(static_cast<uintptr_t>(addr));
 }
 
+// delta: byte offset of the staged tile from the one the node columns were
+// set up for (kmask is that tile's), so that one node state serves several
+// staged tiles.
 template <int D, int T0, int T1>
 __device__ __forceinline__ void eval_group(uint32_t kmask, NodeState<D> &ns,
-                                           uint64_t (&R)[1 << D]) {
+                                           uint64_t (&R)[1 << D], uint32_t delta) {
   constexpr int NG = T1 - T0;
   uint32_t a[NG];
 #pragma unroll
-  for (int i = 0; i < NG; ++i) a[i] = ns.col[T0 - 1 + i];
+  for (int i = 0; i < NG; ++i) a[i] = ns.col[T0 - 1 + i] + delta;
+  kmask -= delta;
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
     uint32_t v[NG];
@@ -81,12 +85,12 @@ __device__ __forceinline__ void eval_group(uint32_t kmask, NodeState<D> &ns,
 
 template <int D, int T0>
 __device__ __forceinline__ void eval_nodes(uint32_t kmask, NodeState<D> &ns,
-                                           uint64_t (&R)[1 << D]) {
+                                           uint64_t (&R)[1 << D], uint32_t delta = 0) {
   constexpr int SB = (1 << D) - 1;
   if constexpr (T0 <= SB) {
     constexpr int T1 = (T0 + ILP <= SB + 1) ? T0 + ILP : SB + 1;
-    eval_group<D, T0, T1>(kmask, ns, R);
-    eval_nodes<D, T1>(kmask, ns, R);
+    eval_group<D, T0, T1>(kmask, ns, R, delta);
+    eval_nodes<D, T1>(kmask, ns, R, delta);
   }
 }
 

@@ -56,6 +56,9 @@ struct PersistArgs {
   const uint4 *ranges;
   const uint64_t *prob_ids;  // [problems]
   uint32_t bar_stride;       // barrier words per problem
+  // > 0: every half keeps its (at most tph) tiles resident in LDS, staged in
+  // generation 0 only; 0: tiles are staged every generation
+  uint32_t tph;
 };
 
 // A barrier wait gives up after this many ticks of the device wall clock
@@ -203,19 +206,28 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   const uint32_t nchunk = 48u * F;
   const uint32_t t_begin = T0 + (uint32_t)((uint64_t)(T1 - T0) * b / nb);
   const uint32_t t_end = T0 + (uint32_t)((uint64_t)(T1 - T0) * (b + 1) / nb);
-  const uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
+  uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
+  if (pa.tph && rounds > pa.tph) {
+    // more tiles than resident slots: cannot happen with the host's bound;
+    // stay inside the LDS and report
+    rounds = pa.tph;
+    if (threadIdx.x == 0) __hip_atomic_store(pa.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   const uint32_t mregion = mask_region(F);
   const uint32_t tile_lds = align16u(mregion + F * MCOL);
+  const uint32_t tph = pa.tph;
+  // staged every generation: one buffer per half, the first also the
+  // exchange area; resident: the exchange area, then tph slots per half
   const uint32_t slot_a = persist_slot_a(F, SB, P);
-  const uint32_t tile_off = h == 0 ? 0u : slot_a;
-  uint8_t *my_tile = lds + tile_off;
-  const uint32_t rows_off = slot_a + (H - 1) * tile_lds;
+  const uint32_t x_bytes = align16u(persist_exchange_bytes(SB, P));
+  const uint32_t tile_off = tph ? x_bytes + h * tph * tile_lds : (h == 0 ? 0u : slot_a);
+  const uint32_t rows_off = tph ? x_bytes + H * tph * tile_lds : slot_a + (H - 1) * tile_lds;
   double *rows = reinterpret_cast<double *>(lds + rows_off);
   uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + rows_off + align16u(m * P * 8));
   double *s_cost = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(s_nu) + align16u(F * 4));
   uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_cost + 32);
-  // exchanges in the first tile buffer
+  // exchanges at the start of LDS
   uint8_t *x_feat = lds;                                              // [SB][P]
   uint32_t *x_thr = reinterpret_cast<uint32_t *>(lds + align16u(SB * P));  // [SB][P]
   uint32_t *x_cls = reinterpret_cast<uint32_t *>(lds);                // [P]
@@ -302,9 +314,13 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         ns.acc[t] = 0;
       }
     };
+    // resident tiles are staged in generation 0 only
+    const bool stage = tph == 0 || g == 0;
     for (uint32_t i = 0; i < rounds; ++i) {
       const uint32_t tile = t_begin + i * H + h;
       const bool act = tile < t_end;
+      uint8_t *my_tile = lds + tile_off + (tph ? i * tile_lds : 0u);
+      const uint32_t delta = tph ? i * tile_lds : 0u;
       uint32_t count = 0;
       if (act) {
         const uint32_t inf = inf_next;
@@ -315,8 +331,8 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
           cur_cls = cls;
         }
       }
-      __syncthreads();  // the previous tiles are no longer read
-      if (act) {
+      if (stage) __syncthreads();  // the previous tiles are no longer read
+      if (act && stage) {
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
           const uint32_t c = r + k * NTH;
@@ -329,16 +345,17 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
             stage_chunk(my_tile, mregion, F, c, src[c]);
         }
       }
-      __syncthreads();
+      if (stage) __syncthreads();
       if (act) {
         // the next tile, or this half's first tile again for the next
-        // generation (the layout does not change)
+        // generation (the layout does not change); resident tiles are not
+        // fetched again after generation 0
         const uint32_t nxt = tile + H < t_end ? tile + H : t_begin + h;
-        prefetch(nxt);
+        if (tph == 0 || (g == 0 && tile + H < t_end)) prefetch(nxt);
         inf_next = info[nxt];
         uint64_t R[1 << D];
         R[1] = (1ull << count) - 1ull;  // count <= 63
-        eval_nodes<D, 1>(kmask, ns, R);
+        eval_nodes<D, 1>(kmask, ns, R, delta);
       }
     }
     if constexpr (H == 2) {
@@ -560,18 +577,26 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
       per_cu < 1)
     return MH_OK;  // not co-resident: the caller takes the per-generation kernels
   const uint32_t want = persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
-  // with many tiles per CU and fewer co-resident waves than wanted (large
-  // LDS), the per-generation kernels keep more waves busy: measured at
-  // n = 1e6, P = 512, depth 4 (one 512-thread block per CU) 355 against
-  // 281 us per generation
-  if (!ctx->persist_blocks_per_cu && want > (uint32_t)per_cu &&
-      max_tiles > 16u * (uint32_t)ctx->num_cu)
-    return MH_OK;
+  // with many tiles per CU the tile work dominates, and the per-generation
+  // kernels win where they keep more waves per CU busy than the whole-run
+  // kernel can (measured at n = 1e6, P = 512, depth 4: one 8-wave block per
+  // CU against two, 355 against 281 us per generation; at P = 128 and 256
+  // the whole-run kernel wins or ties)
+  {
+    uint32_t fw = pad64(pa.P) / 64;
+    fw = fw > 4 ? 8 : (fw > 2 ? 4 : fw);
+    const uint32_t have = (want < (uint32_t)per_cu ? want : (uint32_t)per_cu) * H * WAVES;
+    if (!ctx->persist_blocks_per_cu && max_tiles > 16u * (uint32_t)ctx->num_cu &&
+        ctx->fit_blocks_per_cu * fw > have)
+      return MH_OK;
+  }
   uint32_t bpc = ctx->persist_blocks_per_cu ? ctx->persist_blocks_per_cu : want;
   bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
   bpc = bpc > 8u ? 8u : bpc;
   uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
   PersistArgs a = pa;
+  a.tph = 0;
+  uint32_t per_block = (max_tiles + grid - 1) / grid;  // tiles of one block, at most
   if (gr.tiles) {
     // blocks in proportion to each problem's tiles, at least one each
     const std::vector<uint32_t> &tl = *gr.tiles;
@@ -592,6 +617,11 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
     if (pob.size() > (size_t)per_cu * (size_t)ctx->num_cu || pob.size() > (size_t)ctx->num_cu * 8u)
       return MH_OK;  // more blocks than can be co-resident
     grid = (uint32_t)pob.size();
+    per_block = 0;
+    for (uint32_t i = 0; i < np; ++i) {
+      const uint32_t pb = (tl[i] + rg[i].w - 1) / rg[i].w;
+      per_block = pb > per_block ? pb : per_block;
+    }
     MH_HIP(ctx, hipMemcpyAsync(gr.ranges, rg.data(), np * sizeof(uint4), hipMemcpyHostToDevice,
                                ctx->stream));
     MH_HIP(ctx, hipMemcpyAsync(gr.prob_of_block, pob.data(), pob.size() * 2,
@@ -600,9 +630,27 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
     a.prob_of_block = gr.prob_of_block;
     a.ranges = gr.ranges;
   }
+  // resident tiles when every block's tiles fit the LDS next to the DE rows
+  uint32_t lds_use = lds;
+  if (ctx->persist_resident) {
+    const uint32_t SB = (1u << D) - 1u;
+    const uint32_t tph = (per_block + H - 1) / H;
+    const uint32_t tile = align16u(mask_region(pa.F) + pa.F * MCOL);
+    const uint64_t need = (uint64_t)align16u(persist_exchange_bytes(SB, pa.P)) +
+                          (uint64_t)H * tph * tile + align16u(2 * SB * pa.P * 8) +
+                          align16u(pa.F * 4) + 32 * 8 + 32 * 4;
+    int per_cu_res = 0;
+    if (tph >= 1 && tph <= 32 && need <= ctx->max_lds &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_res, kern, H * WAVES * 64,
+                                                     (size_t)need) == hipSuccess &&
+        (uint64_t)per_cu_res * ctx->num_cu >= grid) {
+      a.tph = tph;
+      lds_use = (uint32_t)need;
+    }
+  }
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
-                                            dim3(H * WAVES * 64), args, lds, ctx->stream);
+                                            dim3(H * WAVES * 64), args, lds_use, ctx->stream);
   if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
       e == hipErrorInvalidConfiguration) {
     // a shape the launch refuses (LDS, block count): the per-generation
@@ -696,6 +744,7 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   pa.ranges = nullptr;
   pa.prob_ids = prob_ids;
   pa.bar_stride = bar_words;
+  pa.tph = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof_pair(ctx, &e0, &e1);
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));
