@@ -166,12 +166,14 @@ def serving(mh, count=96, seed=11, n_hi=1e7, slots=64):
     evals = sum(q.n * q.P * (q.G + 1) for q in reqs)
     prm = [mh.de_params(q.P, q.G, 0.5, 0.9, 5000 + q.rid) for q in reqs]
 
-    # (1) plain: one request at a time on one context
+    # (1) plain: one request at a time on one context (the rank encoding's
+    # NaN check is read with the result)
     ctx = capi.Context(0)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
     t0 = time.perf_counter()
     for q, (X, y), p in zip(reqs, data, prm):
-        ranks, nu = mh.rank_encode(X, ctx)
-        mh.subtree_solve(mh.Dataset(ranks, y, nu, q.n, q.F, q.K), q.D, p, ctx=ctx)
+        ranks, nu = mh.rank_encode(X, ctx, status=status)
+        mh.subtree_solve(mh.Dataset(ranks, y, nu, q.n, q.F, q.K, status), q.D, p, ctx=ctx)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     ctx.close()
@@ -284,10 +286,13 @@ def main():
     Xd = torch.as_tensor(w.X).to(dev)
     yd = torch.as_tensor(w.y).to(dev)
     prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def step():
-        ranks, nu = mh.rank_encode(Xd, ctx)
-        ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
+        # rank encoding's NaN check is read back with the solved tree, so a
+        # step waits for the device once
+        ranks, nu = mh.rank_encode(Xd, ctx, status=status)
+        ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
         return mh.subtree_solve(ds, w.D, prm, ctx=ctx)
 
     # launch configuration for this shape, timed on short runs (before the

@@ -66,6 +66,12 @@ typedef struct {
   const uint32_t *ranks;     /* device, column-major [F][ld] */
   const uint8_t *labels;     /* device, [n] */
   const uint32_t *n_unique;  /* device, [F] */
+  /* device word written by an asynchronous mh_rank_encode, or NULL.
+   * subtree_solve and mh_autotune fail with MH_EINVAL when its bit 0 is set
+   * (X held a NaN) and with MH_EDEVICE when a higher bit is (the encoding
+   * failed on the device); subtree_solve reads it with its result, mh_train
+   * and mh_autotune before they start.  The other calls do not read it. */
+  const uint32_t *status;
 } mh_dataset;
 
 /* DE parameters (Section 2 eqs. mutation / crossover / selection; Section
@@ -123,11 +129,17 @@ mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms,
 /* ---------------------------------------------------------------------- */
 
 /* X: device, row-major [n][F] float32.  Writes ranks (device [F][ld],
- * ld >= n) and n_unique (device [F]).  -0 and +0 are one value.  Returns
- * MH_EINVAL (after the kernels ran, since it synchronises to check) if X
- * holds a NaN.  Synchronises the stream. */
+ * ld >= n; columns n..ld-1 are left unwritten) and n_unique (device [F]).
+ * -0 and +0 are one value.
+ * status == NULL: synchronises the stream and returns MH_EINVAL if X holds
+ * a NaN (MH_EDEVICE if the encoding failed on the device).
+ * status != NULL (a device word): returns once the work is queued; the
+ * device sets *status to 0 when the ranks are valid, bit 0 if X holds a
+ * NaN, and higher bits if the encoding failed on the device.  Pass it on in
+ * mh_dataset.status to have the solving calls check it. */
 mh_status mh_rank_encode(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F,
-                         uint32_t ld, uint32_t *ranks, uint32_t *n_unique);
+                         uint32_t ld, uint32_t *ranks, uint32_t *n_unique,
+                         uint32_t *status);
 
 /* ---------------------------------------------------------------------- */
 /* a2. Decoding individuals (Section 3.1, eq. aenc and eq. benc).           */

@@ -36,7 +36,8 @@ class MhError(RuntimeError):
 
 class DatasetC(C.Structure):
     _fields_ = [("n", C.c_uint32), ("F", C.c_uint32), ("K", C.c_uint32), ("ld", C.c_uint32),
-                ("ranks", C.c_void_p), ("labels", C.c_void_p), ("n_unique", C.c_void_p)]
+                ("ranks", C.c_void_p), ("labels", C.c_void_p), ("n_unique", C.c_void_p),
+                ("status", C.c_void_p)]
 
 
 class DEParamsC(C.Structure):
@@ -86,7 +87,7 @@ def load_library(path: str = LIB_PATH):
         "mh_ctx_profile": ([V, C.c_int], I32),
         "mh_ctx_stats": ([V, C.POINTER(U64), C.POINTER(D), C.POINTER(U64), C.POINTER(U64), C.c_int],
                          I32),
-        "mh_rank_encode": ([V, V, U32, U32, U32, V, V], I32),
+        "mh_rank_encode": ([V, V, U32, U32, U32, V, V, V], I32),
         "tree_decode": ([V, V, U32, U32, U32, V, V, V], I32),
         "fitness_eval": ([V, C.POINTER(DatasetC), V, U32, V, V, U32, U32, U32, D, V, V, V, V], I32),
         "mh_tileset_bytes": ([U32, U32, U32, C.POINTER(C.c_size_t)], I32),
@@ -192,6 +193,7 @@ class Dataset:
     n: int
     F: int
     K: int
+    status: object = None  # torch.int32 [1] from rank_encode(..., status=...), or None
 
     @property
     def ld(self) -> int:
@@ -199,20 +201,25 @@ class Dataset:
 
     def cstruct(self) -> DatasetC:
         return DatasetC(self.n, self.F, self.K, self.ld, self.ranks.data_ptr(),
-                        self.labels.data_ptr(), self.n_unique.data_ptr())
+                        self.labels.data_ptr(), self.n_unique.data_ptr(),
+                        None if self.status is None else self.status.data_ptr())
 
 
-def rank_encode(X, ctx: Context | None = None, pad_to: int = 256):
+def rank_encode(X, ctx: Context | None = None, pad_to: int = 256, status=None):
     """mh_rank_encode: X float32 [n][F] (torch, on the device) -> (ranks
-    int32 [F][ld], n_unique int32 [F]) with ld = n rounded up to pad_to."""
+    int32 [F][ld], n_unique int32 [F]) with ld = n rounded up to pad_to (the
+    padding columns are left unwritten).  With `status` (a device int32
+    tensor of one element) the call does not wait: the device writes the
+    NaN / failure status there (pass it on to Dataset)."""
     torch = _torch()
     ctx = ctx or default_context()
     X = X.contiguous()
     n, F = X.shape
     ld = max(pad_to, ((n + pad_to - 1) // pad_to) * pad_to)
-    ranks = torch.zeros((F, ld), dtype=torch.int32, device=X.device)
-    nu = torch.zeros(F, dtype=torch.int32, device=X.device)
-    ctx.check(ctx.lib.mh_rank_encode(ctx.h, _ptr(X), n, F, ld, _ptr(ranks), _ptr(nu)))
+    ranks = torch.empty((F, ld), dtype=torch.int32, device=X.device)
+    nu = torch.empty(F, dtype=torch.int32, device=X.device)
+    ctx.check(ctx.lib.mh_rank_encode(ctx.h, _ptr(X), n, F, ld, _ptr(ranks), _ptr(nu),
+                                     _ptr(status)))
     return ranks, nu
 
 

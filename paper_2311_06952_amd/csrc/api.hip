@@ -38,6 +38,18 @@ uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu) {
 
 constexpr size_t PROF_MAX_PAIRS = 4096;
 
+uint32_t *host_words(Ctx *ctx) {
+  if (!ctx->hwords) {
+    const hipError_t e = hipHostMalloc((void **)&ctx->hwords, 64 * sizeof(uint32_t));
+    if (e != hipSuccess) {
+      ctx->hwords = nullptr;
+      hip_fail(ctx, e, "hipHostMalloc");
+      return nullptr;
+    }
+  }
+  return ctx->hwords;
+}
+
 mh_status prof_collect(Ctx *ctx) {
   MH_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (size_t i = 0; i + 1 < ctx->prof_used; i += 2) {
@@ -116,6 +128,18 @@ static mh_status check_dataset(Ctx *ctx, const mh_dataset *ds) {
   return MH_OK;
 }
 
+// Reads the dataset's status word, if it has one (synchronises).
+static mh_status check_ds_status(Ctx *ctx, const mh_dataset *ds) {
+  if (!ds->status) return MH_OK;
+  uint32_t *h = host_words(ctx);
+  if (!h) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemcpyAsync(h, ds->status, 4, hipMemcpyDeviceToHost, ctx->stream));
+  MH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h[0] & 1u) return fail(ctx, MH_EINVAL, "X holds a NaN");
+  if (h[0]) return fail(ctx, MH_EDEVICE, "rank encoding failed on the device");
+  return MH_OK;
+}
+
 mh_status check_de(Ctx *ctx, const mh_de_params *p, uint32_t D) {
   if (!p) return fail(ctx, MH_EINVAL, "DE params are null");
   if (p->P < 3 || p->P > MH_MAX_POP) return fail(ctx, MH_EINVAL, "P must be in 3..1024");
@@ -165,7 +189,6 @@ static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   if (!tiles || !cnt) return MH_ENOMEM;
   mh_status s = launch_tile_build(ctx, ds, idx, nullptr, n_sub, 1, tiles, h.total_bytes);
   if (s) return s;
-  MH_HIP(ctx, hipMemsetAsync(cnt, 0, cnt_bytes(1, D, ds->K, P), ctx->stream));
   es.tiles = tiles;
   es.cnt = cnt;
   es.max_tiles = h.max_tiles;
@@ -205,7 +228,8 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
   uint32_t *err = (uint32_t *)arena_get(ctx, "ss_err", 256);
   if (!err) return MH_ENOMEM;
-  MH_HIP(ctx, hipMemsetAsync(err, 0, 4, st));
+  s = launch_zero(ctx, {{es.cnt, es.cnt ? cnt_bytes(1, D, K, P) : 0}, {err, 4}});
+  if (s) return s;
   // g = 0: initialise, decode, evaluate
   s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop, true);
   if (s) return s;
@@ -286,17 +310,24 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   s = eval_trees(ctx, es, f1, t1, 1, D, prm->n_min, prm->alpha, fb);
   ctx->profile = prof;
   if (s) return s;
+  if (!ctx->result) {
+    MH_HIP(ctx, hipHostMalloc((void **)&ctx->result, sizeof(ResultOut)));
+    std::memset(ctx->result, 0, sizeof(ResultOut));
+  }
+  s = launch_pack_result(ctx, D, f1, t1, lab1, corr1, cost1, err, ds->status, ctx->result);
+  if (s) return s;
+  MH_HIP(ctx, hipStreamSynchronize(st));
   std::memset(out, 0, sizeof(*out));
   out->D = D;
-  MH_HIP(ctx, hipMemcpyAsync(out->feat, f1, SB, hipMemcpyDeviceToHost, st));
-  MH_HIP(ctx, hipMemcpyAsync(out->tau, t1, (size_t)SB * 4, hipMemcpyDeviceToHost, st));
-  MH_HIP(ctx, hipMemcpyAsync(out->label, lab1, SL, hipMemcpyDeviceToHost, st));
-  MH_HIP(ctx, hipMemcpyAsync(&out->correct, corr1, 4, hipMemcpyDeviceToHost, st));
-  MH_HIP(ctx, hipMemcpyAsync(&out->cost, cost1, 8, hipMemcpyDeviceToHost, st));
-  uint32_t h_err = 0;
-  MH_HIP(ctx, hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st));
-  MH_HIP(ctx, hipStreamSynchronize(st));
-  if (h_err) return fail(ctx, MH_EDEVICE, "DEOCT grid barrier: a wait gave up");
+  std::memcpy(out->feat, ctx->result->tree.feat, SB);
+  std::memcpy(out->tau, ctx->result->tree.tau, (size_t)SB * 4);
+  std::memcpy(out->label, ctx->result->tree.label, SL);
+  out->correct = ctx->result->tree.correct;
+  out->cost = ctx->result->tree.cost;
+  const uint32_t flag = ctx->result->flag;
+  if (flag & 1u) return fail(ctx, MH_EDEVICE, "DEOCT grid barrier: a wait gave up");
+  if (flag & 2u) return fail(ctx, MH_EINVAL, "X holds a NaN");
+  if (flag) return fail(ctx, MH_EDEVICE, "rank encoding failed on the device");
   (void)K;
   return MH_OK;
 }
@@ -364,6 +395,11 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
     c->c.persist_halves = atoi(v) == 1 ? 1u : 2u;
   if (const char *v = std::getenv("MHDEOCT_PERSIST_BLOCKS_PER_CU"))
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
+  if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_RANK_R")) {
+    const int r = atoi(v);
+    c->c.rank_coop_R = (r >= 256 && r <= 8192 && (r & (r - 1)) == 0) ? (uint32_t)r : 0u;
+  }
   int coop = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
     c->c.coop = coop != 0;
@@ -382,6 +418,8 @@ void mh_ctx_destroy(mh_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->c.stream);
   for (auto &b : ctx->c.arena.bufs) (void)hipFree(b.ptr);
   for (hipEvent_t e : ctx->c.prof_ev) (void)hipEventDestroy(e);
+  if (ctx->c.result) (void)hipHostFree(ctx->c.result);
+  if (ctx->c.hwords) (void)hipHostFree(ctx->c.hwords);
   delete ctx;
 }
 
@@ -411,13 +449,13 @@ mh_status mh_ctx_stats(mh_ctx *ctx, uint64_t *launches, double *ms, uint64_t *ev
 }
 
 mh_status mh_rank_encode(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
-                         uint32_t *ranks, uint32_t *n_unique) {
+                         uint32_t *ranks, uint32_t *n_unique, uint32_t *status) {
   CTX_OR_FAIL(ctx);
   Ctx *c = &ctx->c;
   if (F == 0 || F > MH_MAX_FEATURES) return fail(c, MH_EINVAL, "F must be in 1..255");
   if (ld < n) return fail(c, MH_EINVAL, "ld must be >= n");
   if ((n > 0 && (!X || !ranks)) || !n_unique) return fail(c, MH_EINVAL, "null pointer");
-  return launch_rank_encode(c, X, n, F, ld, ranks, n_unique);
+  return launch_rank_encode(c, X, n, F, ld, ranks, n_unique, status);
 }
 
 mh_status tree_decode(mh_ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
@@ -472,6 +510,8 @@ mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, u
   if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
   EvalSet es;
   s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es);
+  if (s) return s;
+  s = launch_zero(c, {{es.cnt, es.cnt ? cnt_bytes(1, D, ds->K, P) : 0}});
   if (s) return s;
   FitnessOut out;
   out.counts = counts;
@@ -585,6 +625,8 @@ mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, const mh_de
   if (s) return s;
   if (!out) return fail(c, MH_EINVAL, "out is null");
   if (generations == 0) return fail(c, MH_EINVAL, "generations must be >= 1");
+  s = check_ds_status(c, ds);
+  if (s) return s;
   // candidates: the whole-run kernel with one or two tile streams per block
   // and 1, 2 or 4 blocks per CU, and the per-generation kernels with 1, 2 or
   // 4 fitness blocks per CU
@@ -663,6 +705,8 @@ mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
   if (flags & ~MH_BATCHED) return fail(c, MH_EINVAL, "unknown flags");
   if ((flags & MH_BATCHED) && (std::min(D_MH, D) > 5 || ds->F > 80))
     return fail(c, MH_EINVAL, "the batched form needs subtree depth <= 5 and F <= 80");
+  s = check_ds_status(c, ds);
+  if (s) return s;
   return mh_train_impl(c, ds, D, D_MH, prm, flags, out, solve_node);
 }
 

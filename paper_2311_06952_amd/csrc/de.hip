@@ -278,4 +278,39 @@ mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, ui
   return MH_OK;
 }
 
+namespace {
+// One solved tree, its labels, correct count, cost and a status word, copied
+// into one record (pinned host memory) so that the host waits once.
+__global__ void k_pack_result(uint32_t D, uint32_t SB, uint32_t SL, const uint8_t *__restrict__ f1,
+                              const uint32_t *__restrict__ t1, const uint8_t *__restrict__ lab1,
+                              const uint32_t *__restrict__ corr1, const double *__restrict__ cost1,
+                              const uint32_t *__restrict__ flag_a,
+                              const uint32_t *__restrict__ flag_b, ResultOut *out) {
+  for (uint32_t i = threadIdx.x; i < SL; i += blockDim.x) {
+    if (i < SB) {
+      out->tree.feat[i] = f1[i];
+      out->tree.tau[i] = t1[i];
+    }
+    out->tree.label[i] = lab1[i];
+  }
+  if (threadIdx.x == 0) {
+    out->tree.D = D;
+    out->tree.correct = *corr1;
+    out->tree.cost = *cost1;
+    const uint32_t a = flag_a ? *flag_a : 0u, b = flag_b ? *flag_b : 0u;
+    out->flag = (a ? 1u : 0u) | (b << 1);
+  }
+}
+}  // namespace
+
+mh_status launch_pack_result(Ctx *ctx, uint32_t D, const uint8_t *f1, const uint32_t *t1,
+                             const uint8_t *lab1, const uint32_t *corr1, const double *cost1,
+                             const uint32_t *flag_a, const uint32_t *flag_b, ResultOut *out) {
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
+  k_pack_result<<<1, 64, 0, ctx->stream>>>(D, SB, SL, f1, t1, lab1, corr1, cost1, flag_a, flag_b,
+                                            out);
+  MH_LAUNCHED(ctx, "k_pack_result");
+  return MH_OK;
+}
+
 }  // namespace mh

@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,8 @@ struct Arena {
   };
   std::vector<Buf> bufs;
 };
+
+struct ResultOut;
 
 struct Ctx {
   int device = 0;
@@ -60,7 +63,17 @@ struct Ctx {
     uint32_t persist, halves, persist_bpc, fit_bpc;
   };
   std::vector<Tuned> tuned;
+  // pinned host record for subtree_solve's result (allocated on first use)
+  ResultOut *result = nullptr;
+  // pinned host words for small status read-backs (allocated on first use)
+  uint32_t *hwords = nullptr;
+  // rank encoding in one cooperative launch when it fits (MHDEOCT_RANK_COOP);
+  // samples per block forced by MHDEOCT_RANK_R (0 = by size)
+  bool rank_coop = true;
+  uint32_t rank_coop_R = 0;
 };
+// 64 pinned host words of the context, or nullptr (error set).
+uint32_t *host_words(Ctx *ctx);
 // Shape key bucket of a tile count: floor(log2(tiles per CU)) + 1 (0 for none).
 uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu);
 
@@ -233,6 +246,29 @@ struct DeDev {
 mh_status launch_de_init(Ctx *ctx, uint32_t P, uint32_t D, uint32_t F, uint64_t seed,
                          const uint64_t *prob_ids, uint64_t prob_base, uint32_t n_problems,
                          const double *warm, uint32_t W, double *pop, bool gene_major);
+// Sets up to MAX_ZERO_RANGES device buffers (byte sizes multiples of 4; null
+// or empty entries are skipped) to zero with one launch on the context's
+// stream.
+constexpr uint32_t MAX_ZERO_RANGES = 8;
+struct ZeroRange {
+  void *ptr;
+  size_t bytes;
+};
+mh_status launch_zero(Ctx *ctx, std::initializer_list<ZeroRange> ranges);
+
+// A solved tree and a status word, written by the device into pinned host
+// memory: bit 0 a device wait gave up, bits 1 and up the rank-encoding status
+// of the data (bit 1: X held a NaN).
+struct ResultOut {
+  mh_tree tree;
+  uint32_t flag;
+};
+// Packs the best tree (f1, t1: its nodes; lab1: leaf labels; corr1, cost1)
+// into *out, on the context's stream, with flag = (*flag_a != 0) |
+// (*flag_b << 1) (a null pointer reads as 0).
+mh_status launch_pack_result(Ctx *ctx, uint32_t D, const uint8_t *f1, const uint32_t *t1,
+                             const uint8_t *lab1, const uint32_t *corr1, const double *cost1,
+                             const uint32_t *flag_a, const uint32_t *flag_b, ResultOut *out);
 mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
                         const uint32_t *n_unique, uint8_t *feat, uint32_t *tau,
                         uint32_t n_problems, const uint32_t *row_sel, bool gene_major);

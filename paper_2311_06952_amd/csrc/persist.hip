@@ -32,6 +32,7 @@
 #include "device_common.h"
 #include "epilogue.h"
 #include "fitness_core.h"
+#include "grid_sync.h"
 #include "internal.h"
 
 namespace mh {
@@ -60,57 +61,6 @@ struct PersistArgs {
   // generation 0 only; 0: tiles are staged every generation
   uint32_t tph;
 };
-
-// A barrier wait gives up after this many ticks of the device wall clock
-// (2 s at its usual 100 MHz), or at once when another block already gave up.
-constexpr uint64_t WAIT_LIMIT_TICKS = 200000000ull;
-
-// Barrier words, each on its own 256-byte line: [0] arrivals of group
-// leaders, [64] release (the number of completed barriers), [128 + 64 g]
-// arrivals in group g of BAR_GROUP consecutive blocks.  A block arrives at its
-// group; the last arrival of a group arrives at the top; the last top arrival
-// publishes the release.  Spreading the arrivals over separate words avoids
-// serialising every block on one address.
-constexpr uint32_t BAR_GROUP = 16;
-__host__ __device__ __forceinline__ uint32_t barrier_words(uint32_t blocks) {
-  return 128 + 64 * ((blocks + BAR_GROUP - 1) / BAR_GROUP);
-}
-
-// Barrier number k (0-based) among the nb blocks of a problem (block b of
-// them), in two parts
-// so that a block can do independent work between arriving and waiting.
-// Arrival: every wave's atomics are complete, then thread 0 arrives.
-__device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t k, uint32_t b, uint32_t nb) {
-  __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's atomics are done
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t grp = b / BAR_GROUP;
-    const uint32_t gsize = min(BAR_GROUP, nb - grp * BAR_GROUP);
-    const uint32_t ngroups = (nb + BAR_GROUP - 1) / BAR_GROUP;
-    const uint32_t old = __hip_atomic_fetch_add(bar + 128 + 64 * grp, 1u, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (old == (k + 1) * gsize - 1) {
-      const uint32_t o2 = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (o2 == (k + 1) * ngroups - 1)
-        __hip_atomic_store(bar + 64, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-// Wait: thread 0 polls the release word, then the block proceeds together.
-__device__ __forceinline__ void barrier_wait(uint32_t *bar, uint32_t k, uint32_t *err) {
-  if (threadIdx.x == 0) {
-    const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(bar + 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > WAIT_LIMIT_TICKS) {
-        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  __syncthreads();
-}
 
 __host__ __device__ __forceinline__ uint32_t align16u(uint32_t x) { return (x + 15u) & ~15u; }
 
@@ -718,9 +668,10 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
     if (!gr.prob_of_block || !gr.ranges) return MH_ENOMEM;
   }
   hipStream_t st = ctx->stream;
-  MH_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n_problems * 3 * cstride * 4, st));
-  MH_HIP(ctx, hipMemsetAsync(bar, 0, (size_t)n_problems * bar_words * 4, st));
-  MH_HIP(ctx, hipMemsetAsync(err, 0, 4, st));
+  mh_status zs = launch_zero(ctx, {{cnt, (size_t)n_problems * 3 * cstride * 4},
+                                   {bar, (size_t)n_problems * bar_words * 4},
+                                   {err, 4}});
+  if (zs) return zs;
   PersistArgs pa;
   pa.hdr = reinterpret_cast<const TileHdr *>(tiles);
   pa.n_unique = n_unique;

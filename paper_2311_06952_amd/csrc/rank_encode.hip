@@ -1,13 +1,27 @@
 // rank_encode.hip -- threshold sets as dense ranks (Section 3.1: the sorted
 // unique values of each feature, generated once at the start).
 //
-// All F columns are sorted together by the composite key
-// (feature << 32 | order-preserving bits of the value) with the sample index
-// as payload, by a stable LSD radix sort (8 bits per pass, 5 passes).  A flag
-// marks every position whose key differs from its predecessor; the inclusive
-// scan of the flags counts distinct (feature, value) pairs, and a sample's
-// rank is that count minus the count at its feature's first position.
+// A sample's rank in feature f is the number of distinct values of f below
+// its value.  Two forms compute it:
+//
+// * one cooperative launch (inputs of up to a few million values): block b
+//   owns a contiguous range of one feature's samples, held in LDS as
+//   (order-preserving value bits << 32 | sample) pairs.  Four stable LSD
+//   radix passes of 8 bits sort every feature's column; per pass each block
+//   publishes its digit histogram and, while a grid barrier completes them,
+//   sorts its pairs by digit in LDS; then it derives its digit offsets
+//   (totals over the feature's blocks, plus the counts of the blocks before
+//   it) and writes each digit's pairs as one contiguous run, and a second
+//   barrier precedes the reload of its range in the new order.  A last pass
+//   flags every position whose value differs from its predecessor, counts the
+//   flags per block, and after a barrier writes each sample's rank (the
+//   flags up to it, minus one) and each feature's distinct-value count.
+// * separate launches (any size): all F columns sorted together by the
+//   composite key (feature << 32 | value bits) with the sample as payload,
+//   by a stable LSD radix sort (8 bits per pass), then distinct-key flags, an
+//   inclusive scan, and the rank scatter.
 #include "device_common.h"
+#include "grid_sync.h"
 #include "internal.h"
 
 namespace mh {
@@ -203,6 +217,241 @@ __global__ void k_rank_write(const uint32_t *__restrict__ vals, const uint32_t *
   if (j == f * n + n - 1) n_unique[f] = U[j] - first + 1u;
 }
 
+
+// ---------------------------------------------------------------------------
+// cooperative form
+// ---------------------------------------------------------------------------
+constexpr uint32_t RC_THREADS = 256;
+constexpr uint32_t RC_WAVES = RC_THREADS / 64;
+constexpr uint32_t RC_MAX_R = 8192;  // samples per block (a multiple of 256)
+constexpr uint32_t RC_BARRIERS = 9;  // 2 per radix pass, 1 before the rank write
+
+__host__ __device__ __forceinline__ uint32_t rc_lds_bytes(uint32_t R) {
+  return R * 16 + RC_WAVES * 256 * 4 + 256 * 4 + 64;
+}
+
+struct RankCoopArgs {
+  const float *X;  // [n][F]
+  uint32_t n, F, ld;
+  uint32_t R, nbf;       // samples per block, blocks per feature
+  uint64_t *buf0, *buf1;  // [F][n] pairs, ping-pong
+  uint32_t *hist;         // [F][nbf][256]
+  uint32_t *dcount;       // [F][nbf]
+  uint32_t *bar, *err, *nan_flag;
+  uint32_t *ranks, *n_unique;
+};
+
+// Cross-block stores and loads go through agent-scope accesses (the L2s of
+// the XCDs are not coherent for ordinary ones).
+template <typename T>
+__device__ __forceinline__ void xst(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T xld(const T *p) {
+  return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan of one value per thread over the block (256 threads);
+// *total receives the sum.  `tmp` holds RC_WAVES + 1 words of LDS.
+__device__ __forceinline__ uint32_t rc_block_exscan(uint32_t v, uint32_t *tmp, uint32_t *total) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[w] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < RC_WAVES; ++q) {
+    const uint32_t t = tmp[q];
+    before += q < w ? t : 0u;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
+  extern __shared__ __align__(16) uint8_t rc_lds[];
+  uint64_t *kv = reinterpret_cast<uint64_t *>(rc_lds);                // [R] the block's range
+  uint64_t *kv2 = kv + a.R;                                          // [R] sorted by digit
+  uint32_t *wcnt = reinterpret_cast<uint32_t *>(rc_lds + a.R * 16);  // [RC_WAVES][256]
+  uint32_t *hb = wcnt + RC_WAVES * 256;                              // [256]
+  uint32_t *tmp = hb + 256;                                          // [16]
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t f = b / a.nbf, j = b % a.nbf;
+  const uint32_t n = a.n;
+  const uint32_t lo = min(n, j * a.R), hi = min(n, lo + a.R), cnt = hi - lo;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const size_t seg = (size_t)f * n;
+  uint32_t k = 0;  // barriers passed
+
+  // load: order-preserving bits of X[i][f] (-0 as +0) with the sample index
+  bool nan = false;
+  for (uint32_t q = tid; q < cnt; q += RC_THREADS) {
+    const float x = a.X[(size_t)(lo + q) * a.F + f];
+    nan |= x != x;
+    uint32_t u = __float_as_uint(x);
+    if (x == 0.0f) u = 0u;
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    kv[q] = ((uint64_t)u << 32) | (uint64_t)(lo + q);
+  }
+  if (__ballot(nan) && lane == 0)
+    __hip_atomic_fetch_or(a.nan_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // wave w handles the span [w0, w1) of S consecutive positions
+  const uint32_t S = ((cnt + RC_THREADS - 1) / RC_THREADS) * 64;
+  const uint32_t w0 = min(cnt, w * S), w1 = min(cnt, w0 + S);
+
+  const uint64_t *src = nullptr;
+  uint64_t *dst = a.buf0;
+  for (uint32_t pass = 0; pass < 4; ++pass) {
+    const uint32_t shift = 32 + 8 * pass;
+    // digit histogram of each wave's span
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) wcnt[w * 256 + q * 64 + lane] = 0;
+    __syncthreads();
+    for (uint32_t q = w0 + lane; q < w1; q += 64)
+      atomicAdd(&wcnt[w * 256 + ((uint32_t)(kv[q] >> shift) & 0xFFu)], 1u);
+    __syncthreads();
+    // the block's histogram is published; in the block's digit-sorted order
+    // digit d starts at hb[d], and wave w's keys of digit d at wcnt[w][d]
+    {
+      uint32_t c[RC_WAVES], tot = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < RC_WAVES; ++q) {
+        c[q] = wcnt[q * 256 + tid];
+        tot += c[q];
+      }
+      xst(a.hist + ((size_t)b * 256 + tid), tot);
+      uint32_t all;
+      const uint32_t loc = rc_block_exscan(tot, tmp, &all);
+      hb[tid] = loc;
+      uint32_t run = loc;
+#pragma unroll
+      for (uint32_t q = 0; q < RC_WAVES; ++q) {
+        wcnt[q * 256 + tid] = run;
+        run += c[q];
+      }
+    }
+    barrier_arrive(a.bar, k, b, nb);
+    // meanwhile: the block's keys, stably sorted by digit, into kv2 (a
+    // position's rank among the earlier positions of its wave's span with
+    // the same digit: ballot match over the digit's bits)
+    for (uint32_t q0 = w0; q0 < w1; q0 += 64) {
+      const uint32_t q = q0 + lane;
+      const bool valid = q < w1;
+      const uint64_t v = valid ? kv[q] : 0ull;
+      const uint32_t d = (uint32_t)(v >> shift) & 0xFFu;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (uint32_t bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t bal = __ballot(on);
+        peers &= on ? bal : ~bal;
+      }
+      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t c = valid ? wcnt[w * 256 + d] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        if (c + below < cnt) kv2[c + below] = v;
+        if (below == 0) wcnt[w * 256 + d] = c + (uint32_t)__popcll(peers);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    barrier_wait(a.bar, k, a.err);
+    ++k;
+    // global start of the block's keys of digit tid: all smaller digits of
+    // the feature, plus digit tid in the feature's earlier blocks
+    {
+      uint32_t pre = 0, tot = 0;
+      const uint32_t *h = a.hist + (size_t)f * a.nbf * 256 + tid;
+      for (uint32_t j0 = 0; j0 < a.nbf; j0 += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) v[u] = j0 + u < a.nbf ? xld(h + (size_t)(j0 + u) * 256) : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) {
+          tot += v[u];
+          pre += j0 + u < j ? v[u] : 0u;
+        }
+      }
+      uint32_t all;
+      const uint32_t gb = rc_block_exscan(tot, tmp, &all) + pre;
+      hb[tid] = gb - hb[tid];  // kv2[q] of digit d goes to position hb[d] + q
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < cnt; q += RC_THREADS) {
+      const uint64_t v = kv2[q];
+      const uint32_t pos = hb[(uint32_t)(v >> shift) & 0xFFu] + q;
+      if (pos < n)
+        xst(dst + seg + pos, v);
+      else
+        __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    barrier_arrive(a.bar, k, b, nb);
+    barrier_wait(a.bar, k, a.err);
+    ++k;
+    for (uint32_t q = tid; q < cnt; q += RC_THREADS) kv[q] = xld(dst + seg + lo + q);
+    src = dst;
+    dst = dst == a.buf0 ? a.buf1 : a.buf0;
+  }
+  __syncthreads();
+
+  // distinct-value flags of the sorted column: a position starts a new value
+  // when it is the feature's first or its value differs from the previous one
+  const uint64_t prev_lo = lo > 0 ? xld(src + seg + lo - 1) : 0ull;
+  auto flag_at = [&](uint32_t q) -> uint32_t {
+    const uint32_t v = (uint32_t)(kv[q] >> 32);
+    if (q == 0) return (lo == 0 || (uint32_t)(prev_lo >> 32) != v) ? 1u : 0u;
+    return (uint32_t)(kv[q - 1] >> 32) != v ? 1u : 0u;
+  };
+  uint32_t mine = 0;
+  for (uint32_t q = tid; q < cnt; q += RC_THREADS) mine += flag_at(q);
+  uint32_t count;
+  (void)rc_block_exscan(mine, tmp, &count);
+  if (tid == 0) xst(a.dcount + b, count);
+  barrier_arrive(a.bar, k, b, nb);
+  barrier_wait(a.bar, k, a.err);
+  ++k;
+  uint32_t base = 0;
+  {
+    uint32_t part = 0;
+    for (uint32_t jj = tid; jj < j; jj += RC_THREADS)
+      part += xld(a.dcount + (size_t)f * a.nbf + jj);
+    uint32_t all;
+    (void)rc_block_exscan(part, tmp, &all);
+    base = all;
+  }
+  // rank = distinct values up to and including this position, minus one
+  uint32_t carry = base;
+  for (uint32_t c0 = 0; c0 < cnt; c0 += RC_THREADS) {
+    const uint32_t q = c0 + tid;
+    const uint32_t fl = q < cnt ? flag_at(q) : 0u;
+    uint32_t chunk;
+    const uint32_t ex = rc_block_exscan(fl, tmp, &chunk);
+    if (q < cnt) {
+      const uint32_t i = (uint32_t)kv[q];
+      if (i < n)
+        a.ranks[(size_t)f * a.ld + i] = carry + ex + fl - 1u;
+      else
+        __hip_atomic_fetch_or(a.err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    carry += chunk;
+  }
+  if (j == a.nbf - 1 && tid == 0) a.n_unique[f] = base + count;
+  // a caller that takes the NaN flag sees a failure there too (bit 1 and up)
+  if (tid == 0) {
+    const uint32_t e = xld(a.err);
+    if (e) __hip_atomic_fetch_or(a.nan_flag, e << 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  (void)RC_BARRIERS;
+}
 }  // namespace
 
 mh_status scan_u32(Ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, bool inclusive) {
@@ -248,46 +497,132 @@ mh_status radix_sort_pairs(Ctx *ctx, uint64_t **keys, uint32_t **vals, uint64_t 
   return MH_OK;
 }
 
+namespace {
+// Samples per block of the cooperative form for an n x F input, or 0 when it
+// does not apply: the smallest power of two from 256 that keeps the grid
+// within four blocks per CU (grids of six blocks per CU, although accepted
+// by the launch, did not all become resident together) and within what the
+// occupancy query allows.
+uint32_t rank_coop_R(Ctx *ctx, uint32_t n, uint32_t F) {
+  if (!ctx->coop || !ctx->rank_coop) return 0;
+  const uint64_t target = (uint64_t)ctx->num_cu * 4u;
+  for (uint32_t R = 256; R <= RC_MAX_R; R *= 2) {
+    if (ctx->rank_coop_R && R != ctx->rank_coop_R) continue;
+    const uint64_t grid = (uint64_t)F * ((n + R - 1) / R);
+    if (grid > target) continue;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank_coop, RC_THREADS,
+                                                     rc_lds_bytes(R)) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    if ((uint64_t)per_cu * ctx->num_cu >= grid) return R;
+  }
+  return 0;
+}
+
+// The cooperative form; *used = false leaves the work to the separate
+// launches (a shape the cooperative launch refuses).
+mh_status rank_encode_coop(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
+                           uint32_t R, uint32_t *ranks, uint32_t *n_unique, uint32_t *nan_flag,
+                           uint32_t *err, uint32_t *bar, bool *used) {
+  *used = false;
+  const uint32_t nbf = (n + R - 1) / R, grid = F * nbf;
+  const size_t total = (size_t)n * F;
+  RankCoopArgs a;
+  a.X = X;
+  a.n = n;
+  a.F = F;
+  a.ld = ld;
+  a.R = R;
+  a.nbf = nbf;
+  a.buf0 = (uint64_t *)arena_get(ctx, "re_keys_a", total * 8);
+  a.buf1 = (uint64_t *)arena_get(ctx, "re_keys_b", total * 8);
+  a.hist = (uint32_t *)arena_get(ctx, "re_hist", (size_t)grid * 256 * 4);
+  a.dcount = (uint32_t *)arena_get(ctx, "re_dcount", (size_t)grid * 4);
+  a.bar = bar;
+  if (!a.buf0 || !a.buf1 || !a.hist || !a.dcount) return MH_ENOMEM;
+  a.err = err;
+  a.nan_flag = nan_flag;
+  a.ranks = ranks;
+  a.n_unique = n_unique;
+  void *args[] = {&a};
+  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rank_coop), dim3(grid),
+                                            dim3(RC_THREADS), args, rc_lds_bytes(R), ctx->stream);
+  if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
+      e == hipErrorInvalidConfiguration) {
+    (void)hipGetLastError();
+    return MH_OK;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "k_rank_coop");
+  *used = true;
+  return MH_OK;
+}
+}  // namespace
+
 mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
                              uint32_t *ranks, uint32_t *n_unique, uint32_t *nan_out) {
   uint64_t total64 = (uint64_t)n * F;
   if (total64 >= 0xFFFFFFFFull) return fail(ctx, MH_EINVAL, "n * F too large");
   uint32_t total = (uint32_t)total64;
+  hipStream_t st = ctx->stream;
   if (total == 0) {
-    MH_HIP(ctx, hipMemsetAsync(n_unique, 0, (size_t)F * 4, ctx->stream));
-    if (nan_out) MH_HIP(ctx, hipMemsetAsync(nan_out, 0, 4, ctx->stream));
+    MH_HIP(ctx, hipMemsetAsync(n_unique, 0, (size_t)F * 4, st));
+    if (nan_out) MH_HIP(ctx, hipMemsetAsync(nan_out, 0, 4, st));
     return MH_OK;
   }
-  uint64_t *ka = (uint64_t *)arena_get(ctx, "re_keys_a", (size_t)total * 8);
-  uint64_t *kb = (uint64_t *)arena_get(ctx, "re_keys_b", (size_t)total * 8);
-  uint32_t *va = (uint32_t *)arena_get(ctx, "re_vals_a", (size_t)total * 4);
-  uint32_t *vb = (uint32_t *)arena_get(ctx, "re_vals_b", (size_t)total * 4);
-  uint32_t *flags = (uint32_t *)arena_get(ctx, "re_flags", (size_t)total * 4 + 256);
-  if (!ka || !kb || !va || !vb || !flags) return MH_ENOMEM;
-  uint32_t *nan_flag = nan_out ? nan_out : flags + ((total + 63u) & ~63u);
-  hipStream_t st = ctx->stream;
-  MH_HIP(ctx, hipMemsetAsync(nan_flag, 0, 4, st));
-  uint32_t blocks = (total + 255) / 256;
-  k_rank_keys<<<blocks, 256, 0, st>>>(X, n, F, ka, va, nan_flag);
-  MH_LAUNCHED(ctx, "k_rank_keys");
-  uint32_t fbits = 32;
-  while ((1u << (fbits - 32)) < F && fbits < 40) fbits += 1;  // bits for the feature id
-  uint32_t key_bits = ((fbits + 7) / 8) * 8;
-  uint64_t *keys = ka;
-  uint32_t *vals = va;
-  mh_status s = radix_sort_pairs(ctx, &keys, &vals, kb, vb, total, key_bits);
-  if (s) return s;
-  k_rank_flags<<<blocks, 256, 0, st>>>(keys, total, flags);
-  MH_LAUNCHED(ctx, "k_rank_flags");
-  s = scan_u32(ctx, flags, flags, total, true);
-  if (s) return s;
-  k_rank_write<<<blocks, 256, 0, st>>>(vals, flags, n, total, ld, ranks, n_unique);
-  MH_LAUNCHED(ctx, "k_rank_write");
+  // [0] NaN seen (unless the caller takes it); [1] cooperative-form failure
+  // bits: 1 a grid barrier wait gave up, 2 and 4 an index out of range
+  uint32_t *words = (uint32_t *)arena_get(ctx, "re_words", 256);
+  if (!words) return MH_ENOMEM;
+  uint32_t *nan_flag = nan_out ? nan_out : words;
+  // the cooperative form's barrier words are cleared with the flags
+  const uint32_t R = rank_coop_R(ctx, n, F);
+  const size_t bar_bytes = R ? (size_t)barrier_words(F * ((n + R - 1) / R)) * 4 : 0;
+  uint32_t *bar = R ? (uint32_t *)arena_get(ctx, "re_bar", bar_bytes) : nullptr;
+  if (R && !bar) return MH_ENOMEM;
+  mh_status zs = launch_zero(ctx, {{words, 8}, {nan_out, nan_out ? 4u : 0u}, {bar, bar_bytes}});
+  if (zs) return zs;
+  bool done = false;
+  if (R) {
+    mh_status s =
+        rank_encode_coop(ctx, X, n, F, ld, R, ranks, n_unique, nan_flag, words + 1, bar, &done);
+    if (s) return s;
+  }
+  if (!done) {
+    uint64_t *ka = (uint64_t *)arena_get(ctx, "re_keys_a", (size_t)total * 8);
+    uint64_t *kb = (uint64_t *)arena_get(ctx, "re_keys_b", (size_t)total * 8);
+    uint32_t *va = (uint32_t *)arena_get(ctx, "re_vals_a", (size_t)total * 4);
+    uint32_t *vb = (uint32_t *)arena_get(ctx, "re_vals_b", (size_t)total * 4);
+    uint32_t *flags = (uint32_t *)arena_get(ctx, "re_flags", (size_t)total * 4 + 256);
+    if (!ka || !kb || !va || !vb || !flags) return MH_ENOMEM;
+    uint32_t blocks = (total + 255) / 256;
+    k_rank_keys<<<blocks, 256, 0, st>>>(X, n, F, ka, va, nan_flag);
+    MH_LAUNCHED(ctx, "k_rank_keys");
+    uint32_t fbits = 32;
+    while ((1u << (fbits - 32)) < F && fbits < 40) fbits += 1;  // bits for the feature id
+    uint32_t key_bits = ((fbits + 7) / 8) * 8;
+    uint64_t *keys = ka;
+    uint32_t *vals = va;
+    mh_status s = radix_sort_pairs(ctx, &keys, &vals, kb, vb, total, key_bits);
+    if (s) return s;
+    k_rank_flags<<<blocks, 256, 0, st>>>(keys, total, flags);
+    MH_LAUNCHED(ctx, "k_rank_flags");
+    s = scan_u32(ctx, flags, flags, total, true);
+    if (s) return s;
+    k_rank_write<<<blocks, 256, 0, st>>>(vals, flags, n, total, ld, ranks, n_unique);
+    MH_LAUNCHED(ctx, "k_rank_write");
+  }
   if (nan_out) return MH_OK;
-  uint32_t h_nan = 0;
-  MH_HIP(ctx, hipMemcpyAsync(&h_nan, nan_flag, 4, hipMemcpyDeviceToHost, st));
+  uint32_t *h = host_words(ctx);
+  if (!h) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemcpyAsync(h, words, 8, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipStreamSynchronize(st));
-  if (h_nan) return fail(ctx, MH_EINVAL, "X holds a NaN");
+  if (h[1])
+    return fail(ctx, MH_EDEVICE, "rank encoding failed on the device (" +
+                                     std::string(h[1] & 1u ? "a grid barrier wait gave up" : "an index out of range") +
+                                     ", code " + std::to_string(h[1]) + ")");
+  if (h[0]) return fail(ctx, MH_EINVAL, "X holds a NaN");
   return MH_OK;
 }
 

@@ -123,30 +123,6 @@ Carve carve(uint32_t n, uint32_t F, uint32_t K, uint32_t D, uint32_t P) {
   return c;
 }
 
-// Result staging in pinned host memory, one per slot.
-struct SlotOut {
-  mh_tree tree;
-  uint32_t nan;
-};
-
-__global__ void k_pack_result(uint32_t SB, uint32_t SL, const uint8_t *__restrict__ f1,
-                              const uint32_t *__restrict__ t1, const uint8_t *__restrict__ lab1,
-                              const uint32_t *__restrict__ corr1, const double *__restrict__ cost1,
-                              const uint32_t *__restrict__ nan, SlotOut *out) {
-  for (uint32_t i = threadIdx.x; i < SL; i += blockDim.x) {
-    if (i < SB) {
-      out->tree.feat[i] = f1[i];
-      out->tree.tau[i] = t1[i];
-    }
-    out->tree.label[i] = lab1[i];
-  }
-  if (threadIdx.x == 0) {
-    out->tree.correct = *corr1;
-    out->tree.cost = *cost1;
-    out->nan = *nan;
-  }
-}
-
 struct Req {
   uint64_t id = 0;
   const float *X = nullptr;
@@ -192,7 +168,7 @@ struct mh_server {
   mh::Pool pool;
   uint32_t max_slots = 0;
   std::vector<int> free_slots;
-  mh::SlotOut *pinned = nullptr;
+  mh::ResultOut *pinned = nullptr;
   std::vector<hipEvent_t> slot_ev;
   std::deque<mh::Req> queue;
   std::vector<mh::Req> active;    // generating
@@ -257,11 +233,11 @@ mh_status retire(mh_server *s, Req &q) {
                            q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1), 1, q.D,
                            q.prm.n_min, q.prm.alpha, q.at<uint32_t>(q.cv.cnt), fb);
   if (r) return r;
-  k_pack_result<<<1, 256, 0, c->stream>>>(SB, SL, q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1),
-                                          q.at<uint8_t>(q.cv.lab1), q.at<uint32_t>(q.cv.corr1),
-                                          q.at<double>(q.cv.cost1), q.at<uint32_t>(q.cv.nan),
-                                          s->pinned + q.slot);
-  MH_LAUNCHED(c, "k_pack_result");
+  mh_status st = launch_pack_result(c, q.D, q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1),
+                                    q.at<uint8_t>(q.cv.lab1), q.at<uint32_t>(q.cv.corr1),
+                                    q.at<double>(q.cv.cost1), nullptr,
+                                    q.at<uint32_t>(q.cv.nan), s->pinned + q.slot);
+  if (st) return st;
   MH_HIP(c, hipEventRecord(s->slot_ev[q.slot], c->stream));
   return MH_OK;
 }
@@ -282,11 +258,11 @@ mh_status collect(mh_server *s, bool wait) {
       continue;
     }
     if (e != hipSuccess) return hip_fail(c, e, "hipEventQuery");
-    const SlotOut &o = s->pinned[q.slot];
+    const ResultOut &o = s->pinned[q.slot];
     mh_result res;
     std::memset(&res, 0, sizeof(res));
     res.req_id = q.id;
-    res.status = o.nan ? MH_EINVAL : MH_OK;
+    res.status = (o.flag & 2u) ? MH_EINVAL : o.flag ? MH_EDEVICE : MH_OK;
     res.n = q.n;
     res.F = q.F;
     res.K = q.K;
@@ -473,7 +449,7 @@ mh_status mh_server_create(mh_ctx *ctx, uint64_t hbm_budget, uint32_t max_slots,
   s->desc_bytes = desc_capacity(max_slots, (uint32_t)c->num_cu);
   hipError_t e = hipMalloc((void **)&s->pool_base, s->pool_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&s->desc_dev, s->desc_bytes);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&s->pinned, sizeof(SlotOut) * max_slots);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->pinned, sizeof(ResultOut) * max_slots);
   for (int k = 0; k < RING && e == hipSuccess; ++k) {
     e = hipHostMalloc((void **)&s->ring[k], s->desc_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ring_ev[k], hipEventDisableTiming);

@@ -41,8 +41,14 @@ TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems)
 
 namespace {
 
-// The header travels as a kernel argument (no host buffer outlives the call).
-__global__ void k_tile_hdr(TileHdr *__restrict__ dst, TileHdr h) { *dst = h; }
+// The header travels as a kernel argument (no host buffer outlives the call);
+// the per-(subproblem, class) counts that follow start at zero.
+__global__ void k_tile_hdr(TileHdr *__restrict__ dst, TileHdr h, uint32_t *__restrict__ ctot,
+                           uint32_t nseg) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = h;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x)
+    ctot[i] = 0u;
+}
 
 // Per-(subproblem, class) sample counts.
 // Samples with an index >= n, a label >= K or a subproblem >= n_problems are
@@ -240,11 +246,11 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   if (n_problems == 0 || n_problems > 65535) return fail(ctx, MH_EINVAL, "bad subproblem count");
   hipStream_t st = ctx->stream;
   TileHdr *dh = reinterpret_cast<TileHdr *>(base);
-  k_tile_hdr<<<1, 1, 0, st>>>(dh, h);
-  MH_LAUNCHED(ctx, "k_tile_hdr");
   uint8_t *b = reinterpret_cast<uint8_t *>(base);
-  MH_HIP(ctx, hipMemsetAsync(b + h.off_ctot, 0, (size_t)n_problems * ds->K * 4, st));
   const uint32_t nseg = n_problems * ds->K;
+  k_tile_hdr<<<std::min<uint32_t>((nseg + 255) / 256, 256u), 256, 0, st>>>(
+      dh, h, reinterpret_cast<uint32_t *>(b + h.off_ctot), nseg);
+  MH_LAUNCHED(ctx, "k_tile_hdr");
   if (n_sub > 0) {
     uint32_t nb = (n_sub + 255) / 256;
     k_tile_count<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, ds->K, n_problems,

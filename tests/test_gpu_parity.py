@@ -33,6 +33,29 @@ def test_rank_encode(mh, seed, n, F, levels):
     np.testing.assert_array_equal(u32(ds.ranks)[:, :n], want_r)
 
 
+@pytest.mark.parametrize("coop,R", [("1", None), ("0", None), ("1", "256"), ("1", "8192")])
+@pytest.mark.parametrize("seed,n,F,levels", [(8, 1, 3, None), (9, 257, 5, 4), (10, 20_000, 7, None),
+                                             (11, 100_000, 16, 1000)])
+def test_rank_encode_forms(mh, monkeypatch, coop, R, seed, n, F, levels):
+    """The cooperative launch (several samples-per-block choices) and the
+    separate launches give the oracle's ranks."""
+    from paper_2311_06952_amd import capi
+    monkeypatch.setenv("MHDEOCT_RANK_COOP", coop)
+    if R:
+        monkeypatch.setenv("MHDEOCT_RANK_R", R)
+    ctx = capi.Context(0)
+    X, y = synth.random_small(seed, n, F, 3, levels)
+    want_r, want_nu = oracle.rank_encode(X)
+    ds = mh.dataset(X, y, 3, ctx=ctx)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :n], want_r)
+    Xn = X.copy()
+    Xn[n // 2, F - 1] = np.nan
+    with pytest.raises(mh.MhError):
+        mh.dataset(Xn, y, 3, ctx=ctx)
+    ctx.close()
+
+
 def test_rank_encode_signed_zero_and_nan(mh):
     X = np.array([[0.0, 1.0], [-0.0, 1.0], [-2.5, np.inf], [3.0, -np.inf]], dtype=np.float32)
     want_r, want_nu = oracle.rank_encode(X)
@@ -216,6 +239,36 @@ def test_subtree_solve_plain_small(mh, seed):
     want, got, ods = _deoct_both(mh, w, 1000 + seed)
     _same_tree(want, got)
     assert got["correct"] <= oracle.opt2(ods)[0]
+
+
+def test_async_rank_status(mh):
+    """Rank encoding that does not wait: its status word, carried by the
+    dataset, is read with subtree_solve's result (NaN -> MH_EINVAL) and
+    before mh_train and mh_autotune start; valid data solve as usual."""
+    import torch
+    from paper_2311_06952_amd import capi
+    w = synth.plain_small(7)
+    Xd = torch.as_tensor(w.X).cuda()
+    yd = torch.as_tensor(w.y).cuda()
+    status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1007)
+    ranks, nu = mh.rank_encode(Xd, status=status)
+    got = mh.subtree_solve(mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status), w.D, prm)
+    assert int(status.item()) == 0
+    want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D,
+                        oracle.de_params(w.P, w.G, w.M, w.CR, 1007))
+    _same_tree(want, got)
+    Xn = Xd.clone()
+    Xn[w.n // 3, 1] = float("nan")
+    ranks, nu = mh.rank_encode(Xn, status=status)
+    bad = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
+    for call in (lambda: mh.subtree_solve(bad, w.D, prm),
+                 lambda: mh.mh_train(bad, 3, 2, prm),
+                 lambda: mh.autotune(bad, w.D, prm, generations=2)):
+        with pytest.raises(mh.MhError) as ei:
+            call()
+        assert ei.value.code == capi.MH_EINVAL
+    assert int(status.item()) & 1 == 1
 
 
 def test_subtree_solve_subset_warm_and_random_m(mh):
