@@ -49,7 +49,8 @@ def cpu_baseline(w, seconds=15.0):
 
 
 KERNEL = "k_deoct_persist<3,4,2>"
-KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "internal.h")
+KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "grid_sync.h",
+                  "internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_deoct_persist_plain_scale_traffic.txt")
 
 
@@ -253,6 +254,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-configuration tuning (size rules and environment)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the serving and moving-horizon measurements")
     ap.add_argument("--extra-only", action="store_true",
@@ -297,7 +300,11 @@ def main():
 
     # launch configuration for this shape, timed on short runs (before the
     # warm-up; it changes timing only)
-    tuned = mh.autotune(ds_of(mh, Xd, yd, w, ctx), w.D, prm, generations=20, ctx=ctx)
+    if args.no_tune:
+        tuned = {"persist": 1, "halves": int(os.environ.get("MHDEOCT_PERSIST_HALVES", "2")),
+                 "persist_blocks_per_cu": 0, "fit_blocks_per_cu": 2, "untuned": True}
+    else:
+        tuned = mh.autotune(ds_of(mh, Xd, yd, w, ctx), w.D, prm, generations=20, ctx=ctx)
 
     for _ in range(args.warmup):
         step()

@@ -392,7 +392,7 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_PERSIST_RESIDENT"))
     c->c.persist_resident = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_PERSIST_HALVES"))
-    c->c.persist_halves = atoi(v) == 1 ? 1u : 2u;
+    c->c.persist_halves = atoi(v) >= 4 ? 4u : (atoi(v) == 1 ? 1u : 2u);
   if (const char *v = std::getenv("MHDEOCT_PERSIST_BLOCKS_PER_CU"))
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
@@ -634,7 +634,7 @@ mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, const mh_de
     uint32_t persist, halves, persist_bpc, fit_bpc;
   };
   std::vector<Cand> cands;
-  for (uint32_t hv : {2u, 1u})
+  for (uint32_t hv : {4u, 2u, 1u})
     for (uint32_t b : {1u, 2u, 4u}) cands.push_back({1u, hv, b, c->fit_blocks_per_cu});
   for (uint32_t b : {1u, 2u, 4u}) cands.push_back({0u, 2u, 0u, b});
   mh_de_params p = *prm;

@@ -53,7 +53,7 @@ struct Ctx {
   bool fuse_de = false;  // fitness and DE step in one launch per generation (MHDEOCT_FUSE_DE=1)
   bool persist = true;   // whole DEOCT runs as one cooperative launch (MHDEOCT_PERSIST=0 turns off)
   uint32_t persist_blocks_per_cu = 0;  // its blocks per CU; 0 = by size (MHDEOCT_PERSIST_BLOCKS_PER_CU)
-  uint32_t persist_halves = 2;         // tile streams per block, 1 or 2 (MHDEOCT_PERSIST_HALVES)
+  uint32_t persist_halves = 2;         // tile streams per block, 1, 2 or 4 (MHDEOCT_PERSIST_HALVES)
   bool persist_resident = true;        // tiles kept in LDS when they fit (MHDEOCT_PERSIST_RESIDENT)
   bool coop = false;     // the device supports cooperative launches
   uint32_t max_lds = 64u * 1024u;  // dynamic LDS one block may use

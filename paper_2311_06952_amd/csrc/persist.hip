@@ -96,46 +96,60 @@ __device__ __forceinline__ void wave_argmin(double &c, uint32_t &i) {
   i = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
 }
 
+// LDS after n_unique: argmin scratch (32 costs, 32 indices) and the info
+// words of resident tiles (MAX_TPH per group, 4 groups at most).
+constexpr uint32_t MAX_TPH = 32;
+constexpr uint32_t PERSIST_TAIL = 32 * 8 + 32 * 4 + 4 * MAX_TPH * 4;
+
+// Bytes of one count-merge slot: a group's open class and its counts per
+// tree.
+__host__ __device__ __forceinline__ uint32_t persist_merge_slot(uint32_t SB, uint32_t P) {
+  return align16u(P * 4 + SB * P * 4);
+}
 // Bytes the exchanges need in the first tile buffer: decoded nodes (feature
-// byte and threshold per node and tree), or the second half's class and
-// counts per tree.
-__host__ __device__ __forceinline__ uint32_t persist_exchange_bytes(uint32_t SB, uint32_t P) {
+// byte and threshold per node and tree), or H / 2 count-merge slots.
+__host__ __device__ __forceinline__ uint32_t persist_exchange_bytes(uint32_t SB, uint32_t P,
+                                                                   uint32_t H) {
   const uint32_t nodes = align16u(SB * P) + SB * P * 4;
-  const uint32_t counts = P * 4 + SB * P * 4;
+  const uint32_t counts = (H / 2) * persist_merge_slot(SB, P);
   return nodes > counts ? nodes : counts;
 }
 // The first tile buffer, large enough for the exchanges.
-__host__ __device__ __forceinline__ uint32_t persist_slot_a(uint32_t F, uint32_t SB, uint32_t P) {
+__host__ __device__ __forceinline__ uint32_t persist_slot_a(uint32_t F, uint32_t SB, uint32_t P,
+                                                           uint32_t H) {
   const uint32_t tile = align16u(mask_region(F) + F * MCOL);
-  const uint32_t x = align16u(persist_exchange_bytes(SB, P));
+  const uint32_t x = align16u(persist_exchange_bytes(SB, P, H));
   return tile > x ? tile : x;
 }
-// LDS: first tile buffer (also the exchange area) | second tile buffer
-// (H = 2) | rows [m][P] f64 | n_unique [F] | argmin scratch.
+// LDS: first tile buffer (also the exchange area) | H - 1 more tile buffers
+// | rows [m][P] f64 | n_unique [F] | argmin scratch.
 __host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint32_t P, uint32_t SB,
                                                               uint32_t H) {
   const uint32_t tile = align16u(mask_region(F) + F * MCOL);
-  return persist_slot_a(F, SB, P) + (H - 1) * tile + align16u(2 * SB * P * 8) + align16u(F * 4) +
-         32 * 8 + 32 * 4;
+  return persist_slot_a(F, SB, P, H) + (H - 1) * tile + align16u(2 * SB * P * 8) +
+         align16u(F * 4) + PERSIST_TAIL;
 }
 
-// Two-wave-group layout (H = 2): the block holds two copies of the
-// population's lanes; half h (threads h * NTH ..) counts every other tile
-// of the block's range in its own staging buffer, so two tiles are in flight
-// per block, and in the DE phase half h makes the genes of its share of the
-// nodes (half 0 the first (SB + 1) / 2 nodes, half 1 the rest).  Decoded
-// nodes are exchanged through LDS so that both halves evaluate whole trees.
-template <int D, int WAVES, int H>
+// Wave groups (H = 1, 2 or 4): the block holds H copies of the population's
+// lanes; group h (threads h * NTH ..) counts every H-th tile of the block's
+// range in its own staging buffer, so H tiles are in flight per block, and
+// in the DE phase group h makes the genes of its share of the nodes (nodes
+// h * NA .. with NA = ceil(SB / H)).  Decoded nodes are exchanged through
+// LDS so that every group evaluates whole trees.
+template <int D, int WAVES, int H, bool RES>
 __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   constexpr int SB = (1 << D) - 1, SL = 1 << D, m = 2 * SB;
   constexpr uint32_t NTH = WAVES * 64, NT = H * NTH;
-  constexpr int NA = H == 1 ? SB : (SB + 1) / 2;  // nodes of half 0
+  constexpr int NA = (SB + H - 1) / H;  // nodes per group (the last may have fewer)
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t P = pa.P, Ppad = pad64(P), K = pa.K, F = pa.F;
-  const uint32_t h = threadIdx.x / NTH, r = threadIdx.x % NTH;
+  // wave groups are whole waves, so the group index is wave-uniform
+  const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / NTH));
+  uint32_t r = threadIdx.x % NTH;
   const bool live = r < P;
   const uint32_t rr = live ? r : 0u;
-  const int n_lo = h == 0 ? 0 : NA, n_hi = h == 0 ? NA : SB;  // this half's nodes
+  const int n_lo = (int)h * NA < SB ? (int)h * NA : SB;  // this group's nodes
+  const int n_hi = n_lo + NA < SB ? n_lo + NA : SB;
 
   const uint8_t *base = reinterpret_cast<const uint8_t *>(pa.hdr);
   uint32_t s_prob = 0, b = blockIdx.x, nb = gridDim.x, T0 = 0, T1 = pa.hdr->n_tiles;
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   const uint32_t t_begin = T0 + (uint32_t)((uint64_t)(T1 - T0) * b / nb);
   const uint32_t t_end = T0 + (uint32_t)((uint64_t)(T1 - T0) * (b + 1) / nb);
   uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
-  if (pa.tph && rounds > pa.tph) {
+  if ((RES || pa.tph) && rounds > pa.tph) {
     // more tiles than resident slots: cannot happen with the host's bound;
     // stay inside the LDS and report
     rounds = pa.tph;
@@ -169,40 +183,56 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   const uint32_t tph = pa.tph;
   // staged every generation: one buffer per half, the first also the
   // exchange area; resident: the exchange area, then tph slots per half
-  const uint32_t slot_a = persist_slot_a(F, SB, P);
-  const uint32_t x_bytes = align16u(persist_exchange_bytes(SB, P));
-  const uint32_t tile_off = tph ? x_bytes + h * tph * tile_lds : (h == 0 ? 0u : slot_a);
+  const uint32_t slot_a = persist_slot_a(F, SB, P, H);
+  const uint32_t x_bytes = align16u(persist_exchange_bytes(SB, P, H));
+  const uint32_t tile_off =
+      tph ? x_bytes + h * tph * tile_lds : (h == 0 ? 0u : slot_a + (h - 1) * tile_lds);
   const uint32_t rows_off = tph ? x_bytes + H * tph * tile_lds : slot_a + (H - 1) * tile_lds;
   double *rows = reinterpret_cast<double *>(lds + rows_off);
   uint32_t *s_nu = reinterpret_cast<uint32_t *>(lds + rows_off + align16u(m * P * 8));
   double *s_cost = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(s_nu) + align16u(F * 4));
   uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_cost + 32);
+  uint32_t *s_info = s_idx + 32;  // [H][MAX_TPH] info words of resident tiles
   // exchanges at the start of LDS
   uint8_t *x_feat = lds;                                              // [SB][P]
   uint32_t *x_thr = reinterpret_cast<uint32_t *>(lds + align16u(SB * P));  // [SB][P]
-  uint32_t *x_cls = reinterpret_cast<uint32_t *>(lds);                // [P]
-  uint32_t *x_acc = reinterpret_cast<uint32_t *>(lds + P * 4);         // [SB][P]
+  const uint32_t mslot = persist_merge_slot(SB, P);  // count-merge slot i at lds + i * mslot:
+                                                     // class [P], then counts [SB][P]
   const uint32_t s0 =
       (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds) + tile_off;
   const uint32_t kmask = s0 + mregion - 2u * s0;
 
   for (uint32_t f = threadIdx.x; f < F; f += NT) s_nu[f] = pa.n_unique[f];
-  double gp[m], gt[m];
+  // The post-selection population lives in LDS (rows, gene-major [m][P]);
+  // a thread keeps in registers only the trial genes of its half's nodes:
+  // gt[j] and gt[NA + j] are the feature and threshold genes of node
+  // n_lo + j.  Each half writes the rows of its own nodes.
   double *pop_s = pa.pop + (size_t)s_prob * P * m;
+  double gt[2 * NA];
 #pragma unroll
-  for (int q = 0; q < m; ++q) gt[q] = gp[q] = pop_s[(size_t)q * P + rr];
+  for (int j = 0; j < NA; ++j) {
+    const int t = n_lo + j;
+    gt[j] = gt[NA + j] = 0.0;
+    if (t < n_hi && live) {
+      gt[j] = pop_s[(size_t)t * P + r];
+      gt[NA + j] = pop_s[(size_t)(SB + t) * P + r];
+      rows[(size_t)t * P + r] = gt[j];
+      rows[(size_t)(SB + t) * P + r] = gt[NA + j];
+    }
+  }
   __syncthreads();
 
   NodeState<D> ns;
   uint32_t nsplit = 0;
   // decode this half's nodes of `gen`, publish them, then take the whole tree
   // (callers: every thread; contains barriers)
-  auto set_tree = [&](const double (&gen)[m]) {
+  auto set_tree = [&](const double (&gen)[2 * NA]) {
 #pragma unroll
-    for (int t = 0; t < SB; ++t) {
-      if (t >= n_lo && t < n_hi && live) {
+    for (int j = 0; j < NA; ++j) {
+      const int t = n_lo + j;
+      if (t < n_hi && live) {
         uint32_t f = 0, th = 0;
-        decode_node(gen[t], gen[SB + t], F, s_nu, f, th);
+        decode_node(gen[j], gen[NA + j], F, s_nu, f, th);
         x_feat[t * P + r] = (uint8_t)f;
         x_thr[t * P + r] = th;
       }
@@ -219,31 +249,49 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     }
     __syncthreads();  // the exchange area is a tile buffer again
   };
-  set_tree(gp);
+  set_tree(gt);
 
   const size_t cstride = (size_t)SB * K * Ppad;
   const uint64_t key = de_key(pa.seed, pa.prob_ids ? pa.prob_ids[s_prob] : pa.prob);
   uint32_t *cnt3 = pa.cnt + (size_t)s_prob * 3 * cstride;
   uint32_t *bar = pa.bar + (size_t)s_prob * pa.bar_stride;
   double cost_r = 0.0;
-  uint4 pf[PF];
+  constexpr int NPF = RES ? 1 : PF;
+  uint4 pf[NPF];
   auto prefetch = [&](uint32_t tile) {
     const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
+    for (int k = 0; k < NPF; ++k) {
       const uint32_t c = r + k * NTH;
       if (c < nchunk) pf[k] = src[c];
     }
   };
-  // the next tile's info word travels with its prefetch, so that the loop
-  // never waits on it
   uint32_t inf_next = 0;
-  if (t_begin + h < t_end) {
+  if constexpr (RES) {
+    // resident tiles: group h's tiles (t_begin + h, + H, ...) go to its slots
+    // once, with their info words
+    for (uint32_t i = 0; i < rounds; ++i) {
+      const uint32_t tile = t_begin + i * H + h;
+      if (tile >= t_end) break;
+      uint8_t *dst = lds + tile_off + i * tile_lds;
+      const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+      for (uint32_t c = r; c < nchunk; c += NTH) stage_chunk(dst, mregion, F, c, src[c]);
+      if (r == 0) s_info[h * MAX_TPH + i] = info[tile];
+    }
+    __syncthreads();
+  } else if (t_begin + h < t_end) {
+    // the next tile's info word travels with its prefetch, so that the loop
+    // never waits on it
     prefetch(t_begin + h);
     inf_next = info[t_begin + h];
   }
 
   for (uint32_t g = 0; g <= pa.G; ++g) {
+    // with four groups or deep trees the lane index is re-read each
+    // generation, so that the compiler recomputes the addresses derived from
+    // it instead of holding them in registers across the whole loop (1024
+    // threads leave 128 registers per lane; deep trees spill otherwise)
+    if constexpr (H == 4 || D >= 4) asm volatile("" : "+v"(r));
     uint32_t *cnt = cnt3 + (size_t)(g % 3) * cstride;
     {
       uint32_t *z = cnt3 + (size_t)((g + 1) % 3) * cstride;
@@ -264,77 +312,96 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         ns.acc[t] = 0;
       }
     };
-    // resident tiles are staged in generation 0 only
-    const bool stage = tph == 0 || g == 0;
-    for (uint32_t i = 0; i < rounds; ++i) {
-      const uint32_t tile = t_begin + i * H + h;
-      const bool act = tile < t_end;
-      uint8_t *my_tile = lds + tile_off + (tph ? i * tile_lds : 0u);
-      const uint32_t delta = tph ? i * tile_lds : 0u;
-      uint32_t count = 0;
-      if (act) {
-        const uint32_t inf = inf_next;
+    if constexpr (RES) {
+      for (uint32_t i = 0; i < rounds; ++i) {
+        const uint32_t tile = t_begin + i * H + h;
+        if (tile >= t_end) break;
+        const uint32_t inf = s_info[h * MAX_TPH + i];
         const uint32_t cls = (inf >> 8) & 0xFFu;
-        count = inf & 0xFFu;
         if (cls != cur_cls) {
           flush();
           cur_cls = cls;
         }
-      }
-      if (stage) __syncthreads();  // the previous tiles are no longer read
-      if (act && stage) {
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-          const uint32_t c = r + k * NTH;
-          if (c < nchunk) stage_chunk(my_tile, mregion, F, c, pf[k]);
-        }
-        if (nchunk > PF * NTH) {
-          const uint4 *__restrict__ src =
-              reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
-          for (uint32_t c = r + PF * NTH; c < nchunk; c += NTH)
-            stage_chunk(my_tile, mregion, F, c, src[c]);
-        }
-      }
-      if (stage) __syncthreads();
-      if (act) {
-        // the next tile, or this half's first tile again for the next
-        // generation (the layout does not change); resident tiles are not
-        // fetched again after generation 0
-        const uint32_t nxt = tile + H < t_end ? tile + H : t_begin + h;
-        if (tph == 0 || (g == 0 && tile + H < t_end)) prefetch(nxt);
-        inf_next = info[nxt];
         uint64_t R[1 << D];
-        R[1] = (1ull << count) - 1ull;  // count <= 63
-        eval_nodes<D, 1>(kmask, ns, R, delta);
+        R[1] = (1ull << (inf & 0xFFu)) - 1ull;  // count <= 63
+        eval_nodes<D, 1>(kmask, ns, R, i * tile_lds);
+      }
+    } else {
+      for (uint32_t i = 0; i < rounds; ++i) {
+        const uint32_t tile = t_begin + i * H + h;
+        const bool act = tile < t_end;
+        uint8_t *my_tile = lds + tile_off;
+        uint32_t count = 0;
+        if (act) {
+          const uint32_t inf = inf_next;
+          const uint32_t cls = (inf >> 8) & 0xFFu;
+          count = inf & 0xFFu;
+          if (cls != cur_cls) {
+            flush();
+            cur_cls = cls;
+          }
+        }
+        __syncthreads();  // the previous tiles are no longer read
+        if (act) {
+#pragma unroll
+          for (int k = 0; k < NPF; ++k) {
+            const uint32_t c = r + k * NTH;
+            if (c < nchunk) stage_chunk(my_tile, mregion, F, c, pf[k]);
+          }
+          if (nchunk > NPF * NTH) {
+            const uint4 *__restrict__ src =
+                reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+            for (uint32_t c = r + NPF * NTH; c < nchunk; c += NTH)
+              stage_chunk(my_tile, mregion, F, c, src[c]);
+          }
+        }
+        __syncthreads();
+        if (act) {
+          // the next tile, or this group's first tile again for the next
+          // generation (the layout does not change)
+          const uint32_t nxt = tile + H < t_end ? tile + H : t_begin + h;
+          prefetch(nxt);
+          inf_next = info[nxt];
+          uint64_t R[1 << D];
+          R[1] = (1ull << count) - 1ull;  // count <= 63
+          eval_nodes<D, 1>(kmask, ns, R, 0u);
+        }
       }
     }
-    if constexpr (H == 2) {
-      // merge the second half's open counts into the first half's when both
-      // end on the same class (the usual case: tiles are grouped by class)
-      __syncthreads();
-      if (h == 1 && live) {
-        x_cls[r] = cur_cls;
+    if constexpr (H > 1) {
+      // merge the groups' open counts pairwise (group h + w into group h for
+      // w = H / 2, .., 1), adding them when both end on the same class (the
+      // usual case: tiles are grouped by class) and flushing otherwise
 #pragma unroll
-        for (int t = 0; t < SB; ++t) x_acc[t * P + r] = ns.acc[t];
-      }
-      __syncthreads();
-      if (h == 0 && live) {
-        const uint32_t c1 = x_cls[r];
-        if (c1 == cur_cls || cur_cls == 0xFFFFFFFFu) {
-          cur_cls = c1;
+      for (uint32_t w = H / 2; w >= 1; w /= 2) {
+        __syncthreads();
+        if (h >= w && h < 2 * w && live) {
+          uint8_t *sl = lds + (h - w) * mslot;
+          reinterpret_cast<uint32_t *>(sl)[r] = cur_cls;
 #pragma unroll
-          for (int t = 0; t < SB; ++t) ns.acc[t] += x_acc[t * P + r];
-        } else {
-          flush();
-          cur_cls = c1;
-#pragma unroll
-          for (int t = 0; t < SB; ++t) ns.acc[t] = x_acc[t * P + r];
+          for (int t = 0; t < SB; ++t) reinterpret_cast<uint32_t *>(sl + P * 4)[t * P + r] = ns.acc[t];
         }
-      }
-      if (h == 1) {
+        __syncthreads();
+        if (h < w && live) {
+          const uint8_t *sl = lds + h * mslot;
+          const uint32_t c1 = reinterpret_cast<const uint32_t *>(sl)[r];
+          const uint32_t *xa = reinterpret_cast<const uint32_t *>(sl + P * 4);
+          if (c1 == cur_cls || cur_cls == 0xFFFFFFFFu) {
+            if (c1 != 0xFFFFFFFFu) cur_cls = c1;
 #pragma unroll
-        for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
-        cur_cls = 0xFFFFFFFFu;
+            for (int t = 0; t < SB; ++t) ns.acc[t] += xa[t * P + r];
+          } else if (c1 != 0xFFFFFFFFu) {
+            flush();
+            cur_cls = c1;
+#pragma unroll
+            for (int t = 0; t < SB; ++t) ns.acc[t] = xa[t * P + r];
+          }
+        }
+        if (h >= w && h < 2 * w) {
+#pragma unroll
+          for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
+          cur_cls = 0xFFFFFFFFu;
+        }
       }
     }
     flush();
@@ -426,24 +493,25 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       cost_r = tc;
     } else if (tc <= cost_r) {
       cost_r = tc;
+      if (live) {
 #pragma unroll
-      for (int q = 0; q < m; ++q) gp[q] = gt[q];
-    }
-    if (live) {
-#pragma unroll
-      for (int t = 0; t < SB; ++t)
-        if (t >= n_lo && t < n_hi) {
-          rows[(size_t)t * P + r] = gp[t];
-          rows[(size_t)(SB + t) * P + r] = gp[SB + t];
+        for (int j = 0; j < NA; ++j) {
+          const int t = n_lo + j;
+          if (t < n_hi) {
+            rows[(size_t)t * P + r] = gt[j];
+            rows[(size_t)(SB + t) * P + r] = gt[NA + j];
+          }
         }
+      }
     }
 
     // ---- best: lowest index of the minimum cost (both halves hold every
     // individual's cost; duplicates do not change the result)
     double bc = live ? cost_r : DBL_MAX;
     uint32_t bi = r;
+    // (every group holds the same costs: the first group's waves suffice)
     wave_argmin(bc, bi);
-    if ((threadIdx.x & 63u) == 0) {
+    if ((threadIdx.x & 63u) == 0 && h == 0) {
       s_cost[threadIdx.x >> 6] = bc;
       s_idx[threadIdx.x >> 6] = bi;
     }
@@ -451,7 +519,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     bc = s_cost[0];
     bi = s_idx[0];
 #pragma unroll
-    for (uint32_t x = 1; x < NT / 64; ++x) {
+    for (uint32_t x = 1; x < NTH / 64; ++x) {
       const double c2 = s_cost[x];
       const uint32_t i2 = s_idx[x];
       const bool better = (c2 < bc) | ((c2 == bc) & (i2 < bi));
@@ -462,11 +530,13 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     if (g == pa.G) {
       if (b == 0 && live) {
 #pragma unroll
-        for (int t = 0; t < SB; ++t)
-          if (t >= n_lo && t < n_hi) {
-            pop_s[(size_t)t * P + r] = gp[t];
-            pop_s[(size_t)(SB + t) * P + r] = gp[SB + t];
+        for (int j = 0; j < NA; ++j) {
+          const int t = n_lo + j;
+          if (t < n_hi) {
+            pop_s[(size_t)t * P + r] = rows[(size_t)t * P + r];
+            pop_s[(size_t)(SB + t) * P + r] = rows[(size_t)(SB + t) * P + r];
           }
+        }
         if (h == 0) pa.cost[(size_t)s_prob * P + r] = cost_r;
       }
       if (b == 0 && threadIdx.x == 0) pa.best[s_prob] = bst;
@@ -478,8 +548,9 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     if (live) {
       const double Fp1 = (double)F + 1.0;
 #pragma unroll
-      for (int t = 0; t < SB; ++t) {
-        if (t < n_lo || t >= n_hi) continue;
+      for (int j = 0; j < NA; ++j) {
+        const int t = n_lo + j;
+        if (t >= n_hi) continue;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
           const int q = t + (hh ? SB : 0);
@@ -488,7 +559,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
           const double hiq = hh ? 1.0 : Fp1;
           if (!(v >= 0.0)) v = 0.0;
           if (v > hiq) v = hiq;
-          gt[q] = ((cross >> q) & 1ull) ? v : gp[q];
+          gt[j + (hh ? NA : 0)] = ((cross >> q) & 1ull) ? v : rows[(size_t)q * P + r];
         }
       }
     }
@@ -517,15 +588,23 @@ struct Groups {
   uint4 *ranges;
 };
 
+// Four wave groups exist only with resident tiles (staging every generation
+// needs registers that four groups per block do not have).
 template <int D, int WAVES, int H>
 mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles,
                    const Groups &gr, bool *used) {
-  auto kern = k_deoct_persist<D, WAVES, H>;
+  const void *kres = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, true>);
+  const void *kstage = nullptr;
+  if constexpr (H < 4) kstage = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false>);
+  const void *kern = kstage ? kstage : kres;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, H * WAVES * 64, lds) !=
           hipSuccess ||
-      per_cu < 1)
-    return MH_OK;  // not co-resident: the caller takes the per-generation kernels
+      per_cu < 1) {
+    (void)hipGetLastError();
+    return MH_OK;  // not co-resident: the caller tries fewer groups, then the
+                   // per-generation kernels
+  }
   const uint32_t want = persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
   // with many tiles per CU the tile work dominates, and the per-generation
   // kernels win where they keep more waves per CU busy than the whole-run
@@ -542,7 +621,10 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
   }
   uint32_t bpc = ctx->persist_blocks_per_cu ? ctx->persist_blocks_per_cu : want;
   bpc = bpc < (uint32_t)per_cu ? bpc : (uint32_t)per_cu;
-  bpc = bpc > 8u ? 8u : bpc;
+  // at most four blocks per CU: a cooperative grid of about six blocks per CU
+  // (of another kernel) was accepted by the launch but did not become
+  // resident all at once
+  bpc = bpc > 4u ? 4u : bpc;
   uint32_t grid = (uint32_t)ctx->num_cu * (bpc ? bpc : 1u);
   PersistArgs a = pa;
   a.tph = 0;
@@ -586,21 +668,25 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
     const uint32_t SB = (1u << D) - 1u;
     const uint32_t tph = (per_block + H - 1) / H;
     const uint32_t tile = align16u(mask_region(pa.F) + pa.F * MCOL);
-    const uint64_t need = (uint64_t)align16u(persist_exchange_bytes(SB, pa.P)) +
+    const uint64_t need = (uint64_t)align16u(persist_exchange_bytes(SB, pa.P, H)) +
                           (uint64_t)H * tph * tile + align16u(2 * SB * pa.P * 8) +
-                          align16u(pa.F * 4) + 32 * 8 + 32 * 4;
+                          align16u(pa.F * 4) + PERSIST_TAIL;
     int per_cu_res = 0;
-    if (tph >= 1 && tph <= 32 && need <= ctx->max_lds &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_res, kern, H * WAVES * 64,
+    if (tph >= 1 && tph <= MAX_TPH && need <= ctx->max_lds &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_res, kres, H * WAVES * 64,
                                                      (size_t)need) == hipSuccess &&
         (uint64_t)per_cu_res * ctx->num_cu >= grid) {
       a.tph = tph;
       lds_use = (uint32_t)need;
+      kern = kres;
     }
+    (void)hipGetLastError();
   }
+  if (!a.tph && !kstage) return MH_OK;  // four groups need resident tiles
+  if (!a.tph) kern = kstage;
   void *args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
-                                            dim3(H * WAVES * 64), args, lds_use, ctx->stream);
+  hipError_t e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(H * WAVES * 64), args, lds_use,
+                                            ctx->stream);
   if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
       e == hipErrorInvalidConfiguration) {
     // a shape the launch refuses (LDS, block count): the per-generation
@@ -620,15 +706,16 @@ mh_status launch_d(Ctx *ctx, uint32_t waves, const PersistArgs &pa, uint32_t lds
     case 1: return launch_w<D, 1, H>(ctx, pa, lds, max_tiles, gr, used);
     case 2: return launch_w<D, 2, H>(ctx, pa, lds, max_tiles, gr, used);
     case 4: return launch_w<D, 4, H>(ctx, pa, lds, max_tiles, gr, used);
-    default: return launch_w<D, (H == 2 ? 4 : 8), H>(ctx, pa, lds, max_tiles, gr, used);
+    default: return launch_w<D, (H == 1 ? 8 : 4), H>(ctx, pa, lds, max_tiles, gr, used);
   }
 }
 
 template <int D>
 mh_status launch_dh(Ctx *ctx, uint32_t waves, uint32_t H, const PersistArgs &pa, uint32_t lds,
                     uint32_t max_tiles, const Groups &gr, bool *used) {
-  return H == 2 ? launch_d<D, 2>(ctx, waves, pa, lds, max_tiles, gr, used)
-                : launch_d<D, 1>(ctx, waves, pa, lds, max_tiles, gr, used);
+  if (H == 4) return launch_d<D, 4>(ctx, waves, pa, lds, max_tiles, gr, used);
+  if (H == 2) return launch_d<D, 2>(ctx, waves, pa, lds, max_tiles, gr, used);
+  return launch_d<D, 1>(ctx, waves, pa, lds, max_tiles, gr, used);
 }
 
 // One problem (ptiles == null) or the problems of a multi-problem tile set.
@@ -647,14 +734,14 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   if ((uint64_t)(prm->G + 1) * (uint64_t)ctx->num_cu * 8u >= (1ull << 31)) return MH_OK;
   uint32_t waves = pad64(P) / 64;
   waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
-  // two tile streams per block when the LDS and the 1024-thread limit allow
+  // up to persist_halves tile streams per block, as the LDS and the
+  // 1024-thread limit allow
   const uint32_t max_lds = ctx->max_lds;
-  uint32_t H = (ctx->persist_halves != 1 && waves <= 4 &&
-                persist_lds_bytes(F, P, SB, 2) <= max_lds)
-                   ? 2u
-                   : 1u;
-  const uint32_t lds = persist_lds_bytes(F, P, SB, H);
-  if (lds > max_lds) return MH_OK;
+  uint32_t H = 1;
+  for (uint32_t hh = 2; hh <= 4; hh *= 2)
+    if (ctx->persist_halves >= hh && waves <= 4 && persist_lds_bytes(F, P, SB, hh) <= max_lds)
+      H = hh;
+  if (persist_lds_bytes(F, P, SB, H) > max_lds) return MH_OK;
   (void)m;
   const size_t cstride = (size_t)SB * K * pad64(P);
   const uint32_t bar_words = barrier_words((uint32_t)ctx->num_cu * 8u);
@@ -701,14 +788,18 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));
   mh_status s = MH_OK;
   const uint32_t max_tiles = tile_layout(n_sub, F, K, n_problems).max_tiles;
-  switch (D) {
-    case 1: s = launch_dh<1>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
-    case 2: s = launch_dh<2>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
-    case 3: s = launch_dh<3>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
-    case 4: s = launch_dh<4>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
-    default: s = launch_dh<5>(ctx, waves, H, pa, lds, max_tiles, gr, used); break;
+  // the most wave groups that launch, down to one
+  for (uint32_t hh = H; hh >= 1 && !*used; hh /= 2) {
+    const uint32_t lds_h = persist_lds_bytes(F, P, SB, hh);
+    switch (D) {
+      case 1: s = launch_dh<1>(ctx, waves, hh, pa, lds_h, max_tiles, gr, used); break;
+      case 2: s = launch_dh<2>(ctx, waves, hh, pa, lds_h, max_tiles, gr, used); break;
+      case 3: s = launch_dh<3>(ctx, waves, hh, pa, lds_h, max_tiles, gr, used); break;
+      case 4: s = launch_dh<4>(ctx, waves, hh, pa, lds_h, max_tiles, gr, used); break;
+      default: s = launch_dh<5>(ctx, waves, hh, pa, lds_h, max_tiles, gr, used); break;
+    }
+    if (s) return s;
   }
-  if (s) return s;
   if (timed) {
     MH_HIP(ctx, hipEventRecord(e1, st));
     if (*used) ctx->prof_launches += 1;

@@ -337,6 +337,35 @@ def test_persistent_and_per_generation_deoct_agree(mh, monkeypatch, D, P, K, M):
     ctx_per.close()
 
 
+_GROUP_SHAPES = [(1, 12, 2, 3000, 5), (3, 256, 3, 20000, 16), (3, 100, 6, 7000, 9),
+                 (4, 128, 3, 9000, 12), (5, 64, 2, 5000, 7), (2, 256, 40, 12000, 8)]
+_group_want = {}
+
+
+@pytest.mark.parametrize("halves", ["1", "2", "4"])
+@pytest.mark.parametrize("resident", ["0", "1"])
+@pytest.mark.parametrize("D,P,K,n,F", _GROUP_SHAPES)
+def test_persistent_wave_groups_agree(mh, monkeypatch, halves, resident, D, P, K, n, F):
+    """One, two or four tile streams (wave groups) per block, tiles resident
+    in LDS or staged each generation: the whole-run kernel gives the oracle's
+    DEOCT run (the groups only change the order in which counts are added)."""
+    from paper_2311_06952_amd import capi
+    key = (D, P, K, n, F)
+    X, y = synth.random_small(110 + D + K, n, F, K)
+    prm = (P, 5, 0.5, 0.9, 17 + D)
+    if key not in _group_want:
+        _group_want[key] = oracle.deoct(oracle.dataset_from_X(X, y, K), D,
+                                        oracle.de_params(*prm), prob=4)
+    monkeypatch.setenv("MHDEOCT_PERSIST", "1")
+    monkeypatch.setenv("MHDEOCT_PERSIST_HALVES", halves)
+    monkeypatch.setenv("MHDEOCT_PERSIST_RESIDENT", resident)
+    ctx = capi.Context(0)
+    ds = mh.dataset(X, y, K, ctx=ctx)
+    got = mh.subtree_solve(ds, D, mh.de_params(*prm), prob=4, ctx=ctx)
+    _same_tree(_group_want[key], got)
+    ctx.close()
+
+
 @pytest.mark.parametrize("D,P,K,n", [(1, 3, 2, 1), (2, 3, 20, 500), (3, 65, 9, 0), (2, 200, 3, 64),
                                      (4, 256, 2, 6300), (3, 129, 255, 3000)])
 def test_persistent_deoct_edge_shapes(mh, D, P, K, n):
@@ -378,8 +407,8 @@ def test_autotune_keeps_results(mh):
     ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
     prm = mh.de_params(64, 15, 0.5, 0.9, 21)
     tuned = mh.autotune(ds, w.D, prm, generations=5, ctx=ctx)
-    assert tuned["persist"] in (0, 1) and tuned["halves"] in (1, 2)
-    assert len(tuned["ms"]) == 9 and all(t > 0 for t in tuned["ms"])
+    assert tuned["persist"] in (0, 1) and tuned["halves"] in (1, 2, 4)
+    assert len(tuned["ms"]) == 12 and all(t > 0 for t in tuned["ms"])
     got = mh.subtree_solve(ds, w.D, prm, ctx=ctx)
     want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D, oracle.de_params(64, 15, 0.5,
                                                                                      0.9, 21))
