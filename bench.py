@@ -290,11 +290,12 @@ def main():
     yd = torch.as_tensor(w.y).to(dev)
     prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
+    enc = mh.rank_encode(Xd, ctx)  # output buffers, written again by every step
 
     def step():
         # rank encoding's NaN check is read back with the solved tree, so a
         # step waits for the device once
-        ranks, nu = mh.rank_encode(Xd, ctx, status=status)
+        ranks, nu = mh.rank_encode(Xd, ctx, status=status, out=enc)
         ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
         return mh.subtree_solve(ds, w.D, prm, ctx=ctx)
 

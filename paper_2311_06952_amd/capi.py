@@ -205,19 +205,26 @@ class Dataset:
                         None if self.status is None else self.status.data_ptr())
 
 
-def rank_encode(X, ctx: Context | None = None, pad_to: int = 256, status=None):
+def rank_encode(X, ctx: Context | None = None, pad_to: int = 256, status=None, out=None):
     """mh_rank_encode: X float32 [n][F] (torch, on the device) -> (ranks
     int32 [F][ld], n_unique int32 [F]) with ld = n rounded up to pad_to (the
     padding columns are left unwritten).  With `status` (a device int32
     tensor of one element) the call does not wait: the device writes the
-    NaN / failure status there (pass it on to Dataset)."""
+    NaN / failure status there (pass it on to Dataset).  `out` = (ranks,
+    n_unique) of an earlier call with the same shape are written again instead
+    of allocating new tensors."""
     torch = _torch()
     ctx = ctx or default_context()
     X = X.contiguous()
     n, F = X.shape
     ld = max(pad_to, ((n + pad_to - 1) // pad_to) * pad_to)
-    ranks = torch.empty((F, ld), dtype=torch.int32, device=X.device)
-    nu = torch.empty(F, dtype=torch.int32, device=X.device)
+    if out is not None:
+        ranks, nu = out
+        if tuple(ranks.shape) != (F, ld) or tuple(nu.shape) != (F,):
+            raise ValueError("out tensors do not match the input shape")
+    else:
+        ranks = torch.empty((F, ld), dtype=torch.int32, device=X.device)
+        nu = torch.empty(F, dtype=torch.int32, device=X.device)
     ctx.check(ctx.lib.mh_rank_encode(ctx.h, _ptr(X), n, F, ld, _ptr(ranks), _ptr(nu),
                                      _ptr(status)))
     return ranks, nu

@@ -38,6 +38,18 @@ uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu) {
 
 constexpr size_t PROF_MAX_PAIRS = 4096;
 
+int occupancy(Ctx *ctx, const void *kern, int threads, size_t lds) {
+  for (const Ctx::Occ &o : ctx->occ)
+    if (o.kern == kern && o.threads == threads && o.lds == lds) return o.per_cu;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 0;
+  }
+  if (ctx->occ.size() < 256) ctx->occ.push_back({kern, threads, lds, per_cu});
+  return per_cu;
+}
+
 uint32_t *host_words(Ctx *ctx) {
   if (!ctx->hwords) {
     const hipError_t e = hipHostMalloc((void **)&ctx->hwords, 64 * sizeof(uint32_t));
@@ -235,8 +247,9 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   if (s) return s;
   bool persisted = false;
   if (es.tiles && ctx->persist) {
+    const PersistFinal fin{f1, t1, lab1, corr1, cost1};
     s = launch_deoct_persist(ctx, es.tiles, ds->F, K, n_sub, D, prm, prob, ds->n_unique, pop, cost,
-                             best, err, &persisted);
+                             best, err, &fin, &persisted);
     if (s) return s;
   }
   if (!persisted) {
@@ -297,19 +310,22 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
       if (s) return s;
     }
   }
-  // the best individual: decode and evaluate for its labels
-  s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best, true);
-  if (s) return s;
-  FitnessOut fb;
-  fb.label = lab1;
-  fb.correct = corr1;
-  fb.cost = cost1;
-  // a single-tree evaluation: left out of the population-kernel timing
-  const bool prof = ctx->profile;
-  ctx->profile = false;
-  s = eval_trees(ctx, es, f1, t1, 1, D, prm->n_min, prm->alpha, fb);
-  ctx->profile = prof;
-  if (s) return s;
+  if (!persisted) {
+    // the best individual: decode and evaluate for its labels (the
+    // cooperative launch counted it in a last pass of its own)
+    s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, f1, t1, 1, best, true);
+    if (s) return s;
+    FitnessOut fb;
+    fb.label = lab1;
+    fb.correct = corr1;
+    fb.cost = cost1;
+    // a single-tree evaluation: left out of the population-kernel timing
+    const bool prof = ctx->profile;
+    ctx->profile = false;
+    s = eval_trees(ctx, es, f1, t1, 1, D, prm->n_min, prm->alpha, fb);
+    ctx->profile = prof;
+    if (s) return s;
+  }
   if (!ctx->result) {
     MH_HIP(ctx, hipHostMalloc((void **)&ctx->result, sizeof(ResultOut)));
     std::memset(ctx->result, 0, sizeof(ResultOut));

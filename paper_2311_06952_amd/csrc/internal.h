@@ -71,9 +71,20 @@ struct Ctx {
   // samples per block forced by MHDEOCT_RANK_R (0 = by size)
   bool rank_coop = true;
   uint32_t rank_coop_R = 0;
+  // remembered occupancy queries
+  struct Occ {
+    const void *kern;
+    int threads;
+    size_t lds;
+    int per_cu;
+  };
+  std::vector<Occ> occ;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
+// Blocks of `kern` (threads, dynamic LDS bytes) one CU holds, from the
+// occupancy query, remembered per context; 0 when the query fails.
+int occupancy(Ctx *ctx, const void *kern, int threads, size_t lds);
 // Shape key bucket of a tile count: floor(log2(tiles per CU)) + 1 (0 for none).
 uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu);
 
@@ -314,11 +325,21 @@ mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
 // (device u32) becomes non-zero if a grid-barrier wait gave up.  Sets *used
 // to false, queuing nothing, when the shape does not fit the kernel (depth
 // above 5, P above 512, F above 80, LDS, co-residency); the caller then runs
-// the per-generation kernels.
+// the per-generation kernels.  With fin, the launch also writes the best
+// tree of the last generation (its nodes, leaf classes, correct count and
+// cost, all device buffers), counted in one more pass over the tiles.
+struct PersistFinal {
+  uint8_t *feat;      // [SB]
+  uint32_t *tau;      // [SB]
+  uint8_t *label;     // [SL]
+  uint32_t *correct;  // [1]
+  double *cost;       // [1]
+};
 mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
                                uint32_t n_sub, uint32_t D, const mh_de_params *prm, uint64_t prob,
                                const uint32_t *n_unique, double *pop, double *cost,
-                               uint32_t *best, uint32_t *err, bool *used);
+                               uint32_t *best, uint32_t *err, const PersistFinal *fin,
+                               bool *used);
 
 // The same for the n_problems problems of a multi-problem tile set: each
 // problem gets its own group of blocks (in proportion to its tiles), its own

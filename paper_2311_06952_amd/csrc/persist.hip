@@ -60,6 +60,13 @@ struct PersistArgs {
   // > 0: every half keeps its (at most tph) tiles resident in LDS, staged in
   // generation 0 only; 0: tiles are staged every generation
   uint32_t tph;
+  // the best tree after the last generation (one problem; null: not wanted):
+  // nodes [SB], leaf classes [SL], correct count and cost
+  uint8_t *out_feat;
+  uint32_t *out_tau;
+  uint8_t *out_label;
+  uint32_t *out_correct;
+  double *out_cost;
 };
 
 __host__ __device__ __forceinline__ uint32_t align16u(uint32_t x) { return (x + 15u) & ~15u; }
@@ -286,7 +293,11 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     inf_next = info[t_begin + h];
   }
 
-  for (uint32_t g = 0; g <= pa.G; ++g) {
+  // generation G + 1, when the best tree is wanted, counts that tree alone
+  const uint32_t g_end = pa.out_label ? pa.G + 1 : pa.G;
+  uint32_t bst_fin = 0;
+  double cost_fin = 0.0;
+  for (uint32_t g = 0; g <= g_end; ++g) {
     // with four groups or deep trees the lane index is re-read each
     // generation, so that the compiler recomputes the addresses derived from
     // it instead of holding them in registers across the whole loop (1024
@@ -303,12 +314,14 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 #pragma unroll
     for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
     uint32_t cur_cls = 0xFFFFFFFFu;
+    // (in the pass for the best tree every lane holds that tree; lane 0 adds)
+    const bool adds = live && (g <= pa.G || r == 0);
     auto flush = [&]() {
       if (!live || cur_cls == 0xFFFFFFFFu) return;
       uint32_t *c = cnt + (size_t)cur_cls * Ppad + r;
 #pragma unroll
       for (int t = 0; t < SB; ++t) {
-        if (ns.acc[t]) atomicAdd(c + (size_t)t * K * Ppad, ns.acc[t]);
+        if (ns.acc[t] && adds) atomicAdd(c + (size_t)t * K * Ppad, ns.acc[t]);
         ns.acc[t] = 0;
       }
     };
@@ -443,6 +456,52 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     }
     barrier_wait(bar, g, pa.err);
 
+    if (g > pa.G) {
+      // ---- the best tree's nodes, leaf classes (the largest count, ties to
+      // the lower class, an empty leaf class 0), correct count and cost
+      if (b == 0 && threadIdx.x == 0) {
+        uint32_t nl[SL], bv[SL], bk[SL];
+#pragma unroll
+        for (int l = 0; l < SL; ++l) nl[l] = bv[l] = bk[l] = 0;
+        for (uint32_t k = 0; k < K; ++k) {
+          uint32_t reach[2 * SL];
+          reach[1] = ctot[k];
+#pragma unroll
+          for (int t = 1; t <= SB; ++t) {
+            const uint32_t left = cnt_load<true>(cnt + ((size_t)(t - 1) * K + k) * Ppad);
+            reach[2 * t] = left;
+            reach[2 * t + 1] = reach[t] - left;
+          }
+#pragma unroll
+          for (int l = 0; l < SL; ++l) {
+            const uint32_t v = reach[SL + l];
+            nl[l] += v;
+            if (v > bv[l]) {
+              bv[l] = v;
+              bk[l] = k;
+            }
+          }
+        }
+        uint32_t correct = 0;
+#pragma unroll
+        for (int l = 0; l < SL; ++l) {
+          correct += bv[l];
+          pa.out_label[l] = (uint8_t)bk[l];
+        }
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+          uint32_t f = 0, th = 0;
+          decode_node(rows[(size_t)t * P + bst_fin], rows[(size_t)(SB + t) * P + bst_fin], F,
+                      s_nu, f, th);
+          pa.out_feat[t] = (uint8_t)f;
+          pa.out_tau[t] = th;
+        }
+        *pa.out_correct = correct;
+        *pa.out_cost = cost_fin;
+      }
+      break;
+    }
+
     // ---- epilogue (eq. opt_all and the soft-constraint fitness); the counts
     // of up to KB classes are loaded together
     constexpr uint32_t KB = SB <= 7 ? 4u : (SB <= 15 ? 2u : 1u);
@@ -540,7 +599,21 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         if (h == 0) pa.cost[(size_t)s_prob * P + r] = cost_r;
       }
       if (b == 0 && threadIdx.x == 0) pa.best[s_prob] = bst;
-      break;
+      if (!pa.out_label) break;
+      // one more pass counts the best tree alone (every lane holds it)
+      bst_fin = bst;
+      cost_fin = bc;
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        const int t = n_lo + j;
+        gt[j] = gt[NA + j] = 0.0;
+        if (t < n_hi) {
+          gt[j] = rows[(size_t)t * P + bst];
+          gt[NA + j] = rows[(size_t)(SB + t) * P + bst];
+        }
+      }
+      set_tree(gt);
+      continue;
     }
 
     // ---- DE/best/1 mutation and binomial crossover of generation g + 1,
@@ -597,14 +670,10 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
   const void *kstage = nullptr;
   if constexpr (H < 4) kstage = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false>);
   const void *kern = kstage ? kstage : kres;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, H * WAVES * 64, lds) !=
-          hipSuccess ||
-      per_cu < 1) {
-    (void)hipGetLastError();
+  const int per_cu = occupancy(ctx, kern, H * WAVES * 64, lds);
+  if (per_cu < 1)
     return MH_OK;  // not co-resident: the caller tries fewer groups, then the
                    // per-generation kernels
-  }
   const uint32_t want = persist_bpc(max_tiles, (uint32_t)ctx->num_cu, H * WAVES);
   // with many tiles per CU the tile work dominates, and the per-generation
   // kernels win where they keep more waves per CU busy than the whole-run
@@ -671,16 +740,12 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
     const uint64_t need = (uint64_t)align16u(persist_exchange_bytes(SB, pa.P, H)) +
                           (uint64_t)H * tph * tile + align16u(2 * SB * pa.P * 8) +
                           align16u(pa.F * 4) + PERSIST_TAIL;
-    int per_cu_res = 0;
     if (tph >= 1 && tph <= MAX_TPH && need <= ctx->max_lds &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_res, kres, H * WAVES * 64,
-                                                     (size_t)need) == hipSuccess &&
-        (uint64_t)per_cu_res * ctx->num_cu >= grid) {
+        (uint64_t)occupancy(ctx, kres, H * WAVES * 64, (size_t)need) * ctx->num_cu >= grid) {
       a.tph = tph;
       lds_use = (uint32_t)need;
       kern = kres;
     }
-    (void)hipGetLastError();
   }
   if (!a.tph && !kstage) return MH_OK;  // four groups need resident tiles
   if (!a.tph) kern = kstage;
@@ -724,14 +789,14 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
                       uint64_t prob,
                       const uint64_t *prob_ids, const std::vector<uint32_t> *ptiles,
                       const uint32_t *n_unique, double *pop, double *cost, uint32_t *best,
-                      uint32_t *err, bool *used) {
+                      uint32_t *err, const PersistFinal *fin, bool *used) {
   *used = false;
   const uint32_t P = prm->P, SB = (1u << D) - 1u, m = 2 * SB;
   if (!ctx->coop || D < 1 || D > 5 || P > 512 || F > 80 || n_problems == 0 ||
       n_problems > 65535)
     return MH_OK;
-  // barrier targets (G + 1) * blocks must fit the 32-bit arrival counters
-  if ((uint64_t)(prm->G + 1) * (uint64_t)ctx->num_cu * 8u >= (1ull << 31)) return MH_OK;
+  // barrier targets (G + 2) * blocks must fit the 32-bit arrival counters
+  if ((uint64_t)(prm->G + 2) * (uint64_t)ctx->num_cu * 8u >= (1ull << 31)) return MH_OK;
   uint32_t waves = pad64(P) / 64;
   waves = waves > 4 ? 8 : (waves > 2 ? 4 : waves);
   // up to persist_halves tile streams per block, as the LDS and the
@@ -783,6 +848,11 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   pa.prob_ids = prob_ids;
   pa.bar_stride = bar_words;
   pa.tph = 0;
+  pa.out_feat = fin ? fin->feat : nullptr;
+  pa.out_tau = fin ? fin->tau : nullptr;
+  pa.out_label = fin ? fin->label : nullptr;
+  pa.out_correct = fin ? fin->correct : nullptr;
+  pa.out_cost = fin ? fin->cost : nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof_pair(ctx, &e0, &e1);
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));
@@ -813,9 +883,10 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
 mh_status launch_deoct_persist(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
                                uint32_t n_sub, uint32_t D, const mh_de_params *prm, uint64_t prob,
                                const uint32_t *n_unique, double *pop, double *cost,
-                               uint32_t *best, uint32_t *err, bool *used) {
+                               uint32_t *best, uint32_t *err, const PersistFinal *fin,
+                               bool *used) {
   return persist_run(ctx, tiles, F, K, n_sub, n_sub, 1, D, prm, prob, nullptr, nullptr, n_unique,
-                     pop, cost, best, err, used);
+                     pop, cost, best, err, fin, used);
 }
 
 mh_status launch_deoct_persist_multi(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K,
@@ -833,7 +904,7 @@ mh_status launch_deoct_persist_multi(Ctx *ctx, const void *tiles, uint32_t F, ui
       n_eval += class_counts[(size_t)i * K + k];
     }
   return persist_run(ctx, tiles, F, K, n_sub, n_eval, n_problems, D, prm, 0, prob_ids, &tl,
-                     n_unique, pop, cost, best, err, used);
+                     n_unique, pop, cost, best, err, nullptr, used);
 }
 
 }  // namespace mh

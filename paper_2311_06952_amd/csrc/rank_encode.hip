@@ -510,12 +510,9 @@ uint32_t rank_coop_R(Ctx *ctx, uint32_t n, uint32_t F) {
     if (ctx->rank_coop_R && R != ctx->rank_coop_R) continue;
     const uint64_t grid = (uint64_t)F * ((n + R - 1) / R);
     if (grid > target) continue;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank_coop, RC_THREADS,
-                                                     rc_lds_bytes(R)) != hipSuccess) {
-      (void)hipGetLastError();
-      return 0;
-    }
+    const int per_cu = occupancy(ctx, reinterpret_cast<const void *>(k_rank_coop), RC_THREADS,
+                                 rc_lds_bytes(R));
+    if (per_cu < 1) return 0;
     if ((uint64_t)per_cu * ctx->num_cu >= grid) return R;
   }
   return 0;
