@@ -94,6 +94,68 @@ __device__ __forceinline__ void eval_nodes(uint32_t kmask, NodeState<D> &ns,
   }
 }
 
+// Two staged tiles of the same class at once (byte offsets da and db from
+// the tile the node columns were set up for): the searches of both tiles run
+// interleaved, so twice as many LDS reads are in flight, and both tiles' left
+// counts go to the same counters.
+template <int D, int T0, int T1>
+__device__ __forceinline__ void eval_group2(uint32_t kmask, NodeState<D> &ns,
+                                            uint64_t (&Ra)[1 << D], uint64_t (&Rb)[1 << D],
+                                            uint32_t da, uint32_t db) {
+  constexpr int NG = T1 - T0;
+  uint32_t a[NG], c[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    a[i] = ns.col[T0 - 1 + i] + da;
+    c[i] = ns.col[T0 - 1 + i] + db;
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    uint32_t va[NG], vc[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      va[i] = lds_rd32(a[i] + (s - 1) * 4);
+      vc[i] = lds_rd32(c[i] + (s - 1) * 4);
+    }
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      a[i] += (va[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
+      c[i] += (vc[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
+    }
+  }
+  uint64_t ma[NG], mc[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    ma[i] = lds_rd64(kmask - da + 2 * a[i]);
+    mc[i] = lds_rd64(kmask - db + 2 * c[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    constexpr int SL = 1 << D;
+    const int t = T0 + i;
+    const uint64_t A = Ra[t] & ma[i], C = Rb[t] & mc[i];
+    ns.acc[t - 1] += (uint32_t)__popcll(A) + (uint32_t)__popcll(C);
+    if (2 * t < SL) {
+      Ra[2 * t + 1] = Ra[t] & ~ma[i];
+      Ra[2 * t] = A;
+      Rb[2 * t + 1] = Rb[t] & ~mc[i];
+      Rb[2 * t] = C;
+    }
+  }
+}
+
+template <int D, int T0>
+__device__ __forceinline__ void eval_nodes2(uint32_t kmask, NodeState<D> &ns,
+                                            uint64_t (&Ra)[1 << D], uint64_t (&Rb)[1 << D],
+                                            uint32_t da, uint32_t db) {
+  constexpr int SB = (1 << D) - 1;
+  if constexpr (T0 <= SB) {
+    constexpr int T1 = (T0 + ILP <= SB + 1) ? T0 + ILP : SB + 1;
+    eval_group2<D, T0, T1>(kmask, ns, Ra, Rb, da, db);
+    eval_nodes2<D, T1>(kmask, ns, Ra, Rb, da, db);
+  }
+}
+
 // Staging: the tile record (sorted [F][64] u32, then masks [F][64] u64) moves
 // as 16-byte chunks; chunk c < 16F is four ranks of column c / 16, the rest
 // two masks each.  Up to PF chunks per thread are prefetched into registers

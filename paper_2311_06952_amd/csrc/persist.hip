@@ -326,7 +326,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       }
     };
     if constexpr (RES) {
-      for (uint32_t i = 0; i < rounds; ++i) {
+      for (uint32_t i = 0; i < rounds;) {
         const uint32_t tile = t_begin + i * H + h;
         if (tile >= t_end) break;
         const uint32_t inf = s_info[h * MAX_TPH + i];
@@ -337,7 +337,19 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         }
         uint64_t R[1 << D];
         R[1] = (1ull << (inf & 0xFFu)) - 1ull;  // count <= 63
-        eval_nodes<D, 1>(kmask, ns, R, i * tile_lds);
+        // (the pair test is uniform over the group: the tile list is)
+        const uint32_t inf2 = i + 1 < rounds && tile + H < t_end ? s_info[h * MAX_TPH + i + 1]
+                                                                 : 0xFFFFFFFFu;
+        if (D <= 3 && inf2 != 0xFFFFFFFFu && ((inf2 >> 8) & 0xFFu) == cls) {
+          // two tiles of the same class at once
+          uint64_t R2[1 << D];
+          R2[1] = (1ull << (inf2 & 0xFFu)) - 1ull;
+          eval_nodes2<D, 1>(kmask, ns, R, R2, i * tile_lds, (i + 1) * tile_lds);
+          i += 2;
+        } else {
+          eval_nodes<D, 1>(kmask, ns, R, i * tile_lds);
+          i += 1;
+        }
       }
     } else {
       for (uint32_t i = 0; i < rounds; ++i) {
