@@ -48,7 +48,7 @@ def cpu_baseline(w, seconds=15.0):
                        f"workload, {evals:.3g} evals in {el:.1f} s, single thread")
 
 
-KERNEL = "k_deoct_persist<3,4,2>"
+KERNEL = "k_deoct_persist<3,4,2,true>"
 KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "grid_sync.h",
                   "internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_deoct_persist_plain_scale_traffic.txt")
@@ -331,7 +331,7 @@ def main():
     st = ctx.stats(reset=True)
     kernel_ms = st["ms"] / max(st["launches"], 1)
     lps = max(1, round(st["launches"] / args.steps))
-    kname = (f"k_deoct_persist<3,4,{tuned['halves']}>" if lps == 1
+    kname = (f"k_deoct_persist<3,4,{tuned['halves']},true>" if lps == 1
              else "k_fitness_bits<3,4,false>")
     roof = roofline(w, kernel_ms, lps, kname)
     roof["timed_launches"] = int(st["launches"])

@@ -50,6 +50,24 @@ int occupancy(Ctx *ctx, const void *kern, int threads, size_t lds) {
   return per_cu;
 }
 
+int coop_per_cu(Ctx *ctx, const void *kern, int threads, size_t lds) {
+  int r = occupancy(ctx, kern, threads, lds);
+  if (lds > 0) r = (int)std::min<size_t>((size_t)r, ((size_t)ctx->max_lds - 2048) / lds);
+  if (r >= 3) r -= 1;
+  return std::min(r, 4);
+}
+
+bool coop_is_bad(const Ctx *ctx, const void *kern, uint32_t grid) {
+  for (const auto &p : ctx->coop_bad)
+    if (p.first == kern && p.second == grid) return true;
+  return false;
+}
+
+void coop_note_failure(Ctx *ctx) {
+  if (ctx->last_coop_kern && !coop_is_bad(ctx, ctx->last_coop_kern, ctx->last_coop_grid))
+    ctx->coop_bad.push_back({ctx->last_coop_kern, ctx->last_coop_grid});
+}
+
 uint32_t *host_words(Ctx *ctx) {
   if (!ctx->hwords) {
     const hipError_t e = hipHostMalloc((void **)&ctx->hwords, 64 * sizeof(uint32_t));
@@ -210,7 +228,7 @@ static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
 // DEOCT (Algorithm 4) fully on the device; the best tree goes to *out.
 static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                        uint32_t D, const mh_de_params *prm, const double *warm_host, uint32_t W,
-                       uint64_t prob, mh_tree *out) {
+                       uint64_t prob, mh_tree *out, int depth = 0) {
   const uint32_t P = prm->P, SB = (1u << D) - 1u, SL = 1u << D, m = 2 * SB, K = ds->K;
   hipStream_t st = ctx->stream;
   EvalSet es;
@@ -341,6 +359,12 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   out->correct = ctx->result->tree.correct;
   out->cost = ctx->result->tree.cost;
   const uint32_t flag = ctx->result->flag;
+  if ((flag & 1u) && persisted && depth < 4) {
+    // the cooperative grid did not run all at once: not again, and the run
+    // is redone (results do not depend on the launch form)
+    coop_note_failure(ctx);
+    return deoct(ctx, ds, idx, n_sub, D, prm, warm_host, W, prob, out, depth + 1);
+  }
   if (flag & 1u) return fail(ctx, MH_EDEVICE, "DEOCT grid barrier: a wait gave up");
   if (flag & 2u) return fail(ctx, MH_EINVAL, "X holds a NaN");
   if (flag) return fail(ctx, MH_EDEVICE, "rank encoding failed on the device");
@@ -412,6 +436,7 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_PERSIST_BLOCKS_PER_CU"))
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_DEBUG")) c->c.debug = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_RANK_R")) {
     const int r = atoi(v);
     c->c.rank_coop_R = (r >= 256 && r <= 8192 && (r & (r - 1)) == 0) ? (uint32_t)r : 0u;

@@ -71,6 +71,8 @@ struct Ctx {
   // samples per block forced by MHDEOCT_RANK_R (0 = by size)
   bool rank_coop = true;
   uint32_t rank_coop_R = 0;
+  // launch decisions of the cooperative kernels to stderr (MHDEOCT_DEBUG=1)
+  bool debug = false;
   // remembered occupancy queries
   struct Occ {
     const void *kern;
@@ -79,12 +81,27 @@ struct Ctx {
     int per_cu;
   };
   std::vector<Occ> occ;
+  // cooperative launches (kernel, grid) whose grid barrier gave up: not
+  // launched again by this context; and the last one launched
+  std::vector<std::pair<const void *, uint32_t>> coop_bad;
+  const void *last_coop_kern = nullptr;
+  uint32_t last_coop_grid = 0;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
 // Blocks of `kern` (threads, dynamic LDS bytes) one CU holds, from the
 // occupancy query, remembered per context; 0 when the query fails.
 int occupancy(Ctx *ctx, const void *kern, int threads, size_t lds);
+// Blocks per CU a cooperative grid of `kern` may use: the occupancy query,
+// with a margin (one block less from three blocks up, 2 KiB of LDS per CU
+// left over) and at most four.  Grids that the query called co-resident
+// were seen not to become resident all at once near those limits (the grid
+// barrier then gives up after its time limit).
+int coop_per_cu(Ctx *ctx, const void *kern, int threads, size_t lds);
+// Whether (kern, grid) gave up at a grid barrier before in this context.
+bool coop_is_bad(const Ctx *ctx, const void *kern, uint32_t grid);
+// Records the last cooperative launch as one whose barrier gave up.
+void coop_note_failure(Ctx *ctx);
 // Shape key bucket of a tile count: floor(log2(tiles per CU)) + 1 (0 for none).
 uint32_t tiles_bucket(uint32_t max_tiles, uint32_t num_cu);
 
@@ -167,7 +184,7 @@ TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems)
 // non-zero value when X holds a NaN.
 mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F,
                              uint32_t ld, uint32_t *ranks, uint32_t *n_unique,
-                             uint32_t *nan_out = nullptr);
+                             uint32_t *nan_out = nullptr, bool retry = true);
 // Sorts (key, value) pairs by the low `key_bits` of key (stable LSD radix
 // sort, 8 bits per pass).  Buffers are ping-ponged; the sorted result ends in
 // (*keys, *vals) which may point at the alternate buffers on return.

@@ -394,8 +394,13 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
       uint32_t h_err = 0;
       MH_HIP(ctx, hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st));
       MH_HIP(ctx, hipStreamSynchronize(st));
-      if (h_err) return fail(ctx, MH_EDEVICE, "batched DEOCT grid barrier: a wait gave up");
-      return MH_OK;
+      if (!h_err) return MH_OK;
+      // the cooperative grid did not run all at once: not again; the level
+      // runs on the per-generation kernels from a fresh start
+      coop_note_failure(ctx);
+      MH_HIP(ctx, hipMemsetAsync(cnt, 0, cb, st));
+      s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop, true);
+      if (s) return s;
     }
   }
   s = launch_decode(ctx, pop, P, D, F, ds->n_unique, feat, tau, n_problems, nullptr, true);

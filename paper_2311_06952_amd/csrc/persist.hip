@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstdio>
 #include <type_traits>
 #include <vector>
 
@@ -682,7 +683,7 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
   const void *kstage = nullptr;
   if constexpr (H < 4) kstage = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false>);
   const void *kern = kstage ? kstage : kres;
-  const int per_cu = occupancy(ctx, kern, H * WAVES * 64, lds);
+  const int per_cu = coop_per_cu(ctx, kern, H * WAVES * 64, lds);
   if (per_cu < 1)
     return MH_OK;  // not co-resident: the caller tries fewer groups, then the
                    // per-generation kernels
@@ -753,7 +754,7 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
                           (uint64_t)H * tph * tile + align16u(2 * SB * pa.P * 8) +
                           align16u(pa.F * 4) + PERSIST_TAIL;
     if (tph >= 1 && tph <= MAX_TPH && need <= ctx->max_lds &&
-        (uint64_t)occupancy(ctx, kres, H * WAVES * 64, (size_t)need) * ctx->num_cu >= grid) {
+        (uint64_t)coop_per_cu(ctx, kres, H * WAVES * 64, (size_t)need) * ctx->num_cu >= grid) {
       a.tph = tph;
       lds_use = (uint32_t)need;
       kern = kres;
@@ -761,6 +762,13 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
   }
   if (!a.tph && !kstage) return MH_OK;  // four groups need resident tiles
   if (!a.tph) kern = kstage;
+  if (coop_is_bad(ctx, kern, grid)) return MH_OK;
+  if (ctx->debug)
+    std::fprintf(stderr,
+                 "k_deoct_persist<%d,%d,%d,%s>: grid %u (per CU %d by occupancy), tiles %u "
+                 "(per block %u), LDS %u bytes\n",
+                 D, WAVES, H, a.tph ? "true" : "false", grid, per_cu, max_tiles, per_block,
+                 lds_use);
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(H * WAVES * 64), args, lds_use,
                                             ctx->stream);
@@ -772,6 +780,8 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
     return MH_OK;
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_deoct_persist");
+  ctx->last_coop_kern = kern;
+  ctx->last_coop_grid = grid;
   *used = true;
   return MH_OK;
 }

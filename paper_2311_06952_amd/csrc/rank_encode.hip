@@ -510,10 +510,11 @@ uint32_t rank_coop_R(Ctx *ctx, uint32_t n, uint32_t F) {
     if (ctx->rank_coop_R && R != ctx->rank_coop_R) continue;
     const uint64_t grid = (uint64_t)F * ((n + R - 1) / R);
     if (grid > target) continue;
-    const int per_cu = occupancy(ctx, reinterpret_cast<const void *>(k_rank_coop), RC_THREADS,
-                                 rc_lds_bytes(R));
+    const void *kern = reinterpret_cast<const void *>(k_rank_coop);
+    const int per_cu = coop_per_cu(ctx, kern, RC_THREADS, rc_lds_bytes(R));
     if (per_cu < 1) return 0;
-    if ((uint64_t)per_cu * ctx->num_cu >= grid) return R;
+    if ((uint64_t)per_cu * ctx->num_cu >= grid && !coop_is_bad(ctx, kern, (uint32_t)grid))
+      return R;
   }
   return 0;
 }
@@ -552,13 +553,15 @@ mh_status rank_encode_coop(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uin
     return MH_OK;
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "k_rank_coop");
+  ctx->last_coop_kern = reinterpret_cast<const void *>(k_rank_coop);
+  ctx->last_coop_grid = grid;
   *used = true;
   return MH_OK;
 }
 }  // namespace
 
 mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uint32_t ld,
-                             uint32_t *ranks, uint32_t *n_unique, uint32_t *nan_out) {
+                             uint32_t *ranks, uint32_t *n_unique, uint32_t *nan_out, bool retry) {
   uint64_t total64 = (uint64_t)n * F;
   if (total64 >= 0xFFFFFFFFull) return fail(ctx, MH_EINVAL, "n * F too large");
   uint32_t total = (uint32_t)total64;
@@ -615,6 +618,12 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
   if (!h) return MH_ENOMEM;
   MH_HIP(ctx, hipMemcpyAsync(h, words, 8, hipMemcpyDeviceToHost, st));
   MH_HIP(ctx, hipStreamSynchronize(st));
+  if ((h[1] & 1u) && done && retry) {
+    // the cooperative grid did not run all at once: not again, and the
+    // encoding is redone
+    coop_note_failure(ctx);
+    return launch_rank_encode(ctx, X, n, F, ld, ranks, n_unique, nullptr, false);
+  }
   if (h[1])
     return fail(ctx, MH_EDEVICE, "rank encoding failed on the device (" +
                                      std::string(h[1] & 1u ? "a grid barrier wait gave up" : "an index out of range") +
