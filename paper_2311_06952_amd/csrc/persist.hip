@@ -255,7 +255,8 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       ns.thr[t] = f ? th : 0u;
       nsplit += f != 0;
     }
-    __syncthreads();  // the exchange area is a tile buffer again
+    // staged tiles: the exchange area is a tile buffer again
+    if constexpr (!RES) __syncthreads();
   };
   set_tree(gt);
 
@@ -639,13 +640,16 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         if (t >= n_hi) continue;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
-          const int q = t + (hh ? SB : 0);
-          const double d = __dsub_rn(rows[(size_t)q * P + r1], rows[(size_t)q * P + r2]);
+          const int q = t + (hh ? SB : 0), jj = j + (hh ? NA : 0);
+          const double a1 = rows[(size_t)q * P + r1];
+          const double a2 = rows[(size_t)q * P + r2];
+          const double a0 = rows[(size_t)q * P + r];
+          const double d = __dsub_rn(a1, a2);
           double v = __dadd_rn(rows[(size_t)q * P + bst], __dmul_rn(Mr, d));
           const double hiq = hh ? 1.0 : Fp1;
           if (!(v >= 0.0)) v = 0.0;
           if (v > hiq) v = hiq;
-          gt[j + (hh ? NA : 0)] = ((cross >> q) & 1ull) ? v : rows[(size_t)q * P + r];
+          gt[jj] = ((cross >> q) & 1ull) ? v : a0;
         }
       }
     }
