@@ -280,7 +280,8 @@ typedef struct mh_server mh_server;
 /* Result of one request (host struct). */
 typedef struct {
   uint64_t req_id;
-  mh_status status;      /* MH_OK, or MH_EINVAL when the request's X held a NaN */
+  mh_status status;      /* MH_OK, MH_EINVAL when the request's X held a NaN, MH_EDEVICE
+                            when its cooperative launch gave up at a grid barrier */
   uint32_t n, F, K;
   mh_tree tree;          /* equal to subtree_solve on the same data, problem id 0 */
   uint64_t t_submit_ns;  /* host steady clock: mh_server_submit */
@@ -321,8 +322,12 @@ mh_status mh_server_footprint(uint32_t n, uint32_t F, uint32_t K, uint32_t D,
  * stream), then queues one generation of every resident request: one
  * fitness launch per depth for all of them together, and one DE launch per
  * depth (epilogue, selection, best, next trial), each request at its own
- * generation.  Requests that ran their G generations get their best tree
- * evaluated and copied to pinned host memory.  At most a few rounds are in
+ * generation.  A request whose tile layout has at least two tiles per CU
+ * (about 32,000 samples on 256 CUs; MHDEOCT_SERVE_SOLO_TILES sets the tile
+ * count, 0 never) fills the device by itself: it runs whole at admission as
+ * one cooperative launch, the plain form's kernel.  Requests that ran their
+ * G generations get their best tree evaluated and copied to pinned host
+ * memory.  At most a few rounds are in
  * flight on the device; a round waits for older ones as needed.  Stops
  * early when nothing is resident or queued.  *n_active / *n_queued (may be
  * NULL) receive the counts after the last round. */

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -87,7 +88,7 @@ class Pool {
 // Where a request's state sits inside its pool block.
 struct Carve {
   size_t tiles, tile_bytes, nu, pop, trial, cost, tcost, feat, tau, best, cnt, f1, t1, lab1,
-      corr1, cost1, nan, total;
+      corr1, cost1, nan, err, total;
   uint32_t max_tiles;
 };
 
@@ -119,6 +120,7 @@ Carve carve(uint32_t n, uint32_t F, uint32_t K, uint32_t D, uint32_t P) {
   c.corr1 = take(4);
   c.cost1 = take(8);
   c.nan = take(4);
+  c.err = take(4);
   c.total = o;
   return c;
 }
@@ -135,6 +137,7 @@ struct Req {
   uint8_t *base = nullptr;
   uint32_t g = 0;  // next generation index to queue (0..G; G + 1 = done)
   int slot = -1;
+  bool solo = false;  // solved whole by one cooperative launch at admission
 
   template <typename T>
   T *at(size_t o) const {
@@ -182,6 +185,9 @@ struct mh_server {
   uint8_t *desc_dev = nullptr;
   uint64_t rounds = 0;
   mh_status sticky = MH_OK;
+  // requests with at least this many tiles run whole as one cooperative
+  // launch (0: never); MHDEOCT_SERVE_SOLO_TILES, default two per CU
+  uint32_t solo_tiles = 0;
 };
 
 namespace mh {
@@ -211,6 +217,23 @@ mh_status admit(mh_server *s, Req &q) {
   r = launch_de_init(c, q.prm.P, q.D, q.F, q.prm.seed, nullptr, 0, 1, nullptr, 0,
                      q.at<double>(q.cv.pop), true);
   if (r) return r;
+  if (c->persist && s->solo_tiles && q.cv.max_tiles >= s->solo_tiles) {
+    // a request that fills the device by itself: its whole run as one
+    // cooperative launch (the plain form's kernel), finished at admission
+    const PersistFinal fin{q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1),
+                           q.at<uint8_t>(q.cv.lab1), q.at<uint32_t>(q.cv.corr1),
+                           q.at<double>(q.cv.cost1)};
+    bool used = false;
+    r = launch_deoct_persist(c, q.base + q.cv.tiles, q.F, q.K, q.n, q.D, &q.prm, 0, nu,
+                             q.at<double>(q.cv.pop), q.at<double>(q.cv.cost),
+                             q.at<uint32_t>(q.cv.best), q.at<uint32_t>(q.cv.err), &fin, &used);
+    if (r) return r;
+    if (used) {
+      q.solo = true;
+      q.g = q.prm.G + 1;
+      return MH_OK;
+    }
+  }
   return launch_decode(c, q.at<double>(q.cv.pop), q.prm.P, q.D, q.F, nu, q.at<uint8_t>(q.cv.feat),
                        q.at<uint32_t>(q.cv.tau), 1, nullptr, true);
 }
@@ -221,6 +244,16 @@ mh_status retire(mh_server *s, Req &q) {
   Ctx *c = s->c;
   const uint32_t SB = (1u << q.D) - 1u, SL = 1u << q.D;
   uint32_t *nu = q.at<uint32_t>(q.cv.nu);
+  if (q.solo) {
+    // the cooperative launch wrote the best tree; its barrier flag goes along
+    mh_status r = launch_pack_result(c, q.D, q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1),
+                                     q.at<uint8_t>(q.cv.lab1), q.at<uint32_t>(q.cv.corr1),
+                                     q.at<double>(q.cv.cost1), q.at<uint32_t>(q.cv.err),
+                                     q.at<uint32_t>(q.cv.nan), s->pinned + q.slot);
+    if (r) return r;
+    MH_HIP(c, hipEventRecord(s->slot_ev[q.slot], c->stream));
+    return MH_OK;
+  }
   mh_status r = launch_decode(c, q.at<double>(q.cv.pop), q.prm.P, q.D, q.F, nu,
                               q.at<uint8_t>(q.cv.f1), q.at<uint32_t>(q.cv.t1), 1,
                               q.at<uint32_t>(q.cv.best), true);
@@ -300,7 +333,7 @@ mh_status generation(mh_server *s) {
   for (uint32_t D = 1; D <= 5; ++D) {
     std::vector<Req *> js;
     for (Req &q : s->active)
-      if (q.D == D) js.push_back(&q);
+      if (q.D == D && q.g <= q.prm.G) js.push_back(&q);
     if (js.empty()) continue;
     Launch L{D, 0, 0, 0, (uint32_t)js.size(), 0, 0, 0, 0};
     uint64_t tiles = 0;
@@ -365,7 +398,8 @@ mh_status generation(mh_server *s) {
                        L.P_max);
     if (r) return r;
   }
-  for (Req &q : s->active) q.g += 1;
+  for (Req &q : s->active)
+    if (q.g <= q.prm.G) q.g += 1;
   return MH_OK;
 }
 
@@ -445,6 +479,8 @@ mh_status mh_server_create(mh_ctx *ctx, uint64_t hbm_budget, uint32_t max_slots,
   s->ctx = ctx;
   s->c = c;
   s->max_slots = max_slots;
+  s->solo_tiles = 2u * (uint32_t)c->num_cu;
+  if (const char *v = std::getenv("MHDEOCT_SERVE_SOLO_TILES")) s->solo_tiles = (uint32_t)std::max(0, atoi(v));
   s->pool_bytes = (size_t)hbm_budget & ~(size_t)255;
   s->desc_bytes = desc_capacity(max_slots, (uint32_t)c->num_cu);
   hipError_t e = hipMalloc((void **)&s->pool_base, s->pool_bytes);
