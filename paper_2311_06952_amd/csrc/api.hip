@@ -437,6 +437,8 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_DEBUG")) c->c.debug = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_WAIT_TICKS"))
+    c->c.wait_ticks = std::min<uint64_t>(strtoull(v, nullptr, 10), 200000000ull);
   if (const char *v = std::getenv("MHDEOCT_RANK_R")) {
     const int r = atoi(v);
     c->c.rank_coop_R = (r >= 256 && r <= 8192 && (r & (r - 1)) == 0) ? (uint32_t)r : 0u;

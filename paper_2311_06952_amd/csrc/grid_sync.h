@@ -12,8 +12,9 @@
 
 namespace mh {
 
-// A barrier wait gives up after this many ticks of the device wall clock
-// (2 s at its usual 100 MHz), or at once when another block already gave up.
+// A barrier wait gives up after `limit` ticks of the device wall clock (by
+// default WAIT_LIMIT_TICKS: 2 s at its usual 100 MHz), or at once when
+// another block already gave up.
 constexpr uint64_t WAIT_LIMIT_TICKS = 200000000ull;
 
 // Barrier words, each on its own 256-byte line: [0] arrivals of group
@@ -48,12 +49,13 @@ __device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t k, uint32
   }
 }
 // Wait: thread 0 polls the release word, then the block proceeds together.
-__device__ __forceinline__ void barrier_wait(uint32_t *bar, uint32_t k, uint32_t *err) {
+__device__ __forceinline__ void barrier_wait(uint32_t *bar, uint32_t k, uint32_t *err,
+                                             uint64_t limit = WAIT_LIMIT_TICKS) {
   if (threadIdx.x == 0) {
     const uint64_t t0 = wall_clock64();
     while (__hip_atomic_load(bar + 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > WAIT_LIMIT_TICKS) {
+          wall_clock64() - t0 > limit) {
         __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }

@@ -73,6 +73,9 @@ struct Ctx {
   uint32_t rank_coop_R = 0;
   // launch decisions of the cooperative kernels to stderr (MHDEOCT_DEBUG=1)
   bool debug = false;
+  // grid-barrier time limit in device wall-clock ticks (MHDEOCT_WAIT_TICKS;
+  // tests set a tiny one to exercise the recovery from a barrier that gives up)
+  uint64_t wait_ticks = 200000000ull;
   // remembered occupancy queries
   struct Occ {
     const void *kern;

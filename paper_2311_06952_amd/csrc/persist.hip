@@ -68,6 +68,7 @@ struct PersistArgs {
   uint8_t *out_label;
   uint32_t *out_correct;
   double *out_cost;
+  uint64_t wait_ticks;  // barrier time limit, device wall-clock ticks
 };
 
 __host__ __device__ __forceinline__ uint32_t align16u(uint32_t x) { return (x + 15u) & ~15u; }
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         }
       }
     }
-    barrier_wait(bar, g, pa.err);
+    barrier_wait(bar, g, pa.err, pa.wait_ticks);
 
     if (g > pa.G) {
       // ---- the best tree's nodes, leaf classes (the largest count, ties to
@@ -879,6 +880,7 @@ mh_status persist_run(Ctx *ctx, const void *tiles, uint32_t F, uint32_t K, uint3
   pa.out_label = fin ? fin->label : nullptr;
   pa.out_correct = fin ? fin->correct : nullptr;
   pa.out_cost = fin ? fin->cost : nullptr;
+  pa.wait_ticks = ctx->wait_ticks;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof_pair(ctx, &e0, &e1);
   if (timed) MH_HIP(ctx, hipEventRecord(e0, st));

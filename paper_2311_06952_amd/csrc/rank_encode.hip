@@ -239,6 +239,7 @@ struct RankCoopArgs {
   uint32_t *dcount;       // [F][nbf]
   uint32_t *bar, *err, *nan_flag;
   uint32_t *ranks, *n_unique;
+  uint64_t wait_ticks;  // barrier time limit, device wall-clock ticks
 };
 
 // Cross-block stores and loads go through agent-scope accesses (the L2s of
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
       }
       __builtin_amdgcn_wave_barrier();
     }
-    barrier_wait(a.bar, k, a.err);
+    barrier_wait(a.bar, k, a.err, a.wait_ticks);
     ++k;
     // global start of the block's keys of digit tid: all smaller digits of
     // the feature, plus digit tid in the feature's earlier blocks
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
         __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     barrier_arrive(a.bar, k, b, nb);
-    barrier_wait(a.bar, k, a.err);
+    barrier_wait(a.bar, k, a.err, a.wait_ticks);
     ++k;
     for (uint32_t q = tid; q < cnt; q += RC_THREADS) kv[q] = xld(dst + seg + lo + q);
     src = dst;
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
   (void)rc_block_exscan(mine, tmp, &count);
   if (tid == 0) xst(a.dcount + b, count);
   barrier_arrive(a.bar, k, b, nb);
-  barrier_wait(a.bar, k, a.err);
+  barrier_wait(a.bar, k, a.err, a.wait_ticks);
   ++k;
   uint32_t base = 0;
   {
@@ -544,6 +545,7 @@ mh_status rank_encode_coop(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uin
   a.nan_flag = nan_flag;
   a.ranks = ranks;
   a.n_unique = n_unique;
+  a.wait_ticks = ctx->wait_ticks;
   void *args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rank_coop), dim3(grid),
                                             dim3(RC_THREADS), args, rc_lds_bytes(R), ctx->stream);
@@ -622,7 +624,11 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
     // the cooperative grid did not run all at once: not again, and the
     // encoding is redone
     coop_note_failure(ctx);
-    return launch_rank_encode(ctx, X, n, F, ld, ranks, n_unique, nullptr, false);
+    const bool coop = ctx->rank_coop;
+    ctx->rank_coop = false;  // the separate launches redo it
+    const mh_status r = launch_rank_encode(ctx, X, n, F, ld, ranks, n_unique, nullptr, false);
+    ctx->rank_coop = coop;
+    return r;
   }
   if (h[1])
     return fail(ctx, MH_EDEVICE, "rank encoding failed on the device (" +

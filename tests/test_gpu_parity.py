@@ -398,6 +398,25 @@ def test_persistent_large_lds_shapes(mh, monkeypatch, D, P, F, K):
         ctx.close()
 
 
+def test_barrier_give_up_recovery(mh, monkeypatch):
+    """A cooperative grid whose barrier gives up (forced from the host with a
+    zero time limit, so that waits end at once) is recorded, and the work is
+    redone with another launch form: the rank encoding and the DEOCT run still
+    give the oracle's results."""
+    from paper_2311_06952_amd import capi
+    monkeypatch.setenv("MHDEOCT_WAIT_TICKS", "0")
+    ctx = capi.Context(0)
+    X, y = synth.random_small(123, 20000, 8, 3)
+    ds = mh.dataset(X, y, 3, ctx=ctx)
+    want_r, want_nu = oracle.rank_encode(X)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :20000], want_r)
+    got = mh.subtree_solve(ds, 3, mh.de_params(64, 6, 0.5, 0.9, 9), ctx=ctx)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(64, 6, 0.5, 0.9, 9))
+    _same_tree(want, got)
+    ctx.close()
+
+
 def test_autotune_keeps_results(mh):
     """The autotuner picks a launch configuration for the shape; runs with it
     still equal the oracle."""
