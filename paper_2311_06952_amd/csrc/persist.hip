@@ -116,11 +116,11 @@ __host__ __device__ __forceinline__ uint32_t persist_merge_slot(uint32_t SB, uin
   return align16u(P * 4 + SB * P * 4);
 }
 // Bytes the exchanges need in the first tile buffer: decoded nodes (feature
-// byte and threshold per node and tree), or H / 2 count-merge slots.
+// byte and threshold per node and tree), or two count-merge slots (H > 1).
 __host__ __device__ __forceinline__ uint32_t persist_exchange_bytes(uint32_t SB, uint32_t P,
                                                                    uint32_t H) {
   const uint32_t nodes = align16u(SB * P) + SB * P * 4;
-  const uint32_t counts = (H / 2) * persist_merge_slot(SB, P);
+  const uint32_t counts = (H > 1 ? 2u : 0u) * persist_merge_slot(SB, P);
   return nodes > counts ? nodes : counts;
 }
 // The first tile buffer, large enough for the exchanges.
@@ -396,7 +396,44 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
         }
       }
     }
-    if constexpr (H > 1) {
+    if constexpr (H == 2) {
+      // both groups publish their open class and counts; then group h adds
+      // both groups' counts of its own nodes and flushes them (each group
+      // issues half the atomics).  When the two groups end on different
+      // classes each flushes its own counts instead.  (The first barrier also
+      // keeps the slots, which overlap the node exchange, from being written
+      // while a slower wave still reads the exchanged nodes.)
+      __syncthreads();
+      if (live) {
+        uint8_t *sl = lds + h * mslot;
+        reinterpret_cast<uint32_t *>(sl)[r] = cur_cls;
+#pragma unroll
+        for (int t = 0; t < SB; ++t) reinterpret_cast<uint32_t *>(sl + P * 4)[t * P + r] = ns.acc[t];
+      }
+      __syncthreads();
+      if (live) {
+        const uint8_t *so = lds + (1u - h) * mslot;
+        const uint32_t co = reinterpret_cast<const uint32_t *>(so)[r];
+        const uint32_t *xo = reinterpret_cast<const uint32_t *>(so + P * 4);
+        if (co == cur_cls || co == 0xFFFFFFFFu || cur_cls == 0xFFFFFFFFu) {
+          const uint32_t cls = cur_cls != 0xFFFFFFFFu ? cur_cls : co;
+          if (cls != 0xFFFFFFFFu && adds) {
+            uint32_t *c = cnt + (size_t)cls * Ppad + r;
+#pragma unroll
+            for (int t = 0; t < SB; ++t) {
+              if (t < n_lo || t >= n_hi) continue;
+              const uint32_t v = ns.acc[t] + xo[t * P + r];
+              if (v) atomicAdd(c + (size_t)t * K * Ppad, v);
+            }
+          }
+        } else {
+          flush();
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < SB; ++t) ns.acc[t] = 0;
+      cur_cls = 0xFFFFFFFFu;
+    } else if constexpr (H > 2) {
       // merge the groups' open counts pairwise (group h + w into group h for
       // w = H / 2, .., 1), adding them when both end on the same class (the
       // usual case: tiles are grouped by class) and flushing otherwise
@@ -583,11 +620,13 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
     // individual's cost; duplicates do not change the result)
     double bc = live ? cost_r : DBL_MAX;
     uint32_t bi = r;
-    // (every group holds the same costs: the first group's waves suffice)
-    wave_argmin(bc, bi);
-    if ((threadIdx.x & 63u) == 0 && h == 0) {
-      s_cost[threadIdx.x >> 6] = bc;
-      s_idx[threadIdx.x >> 6] = bi;
+    // (every group holds the same costs: the first group's waves reduce them)
+    if (h == 0) {
+      wave_argmin(bc, bi);
+      if ((threadIdx.x & 63u) == 0) {
+        s_cost[threadIdx.x >> 6] = bc;
+        s_idx[threadIdx.x >> 6] = bi;
+      }
     }
     __syncthreads();
     bc = s_cost[0];
