@@ -289,6 +289,27 @@ def test_subtree_solve_plain_scale_full_n(mh):
     _same_tree(want, got)
 
 
+def test_plain_large_full_size(mh):
+    """The large plain configuration at its full size (n = 10^6, F = 32, K = 4,
+    depth 4, P = 512): ranks, the fitness of 16 random trees, and a DEOCT run
+    cut to G = 1 (the oracle's full run would take hours), all equal to the
+    oracle's."""
+    w = synth.plain_large(1)
+    ods = oracle.dataset_from_X(w.X, w.y, w.K)
+    ds = gpu_ds(mh, w.X, w.y, w.K)
+    np.testing.assert_array_equal(u32(ds.n_unique), ods.n_unique)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :w.n], ods.ranks)
+    rng = np.random.default_rng(5)
+    feat, tau = random_trees(rng, 16, w.D, w.F, ods.n_unique)
+    want = oracle.fitness(ods, feat, tau, w.D)
+    got = mh.fitness_eval(ds, dev(feat), dev(tau), w.D)
+    for i in range(4):
+        np.testing.assert_array_equal(np_(got[i]) if i >= 2 else u32(got[i]), want[i])
+    prm = (w.P, 1, w.M, w.CR, 77)
+    got = mh.subtree_solve(ds, w.D, mh.de_params(*prm))
+    _same_tree(oracle.deoct(ods, w.D, oracle.de_params(*prm)), got)
+
+
 def test_subtree_solve_depth6_walk_path(mh):
     w = synth.plain_small(7, n=1500)
     w.D = 6
