@@ -59,8 +59,14 @@ def _submit(mh, srv, req):
     srv.submit(rid, Xd, yd, K, D, _prm(mh, P, G, M, rid))
 
 
-def test_served_equals_alone_and_oracle(mh):
+@pytest.mark.parametrize("solo", [None, "1", "0"])
+def test_served_equals_alone_and_oracle(mh, monkeypatch, solo):
+    """solo: requests from this many tiles up run whole as one cooperative
+    launch (None: the server's default, two tiles per CU; "1": every request;
+    "0": none, all stepped generation by generation in the batched launches)."""
     from paper_2311_06952_amd import capi
+    if solo is not None:
+        monkeypatch.setenv("MHDEOCT_SERVE_SOLO_TILES", solo)
     big = max(mh.server_footprint(n, F, K, D, P) for _, n, F, K, D, P, _, _ in REQUESTS)
     # room for about two of the largest requests, three slots: requests
     # wait for both, and later ones are admitted while others run
