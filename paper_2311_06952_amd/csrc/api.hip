@@ -68,6 +68,20 @@ void coop_note_failure(Ctx *ctx) {
     ctx->coop_bad.push_back({ctx->last_coop_kern, ctx->last_coop_grid});
 }
 
+mh_status wait_stream(Ctx *ctx) {
+  if (!ctx->done_ev) MH_HIP(ctx, hipEventCreateWithFlags(&ctx->done_ev, hipEventDisableTiming));
+  MH_HIP(ctx, hipEventRecord(ctx->done_ev, ctx->stream));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(ctx->done_ev);
+    if (e == hipSuccess) return MH_OK;
+    if (e != hipErrorNotReady) return hip_fail(ctx, e, "hipEventQuery");
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) break;
+  }
+  MH_HIP(ctx, hipEventSynchronize(ctx->done_ev));
+  return MH_OK;
+}
+
 uint32_t *host_words(Ctx *ctx) {
   if (!ctx->hwords) {
     const hipError_t e = hipHostMalloc((void **)&ctx->hwords, 64 * sizeof(uint32_t));
@@ -350,7 +364,8 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   }
   s = launch_pack_result(ctx, D, f1, t1, lab1, corr1, cost1, err, ds->status, ctx->result);
   if (s) return s;
-  MH_HIP(ctx, hipStreamSynchronize(st));
+  s = wait_stream(ctx);
+  if (s) return s;
   std::memset(out, 0, sizeof(*out));
   out->D = D;
   std::memcpy(out->feat, ctx->result->tree.feat, SB);
@@ -463,6 +478,7 @@ void mh_ctx_destroy(mh_ctx *ctx) {
   for (hipEvent_t e : ctx->c.prof_ev) (void)hipEventDestroy(e);
   if (ctx->c.result) (void)hipHostFree(ctx->c.result);
   if (ctx->c.hwords) (void)hipHostFree(ctx->c.hwords);
+  if (ctx->c.done_ev) (void)hipEventDestroy(ctx->c.done_ev);
   delete ctx;
 }
 

@@ -67,6 +67,8 @@ struct Ctx {
   ResultOut *result = nullptr;
   // pinned host words for small status read-backs (allocated on first use)
   uint32_t *hwords = nullptr;
+  // event for waits on the stream's completed work (created on first use)
+  hipEvent_t done_ev = nullptr;
   // rank encoding in one cooperative launch when it fits (MHDEOCT_RANK_COOP);
   // samples per block forced by MHDEOCT_RANK_R (0 = by size)
   bool rank_coop = true;
@@ -92,6 +94,10 @@ struct Ctx {
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
+// Waits for the work queued so far on the context's stream: polls an event
+// for up to 50 ms (the result of a run is back a few microseconds after the
+// device finishes, where a blocking wait takes tens), then blocks.
+mh_status wait_stream(Ctx *ctx);
 // Blocks of `kern` (threads, dynamic LDS bytes) one CU holds, from the
 // occupancy query, remembered per context; 0 when the query fails.
 int occupancy(Ctx *ctx, const void *kern, int threads, size_t lds);
