@@ -403,12 +403,22 @@ mh_status generation(mh_server *s) {
   return MH_OK;
 }
 
+// Whether a queued request will run whole at admission.
+bool c_solo(const mh_server *s, const Req &q) {
+  return s->c->persist && s->solo_tiles && q.cv.max_tiles >= s->solo_tiles;
+}
+
 mh_status round_once(mh_server *s) {
   mh_status r = collect(s, s->active.empty() && s->queue.empty());
   if (r) return r;
-  // admission, in submission order
+  // admission, in submission order; at most one whole-request run per round,
+  // so that the resident requests get a generation between two of them
+  bool solo_run = false;
   while (!s->queue.empty() && !s->free_slots.empty()) {
     Req &q = s->queue.front();
+    const bool solo = c_solo(s, q);
+    if (solo && solo_run) break;
+    solo_run = solo_run || solo;
     size_t off = 0;
     if (!s->pool.alloc(q.cv.total, &off)) break;
     q.off = off;
