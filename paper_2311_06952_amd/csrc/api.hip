@@ -272,8 +272,6 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   DeDev de{P, D, ds->F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
   uint32_t *err = (uint32_t *)arena_get(ctx, "ss_err", 256);
   if (!err) return MH_ENOMEM;
-  s = launch_zero(ctx, {{es.cnt, es.cnt ? cnt_bytes(1, D, K, P) : 0}, {err, 4}});
-  if (s) return s;
   // g = 0: initialise, decode, evaluate
   s = launch_de_init(ctx, P, D, ds->F, prm->seed, nullptr, prob, 1, warm, W, pop, true);
   if (s) return s;
@@ -285,6 +283,9 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
     if (s) return s;
   }
   if (!persisted) {
+    // (the cooperative launch clears its own flag and counters)
+    s = launch_zero(ctx, {{es.cnt, es.cnt ? cnt_bytes(1, D, K, P) : 0}, {err, 4}});
+    if (s) return s;
     s = launch_decode(ctx, pop, P, D, ds->F, ds->n_unique, feat, tau, 1, nullptr, true);
     if (s) return s;
   }
