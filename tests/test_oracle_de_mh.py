@@ -86,8 +86,9 @@ def test_selection_ties_go_to_trial():
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
 def test_deoct_plain_small_below_exhaustive_optimum(seed):
-    # BASELINE config 1: DEOCT's training correct never exceeds the exact
-    # depth-2 optimum, and its best never gets worse across generations.
+    # The small plain workload (n = 1000, F = 4, K = 2, depth 2, P = 32, 50
+    # generations): DEOCT's training correct never exceeds the exact depth-2
+    # optimum, and its best never gets worse across generations.
     w = synth.plain_small(seed)
     ds = oracle.dataset_from_X(w.X, w.y, w.K)
     prm = oracle.de_params(w.P, w.G, w.M, w.CR, 1000 + seed)
