@@ -57,6 +57,12 @@ int coop_per_cu(Ctx *ctx, const void *kern, int threads, size_t lds) {
   return std::min(r, 4);
 }
 
+hipError_t launch_grid_sync(Ctx *ctx, const void *kern, dim3 grid, dim3 block, void **args,
+                            size_t lds) {
+  if (ctx->coop_api) return hipLaunchCooperativeKernel(kern, grid, block, args, lds, ctx->stream);
+  return hipLaunchKernel(kern, grid, block, args, lds, ctx->stream);
+}
+
 bool coop_is_bad(const Ctx *ctx, const void *kern, uint32_t grid) {
   for (const auto &p : ctx->coop_bad)
     if (p.first == kern && p.second == grid) return true;
@@ -453,6 +459,7 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_DEBUG")) c->c.debug = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_COOP_LAUNCH")) c->c.coop_api = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_WAIT_TICKS"))
     c->c.wait_ticks = std::min<uint64_t>(strtoull(v, nullptr, 10), 200000000ull);
   if (const char *v = std::getenv("MHDEOCT_RANK_R")) {

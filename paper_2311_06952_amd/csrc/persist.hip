@@ -814,8 +814,7 @@ mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_t
                  D, WAVES, H, a.tph ? "true" : "false", grid, per_cu, max_tiles, per_block,
                  lds_use);
   void *args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(H * WAVES * 64), args, lds_use,
-                                            ctx->stream);
+  hipError_t e = launch_grid_sync(ctx, kern, dim3(grid), dim3(H * WAVES * 64), args, lds_use);
   if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
       e == hipErrorInvalidConfiguration) {
     // a shape the launch refuses (LDS, block count): the per-generation

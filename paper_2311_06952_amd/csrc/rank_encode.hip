@@ -547,8 +547,8 @@ mh_status rank_encode_coop(Ctx *ctx, const float *X, uint32_t n, uint32_t F, uin
   a.n_unique = n_unique;
   a.wait_ticks = ctx->wait_ticks;
   void *args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rank_coop), dim3(grid),
-                                            dim3(RC_THREADS), args, rc_lds_bytes(R), ctx->stream);
+  hipError_t e = launch_grid_sync(ctx, reinterpret_cast<const void *>(k_rank_coop), dim3(grid),
+                                  dim3(RC_THREADS), args, rc_lds_bytes(R));
   if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge ||
       e == hipErrorInvalidConfiguration) {
     (void)hipGetLastError();
