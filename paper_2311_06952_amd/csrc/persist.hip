@@ -1,5 +1,5 @@
 // persist.hip -- a whole DEOCT run (Algorithm 4) of one problem as a single
-// cooperative launch.
+// launch whose blocks synchronise through a grid barrier.
 //
 // Every block evaluates its share of the tiles for all P trees (lane = tree,
 // as in the per-generation fitness kernel) and adds its left counts into a
@@ -7,9 +7,10 @@
 // runs the same epilogue, selection, argmin and mutation for the whole
 // population, redundantly: the DE state is a few kilobytes and identical
 // arithmetic on identical inputs gives every block the same next population,
-// so the counts are the only data that cross blocks.  Thread r keeps
-// individual r (parent genes, trial genes, cost) in registers, and the
-// post-selection population sits in LDS for the mutation's parent reads.
+// so the counts are the only data that cross blocks.  Thread r of each wave
+// group keeps individual r's cost and the trial genes of the group's nodes in
+// registers; the post-selection population sits in LDS (the parents of the
+// mutation, and individual r's own genes).
 //
 // Counters rotate over three copies: generation g adds into copy g % 3, all
 // blocks read it between barriers g and g + 1, and each block zeroes its share
@@ -17,8 +18,8 @@
 // barrier g - 1 and is next added into after barrier g).  Cross-block data
 // (counts, the barrier words) moves only through device-scope atomics and
 // agent-scope loads; each wave waits for its own atomics before arriving at a
-// barrier.  A barrier wait gives up after a bounded number of polls and
-// raises the error flag instead of spinning forever.
+// barrier.  A barrier wait gives up after a time limit and raises the error
+// flag instead of spinning forever.
 //
 // The results are those of the per-generation kernels: the same epilogue,
 // the same selection and argmin rules, the same random draws and float64
