@@ -1,7 +1,8 @@
 // grid_sync.h -- a grid barrier for cooperative launches.
 //
-// All blocks of the barrier's group must be co-resident (a cooperative
-// launch guarantees it).  Cross-block data that a barrier orders must move
+// All blocks of the barrier's group must be resident at once: the launcher
+// keeps the grid within what the device holds, with a margin, and a wait's
+// time limit turns a grid that is not resident into an error, not a hang.  Cross-block data that a barrier orders must move
 // through device-scope atomics or agent-scope loads and stores: the L2 of
 // one XCD is not coherent with the others for plain accesses.
 #pragma once
