@@ -39,11 +39,11 @@ def test_split1_subsets_and_pure(mh):
     assert mh.split1(ds, idx=dev(pure)) == oracle.split1(ods, idx=pure) == (0, 0, len(pure))
 
 
-def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9):
+def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9, n_min=1, alpha=0.0):
     ods = oracle.dataset_from_X(X, y, K)
-    want = oracle.mh_train(ods, D, D_MH, oracle.de_params(P, G, M, CR, seed))
+    want = oracle.mh_train(ods, D, D_MH, oracle.de_params(P, G, M, CR, seed, n_min, alpha))
     ds = mh.dataset(X, y, K)
-    prm = mh.de_params(P, G, M, CR, seed)
+    prm = mh.de_params(P, G, M, CR, seed, n_min, alpha)
     seq = mh.mh_train(ds, D, D_MH, prm, batched=False)
     bat = mh.mh_train(ds, D, D_MH, prm, batched=True)
     return want, seq, bat
@@ -66,6 +66,17 @@ def _same(a, b):
 def test_mh_train_matches_oracle(mh, seed, n, F, K, D, D_MH, P, G):
     X, y = synth.random_small(seed, n, F, K, levels=40)
     want, seq, bat = _mh_both(mh, X, y, K, D, D_MH, P, G, 100 + seed)
+    _same(seq, want)
+    _same(bat, want)
+
+
+@pytest.mark.parametrize("n_min,alpha", [(60, 0.0), (30, 12.5), (1, 400.0)])
+def test_mh_train_penalised(mh, n_min, alpha):
+    """Moving horizon under the penalised objective: n_min also decides which
+    nodes of a level are solved (more than n_min samples of two or more
+    classes), alpha prices each split in every subproblem."""
+    X, y = synth.random_small(9, 3000, 5, 3, levels=40)
+    want, seq, bat = _mh_both(mh, X, y, 3, 4, 2, 16, 6, 77, n_min=n_min, alpha=alpha)
     _same(seq, want)
     _same(bat, want)
 

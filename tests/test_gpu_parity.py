@@ -310,6 +310,18 @@ def test_plain_large_full_size(mh):
     _same_tree(oracle.deoct(ods, w.D, oracle.de_params(*prm)), got)
 
 
+@pytest.mark.parametrize("mode,n,P,G", [("normal", 2000, 100, 600), ("long", 400, 200, 4000)])
+def test_paper_parameter_modes(mh, mode, n, P, G):
+    """DEOCT with the paper's parameter modes (Section 4: Normal P = 100,
+    G = 600; Long P = 200, G = 4000; CR = 0.1 and a mutation factor drawn per
+    individual and generation): equal to the oracle's run."""
+    X, y = synth.random_small(300 + P, n, 6, 3)
+    prm = (P, G, -1.0, 0.1, 4242)
+    got = mh.subtree_solve(gpu_ds(mh, X, y, 3), 3, mh.de_params(*prm))
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(*prm))
+    _same_tree(want, got)
+
+
 def test_subtree_solve_depth6_walk_path(mh):
     w = synth.plain_small(7, n=1500)
     w.D = 6
@@ -356,6 +368,32 @@ def test_persistent_and_per_generation_deoct_agree(mh, monkeypatch, D, P, K, M):
     _same_tree(want, out[1])
     ctx_gen.close()
     ctx_per.close()
+
+
+@pytest.mark.parametrize("D,P,K,n_min,alpha", [(2, 64, 3, 40, 150.0), (3, 128, 4, 25, 33.5),
+                                             (4, 96, 2, 200, 0.25), (3, 64, 5, 1, 1e9)])
+def test_penalised_objective_deoct(mh, monkeypatch, D, P, K, n_min, alpha):
+    """DEOCT under the penalised objective (Section 3: a per-split cost alpha
+    and leaves below n_min samples treated as infeasible), whole-run kernel and
+    per-generation kernels against the oracle. With n_min = 1 the cost is the
+    misclassified count plus alpha per split node."""
+    from paper_2311_06952_amd import capi
+    X, y = synth.random_small(70 + D, 5000, 8, K)
+    out = []
+    for persist in ("0", "1"):
+        monkeypatch.setenv("MHDEOCT_PERSIST", persist)
+        ctx = capi.Context(0)
+        ds = mh.dataset(X, y, K, ctx=ctx)
+        out.append(mh.subtree_solve(ds, D, mh.de_params(P, 15, 0.5, 0.9, 9 + D, n_min, alpha),
+                                    ctx=ctx))
+        ctx.close()
+    want = oracle.deoct(oracle.dataset_from_X(X, y, K), D,
+                        oracle.de_params(P, 15, 0.5, 0.9, 9 + D, n_min, alpha))
+    _same_tree(want, out[0])
+    _same_tree(want, out[1])
+    if n_min == 1:
+        nsplit = int(np.count_nonzero(np.asarray(want["feat"])))
+        assert want["cost"] == (len(y) - want["correct"]) + alpha * nsplit
 
 
 _GROUP_SHAPES = [(1, 12, 2, 3000, 5), (3, 256, 3, 20000, 16), (3, 100, 6, 7000, 9),

@@ -100,6 +100,30 @@ def test_served_equals_alone_and_oracle(mh, monkeypatch, solo):
     assert admits == sorted(admits)
 
 
+def test_served_penalised_objective(mh):
+    """Requests with their own n_min and alpha share the server's launches and
+    each still equals the oracle's DEOCT under its own objective."""
+    import torch
+    from paper_2311_06952_amd import capi
+    reqs = [(60, 4000, 6, 3, 3, 64, 10, 40, 25.0), (61, 2500, 5, 2, 2, 32, 12, 1, 0.0),
+            (62, 6000, 8, 4, 4, 96, 8, 150, 3.5)]
+    ctx = capi.Context(0)
+    srv = mh.Server(1 << 30, 3, ctx=ctx)
+    for rid, n, F, K, D, P, G, n_min, alpha in reqs:
+        X, y = _data(rid, n, F, K)
+        srv.submit(rid, torch.as_tensor(X).cuda(), torch.as_tensor(y).cuda(), K, D,
+                   mh.de_params(P, G, 0.5, 0.9, 7000 + rid, n_min, alpha))
+    res = {r["req_id"]: r for r in srv.drain()}
+    srv.close()
+    ctx.close()
+    for rid, n, F, K, D, P, G, n_min, alpha in reqs:
+        assert res[rid]["status"] == 0
+        X, y = _data(rid, n, F, K)
+        want = oracle.deoct(oracle.dataset_from_X(X, y, K), D,
+                            oracle.de_params(P, G, 0.5, 0.9, 7000 + rid, n_min, alpha))
+        _same(res[rid]["tree"], want)
+
+
 def test_server_rejects_oversized_and_reports_nan(mh):
     import torch
     from paper_2311_06952_amd import capi
