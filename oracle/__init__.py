@@ -99,6 +99,11 @@ def _load():
                                  V, C.c_uint32, C.c_uint32, C.POINTER(DEParams), V,
                                  C.c_uint32, C.c_uint64, _f64p, _u8p, _u32p, _u8p,
                                  C.POINTER(C.c_uint32), C.POINTER(C.c_double), V, V]
+    lib.oracle_tree_thresholds.argtypes = [_f32p, C.c_uint32, C.c_uint32, _u8p, _u32p,
+                                           C.c_uint32, _f64p]
+    lib.oracle_predict.argtypes = [_f32p, C.c_uint32, C.c_uint32, _u8p, _f64p, _u8p,
+                                   C.c_uint32, V, V]
+    lib.oracle_predict.restype = C.c_uint32
     lib.oracle_mh_train.argtypes = [_u32p, C.c_size_t, _u32p, C.c_uint32, _u8p,
                                     C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(DEParams), _u8p, _u32p, _u8p,
@@ -348,3 +353,35 @@ def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParams):
                                    C.byref(cost)), "mh_train")
     return dict(feat=feat, tau=tau, label=label, correct=int(correct.value),
                 cost=float(cost.value))
+
+
+# --------------------------------------------------------------------------
+# applying a trained tree to new samples (test accuracy)
+# --------------------------------------------------------------------------
+def tree_thresholds(X, feat, tau, D: int) -> np.ndarray:
+    """Section 3.1 threshold sets in raw units for one tree trained on X
+    (row-major [n][F] float32): the f64 value beta_t each split compares
+    against (reading R13)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, F = X.shape
+    SB = (1 << D) - 1
+    thr = np.zeros(SB, dtype=np.float64)
+    _check(_load().oracle_tree_thresholds(X, n, F, np.ascontiguousarray(feat, dtype=np.uint8),
+                                          np.ascontiguousarray(tau, dtype=np.uint32), D, thr),
+           "tree_thresholds")
+    return thr
+
+
+def predict(X, feat, thr, label, D: int, y=None):
+    """Section 2 routing with raw thresholds: returns (pred [n] uint8, number
+    of rows with pred == y, or 0 without y)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, F = X.shape
+    pred = np.zeros(n, dtype=np.uint8)
+    yv = None if y is None else np.ascontiguousarray(y, dtype=np.uint8)
+    correct = _load().oracle_predict(X, n, F, np.ascontiguousarray(feat, dtype=np.uint8),
+                                     np.ascontiguousarray(thr, dtype=np.float64),
+                                     np.ascontiguousarray(label, dtype=np.uint8), D,
+                                     None if yv is None else yv.ctypes.data_as(C.c_void_p),
+                                     pred.ctypes.data_as(C.c_void_p))
+    return pred, int(correct)

@@ -34,6 +34,9 @@
  *                        properties (monotone best, CR=0, M=0, <= opt2)
  *   oracle_mh_train      parity unpinned against the paper; pinned by the
  *                        horizon-1 special case (greedy tree)
+ *   oracle_tree_thresholds, oracle_predict
+ *                        pinned (the paper's scaled midpoint sets in exact
+ *                        rationals; equal to rank routing on training rows)
  */
 #include <math.h>
 #include <stdint.h>
@@ -676,4 +679,83 @@ int oracle_mh_train(const uint32_t *ranks, size_t ld, const uint32_t *n_unique,
                       cost_out);
   free(counts);
   return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Applying a trained tree to samples it was not trained on (Section 2 tree */
+/* semantics with the Section 3.1 threshold sets; the test accuracy of      */
+/* Section 4; reading R13).  The threshold set of feature p is the midpoints */
+/* of adjacent sorted unique training values, with the scaled 0 (the        */
+/* training minimum) in front.  A split of rank threshold tau therefore     */
+/* sends x left iff x < beta, where, with u_0 < u_1 < ... the unique        */
+/* training values of the feature and n_p their number:                     */
+/*   tau = 0           beta = u_0   (-inf when n_p = 0)                     */
+/*   0 < tau < n_p     beta = (u_{tau-1} + u_tau) / 2                       */
+/*   tau >= n_p        beta = +inf  (reading R2: every sample goes left)    */
+/* Min-max scaling is affine and increasing, so comparing in raw units is   */
+/* the same decision as comparing scaled values.  beta and the comparison   */
+/* are in f64.  A node with a_t = 0 (or a_t > F) gets beta = 0 and sends    */
+/* every sample right.                                                      */
+/* ------------------------------------------------------------------------ */
+static int or_cmp_f(const void *a, const void *b) {
+  float x = *(const float *)a, y = *(const float *)b;
+  return (x < y) ? -1 : (x > y);
+}
+
+/* X: training features, row-major [n][F].  feat / tau: one tree [SB].
+ * thr: out [SB]. */
+int oracle_tree_thresholds(const float *X, uint32_t n, uint32_t F,
+                           const uint8_t *feat, const uint32_t *tau, uint32_t D,
+                           double *thr) {
+  uint32_t SB = (1u << D) - 1u;
+  float *u = (float *)malloc(sizeof(float) * (n ? n : 1));
+  if (!u) return OR_ENOMEM;
+  for (uint32_t t = 0; t < SB; ++t) {
+    uint32_t f = feat[t];
+    thr[t] = 0.0;
+    if (f == 0 || f > F) continue;
+    for (uint32_t i = 0; i < n; ++i) {
+      float v = X[(size_t)i * F + (f - 1)];
+      if (v != v) {
+        free(u);
+        return OR_EINVAL;
+      }
+      u[i] = (v == 0.0f) ? 0.0f : v;
+    }
+    qsort(u, n, sizeof(float), or_cmp_f);
+    uint32_t m = 0; /* unique values, compacted in place */
+    for (uint32_t i = 0; i < n; ++i)
+      if (m == 0 || u[i] != u[m - 1]) u[m++] = u[i];
+    uint32_t k = tau[t];
+    if (k == 0)
+      thr[t] = m ? (double)u[0] : -INFINITY;
+    else if (k >= m)
+      thr[t] = INFINITY;
+    else
+      thr[t] = ((double)u[k - 1] + (double)u[k]) / 2.0;
+  }
+  free(u);
+  return OR_OK;
+}
+
+/* Routes each row of X (row-major [n][F]) through the tree: t <- 1; while
+ * t <= SB: t <- (x_{a_t} < beta_t) ? 2t : 2t + 1; the prediction is the
+ * label of leaf t - 2^D.  Writes pred [n] (if not NULL) and returns the
+ * number of rows whose prediction equals y (0 when y is NULL). */
+uint32_t oracle_predict(const float *X, uint32_t n, uint32_t F, const uint8_t *feat,
+                        const double *thr, const uint8_t *label, uint32_t D,
+                        const uint8_t *y, uint8_t *pred) {
+  uint32_t SB = (1u << D) - 1u, correct = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t t = 1;
+    while (t <= SB) {
+      uint32_t f = feat[t - 1];
+      int left = (f != 0) && (f <= F) && ((double)X[(size_t)i * F + (f - 1)] < thr[t - 1]);
+      t = left ? 2u * t : 2u * t + 1u;
+    }
+    uint8_t p = label[t - (1u << D)];
+    if (pred) pred[i] = p;
+    if (y && y[i] == p) correct += 1;
+  }
+  return correct;
 }
