@@ -251,6 +251,49 @@ def moving_horizon(mh, ctx):
     return out
 
 
+def predict_bench(mh, ctx, w, Xd, yd, tree, reps=16, launches=20):
+    """The trained tree on 10^6 held-out rows of the same mixture (test
+    accuracy), and k_predict's duration on those rows tiled reps times
+    (HIP events on the library's stream, which is torch's current one)."""
+    import torch
+    from paper_2311_06952_amd import synth
+    Xh, yh = synth.plain_scale_heldout(1, 1_000_000)
+    thr = mh.tree_thresholds(ds_of(mh, Xd, yd, w, ctx), Xd, tree, ctx=ctx)
+    _, c_test = mh.predict(Xh, tree, thr, y=yh, ctx=ctx)
+    dev = Xd.device
+    Xb = torch.as_tensor(Xh).to(dev).repeat(reps, 1).contiguous()
+    yb = torch.as_tensor(yh).to(dev).repeat(reps).contiguous()
+    n = int(Xb.shape[0])
+    feat = torch.as_tensor(tree["feat"]).to(dev)
+    label = torch.as_tensor(tree["label"]).to(dev)
+    pred = torch.empty(n, dtype=torch.uint8, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def launch():
+        ctx.check(ctx.lib.mh_predict(ctx.h, Xb.data_ptr(), n, w.F, feat.data_ptr(),
+                                     thr.data_ptr(), label.data_ptr(), w.D, yb.data_ptr(),
+                                     pred.data_ptr(), cnt.data_ptr()))
+
+    launch()
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == reps * c_test
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(launches):
+        launch()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / launches
+    bytes_row = 4 * w.F + 2  # the row, its label, its prediction
+    return {"heldout_rows": len(yh), "test_accuracy": c_test / len(yh),
+            "train_accuracy": tree["correct"] / w.n, "rows_per_launch": n,
+            "ms_per_launch": ms, "rows_per_s": n / (ms * 1e-3),
+            "algorithmic_bytes_per_row": bytes_row,
+            "GB_s": bytes_row * n / (ms * 1e-3) / 1e9,
+            "hbm_frac": bytes_row * n / (ms * 1e-3) / HBM_PEAK,
+            "note": "ms per launch includes the zeroing of the count (one small launch)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +306,8 @@ def main():
                     help="skip the serving and moving-horizon measurements")
     ap.add_argument("--extra-only", action="store_true",
                     help="only the serving and moving-horizon measurements (for profiler runs)")
+    ap.add_argument("--predict-only", action="store_true",
+                    help="only one solve and the held-out predict measurement (for profiler runs)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps fitness-kernel launches "
                          "(for counter runs)")
@@ -301,6 +346,10 @@ def main():
         ranks, nu = mh.rank_encode(Xd, ctx, status=status, out=enc)
         ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
         return mh.subtree_solve(ds, w.D, prm, ctx=ctx)
+
+    if args.predict_only:
+        print(json.dumps({"predict": predict_bench(mh, ctx, w, Xd, yd, step())}), flush=True)
+        return
 
     # launch configuration for this shape, timed on short runs (before the
     # warm-up; it changes timing only)
@@ -353,7 +402,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "F": w.F, "K": w.K, "D": w.D, "P": w.P,
                    "G": w.G, "M": w.M, "CR": w.CR, "form": "plain DEOCT, the whole run in "
-                   "one cooperative launch"},
+                   "one grid-synchronising launch"},
         "kernel_evals_per_s": roof["evals_per_launch"] / (kernel_ms * 1e-3),
         "subtree_solves_per_s": args.steps / el,
         "best_correct": res["correct"],
@@ -362,6 +411,7 @@ def main():
                                                 "fit_blocks_per_cu")},
     }
     if not args.no_extra:
+        out["predict"] = predict_bench(mh, ctx, w, Xd, yd, res)
         out["serving"] = serving(mh)
         # the same forms on a stream of small requests (n log-uniform in
         # [1e3, 2e4]), where a request alone cannot fill the GPU

@@ -271,6 +271,39 @@ mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                  uint32_t n_sub, uint8_t *feat, uint32_t *tau, uint32_t *correct);
 
 /* ---------------------------------------------------------------------- */
+/* Applying a trained tree to held-out samples (Section 2 split rule with   */
+/* the Section 3.1 threshold sets; the test accuracy of Section 4).          */
+/* ---------------------------------------------------------------------- */
+
+/* Raw-unit thresholds of one tree trained on ds.  X: device, row-major
+ * [ds->n][ds->F] float32, the rows ds was rank-encoded from.  feat / tau:
+ * device [SB] (SB = 2^D - 1) as in mh_tree or tree_decode.  Writes thr
+ * (device [SB] float64): with u_0 < u_1 < ... the unique training values of
+ * the node's feature and n_f their number, thr = u_0 for tau = 0 (-inf when
+ * n_f = 0), (u_{tau-1} + u_tau) / 2 in float64 for 0 < tau < n_f, +inf for
+ * tau >= n_f (every sample left, as the rank rule does), and 0 for a node
+ * with feat = 0 or feat > F.  Finite feature values give exactly the rank
+ * rule on the training rows.  The caller owns every buffer; the call only
+ * queues work on the context's stream.  1 <= D <= 10, ds->n <= 2^31;
+ * MH_EINVAL for bad sizes or null pointers. */
+mh_status mh_tree_thresholds(mh_ctx *ctx, const mh_dataset *ds, const float *X,
+                             const uint8_t *feat, const uint32_t *tau, uint32_t D,
+                             double *thr);
+
+/* Routes each row of X (device, row-major [n][F] float32) through the tree
+ * (feat device [SB], thr device [SB] from mh_tree_thresholds, label device
+ * [2^D]): a row goes left at a node iff feat != 0, feat <= F and
+ * (double)x[feat - 1] < thr; it is predicted the label of the leaf it
+ * reaches.  NaN values compare false (right).  Writes pred (device [n]
+ * uint8) unless NULL.  With y (device [n] uint8) and correct (device
+ * uint32) given, *correct receives the number of rows whose prediction
+ * equals y; correct needs y when n > 0.  Only queues work on the context's stream.
+ * n <= 2^31; MH_EINVAL for bad sizes or null pointers. */
+mh_status mh_predict(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, const uint8_t *feat,
+                     const double *thr, const uint8_t *label, uint32_t D, const uint8_t *y,
+                     uint8_t *pred, uint32_t *correct);
+
+/* ---------------------------------------------------------------------- */
 /* a8. Served subtree solves: DEOCT (Algorithm 4) per request on the problem */
 /* of eq. opt_all, with continuous batching.                                 */
 /* ---------------------------------------------------------------------- */

@@ -25,7 +25,8 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_ctx_stats", "mh_rank_encode", "tree_decode", "fitness_eval", "mh_tileset_bytes",
            "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
-           "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune")
+           "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune",
+           "mh_tree_thresholds", "mh_predict")
 
 
 class MhError(RuntimeError):
@@ -109,6 +110,8 @@ def load_library(path: str = LIB_PATH):
         "mh_server_poll": ([V, C.POINTER(ResultC), U32, C.POINTER(U32)], I32),
         "mh_autotune": ([V, C.POINTER(DatasetC), U32, C.POINTER(DEParamsC), U32, C.POINTER(TuneC)],
                         I32),
+        "mh_tree_thresholds": ([V, C.POINTER(DatasetC), V, V, V, U32, V], I32),
+        "mh_predict": ([V, V, U32, U32, V, V, V, U32, V, V, V], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)  # AttributeError if a symbol is missing
@@ -363,6 +366,53 @@ def subtree_solve(ds: Dataset, D: int, prm: DEParamsC, idx=None, warm=None, prob
     ctx.check(ctx.lib.subtree_solve(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp, W,
                                     prob, C.byref(out)))
     return _tree_dict(out)
+
+
+def _on_device(a, dtype, dev):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=dev, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype).contiguous()
+
+
+def tree_thresholds(ds: Dataset, X, tree: dict, ctx: Context | None = None):
+    """mh_tree_thresholds: the float64 thresholds [SB] (on the device) that
+    apply `tree` (a dict from subtree_solve / mh_train) to new rows; X is the
+    float32 [n][F] training matrix ds was encoded from."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    dev = torch.device("cuda", ctx.device)
+    D = int(tree["D"])
+    Xd = _on_device(X, torch.float32, dev)
+    if tuple(Xd.shape) != (ds.n, ds.F):
+        raise ValueError(f"X has shape {tuple(Xd.shape)}, the dataset ({ds.n}, {ds.F})")
+    feat = _on_device(tree["feat"], torch.uint8, dev)
+    tau = _on_device(np.asarray(tree["tau"], dtype=np.uint32).view(np.int32), torch.int32, dev)
+    thr = torch.empty((1 << D) - 1, dtype=torch.float64, device=dev)
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.mh_tree_thresholds(ctx.h, C.byref(dsc), _ptr(Xd), _ptr(feat), _ptr(tau), D,
+                                         _ptr(thr)))
+    return thr
+
+
+def predict(X, tree: dict, thr, y=None, ctx: Context | None = None):
+    """mh_predict: (pred uint8 [n] on the device, number of rows with
+    pred == y, or None without y)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    dev = torch.device("cuda", ctx.device)
+    D = int(tree["D"])
+    Xd = _on_device(X, torch.float32, dev)
+    n, F = int(Xd.shape[0]), int(Xd.shape[1])
+    feat = _on_device(tree["feat"], torch.uint8, dev)
+    label = _on_device(tree["label"], torch.uint8, dev)
+    thr = _on_device(thr, torch.float64, dev)
+    yd = None if y is None else _on_device(y, torch.uint8, dev)
+    pred = torch.empty(n, dtype=torch.uint8, device=dev)
+    correct = None if y is None else torch.empty(1, dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.mh_predict(ctx.h, _ptr(Xd), n, F, _ptr(feat), _ptr(thr), _ptr(label), D,
+                                 _ptr(yd), _ptr(pred), _ptr(correct)))
+    return pred, None if correct is None else int(correct.item())
 
 
 def autotune(ds: Dataset, D: int, prm: DEParamsC, generations: int = 20,

@@ -119,6 +119,16 @@ def plain_scale(seed: int = 1, n: int = 100_000) -> Workload:
     return Workload("plain_scale_n100k_F16_K3_D3_P256_G200", X, y, 3, 3, 256, 200)
 
 
+def plain_scale_heldout(seed: int = 1, n: int = 1_000_000, draw_seed: int = 2):
+    """Rows from the same mixture as plain_scale(seed) (its component means),
+    with draws of their own: a held-out set for the trained tree."""
+    mu = _rng(seed).normal(0.0, np.sqrt(2.0), size=(3, 16))
+    rng = _rng(draw_seed)
+    y = rng.integers(3, size=n)
+    X = (mu[y] + rng.normal(0.0, 1.0, size=(n, 16))).astype(np.float32)
+    return X, y.astype(np.uint8)
+
+
 def plain_large(seed: int = 1, n: int = 1_000_000) -> Workload:
     """n = 1,000,000, F = 32: features 0-15 from a 4-component Gaussian
     mixture, 16-31 U[0,1) noise; K = 4 labels from a planted depth-5 tree
