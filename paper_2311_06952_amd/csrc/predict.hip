@@ -92,7 +92,7 @@ struct PredArgs {
   uint32_t div_m;      // ceil(2^32 / div_w) when div_w > 1: q = umulhi(j, div_m) = j / div_w
 };
 
-constexpr uint32_t PRED_TILE_FLOATS = 8192;  // 32 KB of staged rows per block
+constexpr uint32_t PRED_TILE_FLOATS = 4096;  // 16 KB of staged rows per block
 constexpr uint32_t PRED_UNROLL = 8;          // loads in flight per lane
 
 // j / w for j < 2^16 (a tile holds fewer than 2^16 words) and w < 2^8:
@@ -258,9 +258,10 @@ mh_status mh_predict(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, const 
   const uint32_t m = w > 1 ? (uint32_t)(((1ull << 32) + w - 1) / w) : 0u;
   PredArgs a{X, feat, thr, label, y, pred, correct, n, F, D, tile_rows, w, m};
   const uint32_t tiles = (n + tile_rows - 1) / tile_rows;
-  // about 43 KB of LDS per block: three resident blocks per CU, four
-  // rounds of them
-  const uint32_t blocks = std::min<uint32_t>(tiles, 3u * (uint32_t)c->num_cu * 4u);
+  // about 27 KB of LDS per block: five resident blocks per CU, four rounds
+  // of them (measured: faster than 32 KB tiles at three per CU and 8 KB
+  // tiles at seven)
+  const uint32_t blocks = std::min<uint32_t>(tiles, 5u * (uint32_t)c->num_cu * 4u);
   if (vec)
     k_predict<true><<<blocks, PRED_THREADS, 0, c->stream>>>(a);
   else

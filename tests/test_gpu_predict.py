@@ -79,7 +79,7 @@ def test_random_trees_every_threshold_kind(mh, D):
 @pytest.mark.parametrize("F,n,D", [(100, 5003, 4), (255, 3001, 3), (1, 777, 5), (63, 20000, 6)])
 def test_wide_and_narrow_rows(mh, F, n, D):
     """Row widths that change how many rows one staged tile holds (F = 255:
-    32 rows, F = 100: 81, F = 1: 256), with ragged last tiles."""
+    16 rows, F = 100: 40, F = 63: 64, F = 1: 256), with ragged last tiles."""
     X, y = synth.random_small(40 + F, n, F, 4, levels=50)
     Xtr, ytr, Xte, yte = _split(X, y, F)
     ds = mh.dataset(Xtr, ytr, 4)
