@@ -104,6 +104,9 @@ def _load():
     lib.oracle_predict.argtypes = [_f32p, C.c_uint32, C.c_uint32, _u8p, _f64p, _u8p,
                                    C.c_uint32, V, V]
     lib.oracle_predict.restype = C.c_uint32
+    lib.oracle_tree_encode.argtypes = [_u8p, _u32p, C.c_uint32, C.c_uint32, C.c_uint32, _u32p,
+                                       _f64p]
+    lib.oracle_tree_encode.restype = None
     lib.oracle_mh_train.argtypes = [_u32p, C.c_size_t, _u32p, C.c_uint32, _u8p,
                                     C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(DEParams), _u8p, _u32p, _u8p,
@@ -385,3 +388,16 @@ def predict(X, feat, thr, label, D: int, y=None):
                                      None if yv is None else yv.ctypes.data_as(C.c_void_p),
                                      pred.ctypes.data_as(C.c_void_p))
     return pred, int(correct)
+
+
+def tree_encode(feat, tau, D: int, F: int, n_unique) -> np.ndarray:
+    """The inverse of eq. aenc / eq. benc (reading R14): trees (feat, tau)
+    [P][SB] -> genes [P][2*SB] float64 that decode back to them."""
+    SB = (1 << D) - 1
+    feat = np.ascontiguousarray(feat, dtype=np.uint8).reshape(-1, SB)
+    tau = np.ascontiguousarray(tau, dtype=np.uint32).reshape(-1, SB)
+    P = feat.shape[0]
+    genes = np.zeros((P, 2 * SB), dtype=np.float64)
+    _load().oracle_tree_encode(feat, tau, P, D, F, np.ascontiguousarray(n_unique, dtype=np.uint32),
+                               genes)
+    return genes

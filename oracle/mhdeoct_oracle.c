@@ -34,6 +34,8 @@
  *                        properties (monotone best, CR=0, M=0, <= opt2)
  *   oracle_mh_train      parity unpinned against the paper; pinned by the
  *                        horizon-1 special case (greedy tree)
+ *   oracle_tree_encode   pinned (decode(encode(tree)) == tree, hand-worked
+ *                        genes)
  *   oracle_tree_thresholds, oracle_predict
  *                        pinned (the paper's scaled midpoint sets in exact
  *                        rationals; equal to rank routing on training rows)
@@ -758,4 +760,30 @@ uint32_t oracle_predict(const float *X, uint32_t n, uint32_t F, const uint8_t *f
     if (y && y[i] == p) correct += 1;
   }
   return correct;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoding a tree into genes (the inverse of eq. aenc and eq. benc), for   */
+/* warm starts (Section 4 warm-start variants; reading R14).  Each gene is  */
+/* the centre of the interval that decodes to the node's value:             */
+/*   a^_t = a_t + 0.5,  b^_t = (tau_t + 0.5) / (n_f + 1) for a_t != 0       */
+/* and a^_t = 0.5, b^_t = 0 for a_t = 0 (also for a_t > F, not a feature).   */
+/* feat / tau: [P][SB]; genes: out [P][2*SB] as [a^_1..a^_SB, b^_1..b^_SB]. */
+/* ------------------------------------------------------------------------ */
+void oracle_tree_encode(const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                        uint32_t F, const uint32_t *n_unique, double *genes) {
+  uint32_t SB = (1u << D) - 1u;
+  for (uint32_t r = 0; r < P; ++r) {
+    double *g = genes + (size_t)r * 2 * SB;
+    for (uint32_t t = 0; t < SB; ++t) {
+      uint32_t f = feat[(size_t)r * SB + t];
+      if (f == 0 || f > F) {
+        g[t] = 0.5;
+        g[SB + t] = 0.0;
+      } else {
+        g[t] = (double)f + 0.5;
+        g[SB + t] = ((double)tau[(size_t)r * SB + t] + 0.5) / ((double)n_unique[f - 1] + 1.0);
+      }
+    }
+  }
 }

@@ -110,3 +110,32 @@ def test_nan_in_training_column_is_rejected():
     X = np.array([[1.0], [np.nan]], dtype=np.float32)
     with pytest.raises(Exception):
         oracle.tree_thresholds(X, np.array([1], dtype=np.uint8), np.array([1], dtype=np.uint32), 1)
+
+
+# --------------------------------------------------------------------------
+# encoding a tree into genes (inverse of eq. aenc / eq. benc; reading R14)
+# --------------------------------------------------------------------------
+def test_encode_hand_worked():
+    nu = np.array([3, 9], dtype=np.uint32)
+    g = oracle.tree_encode(np.array([1, 0, 2], np.uint8), np.array([2, 5, 9], np.uint32), 2, 2, nu)
+    # a^ = feat + 0.5; b^ = (tau + 0.5) / (n_f + 1); no split: (0.5, 0)
+    assert list(g[0]) == [1.5, 0.5, 2.5, 2.5 / 4, 0.0, 9.5 / 10]
+
+
+@pytest.mark.parametrize("D,F,nu_hi", [(1, 3, 5), (3, 16, 100_000), (5, 7, 2), (2, 200, 1 << 24),
+                                       (4, 1, 1)])
+def test_decode_of_encode_is_identity(D, F, nu_hi):
+    """Every (feature, tau) pair, tau from 0 to n_f, survives the round trip
+    through the decode of eqs. aenc and benc."""
+    rng = np.random.default_rng(D * 1000 + F)
+    nu = rng.integers(1, nu_hi + 1, size=F).astype(np.uint32)
+    nu[0] = nu_hi
+    SB = (1 << D) - 1
+    P = 64
+    feat = rng.integers(0, F + 1, size=(P, SB)).astype(np.uint8)
+    tau = np.array([[[0, nu[f - 1], rng.integers(0, nu[f - 1] + 1)][rng.integers(0, 3)] if f else 0
+                     for f in row] for row in feat], dtype=np.uint32)
+    genes = oracle.tree_encode(feat, tau, D, F, nu)
+    f2, t2 = oracle.decode(genes, D, F, nu)
+    np.testing.assert_array_equal(f2, feat)
+    np.testing.assert_array_equal(t2, tau)
