@@ -154,6 +154,16 @@ mh_status tree_decode(mh_ctx *ctx, const double *genes, uint32_t P, uint32_t D,
                       uint32_t F, const uint32_t *n_unique, uint8_t *feat,
                       uint32_t *tau);
 
+/* The inverse of tree_decode, for warm starts (the warm-started variants
+ * of Section 4): feat / tau device [P][SB] -> genes device [P][2*SB]
+ * float64 with a^_t = feat_t + 0.5 and b^_t = (tau_t + 0.5) / (n_unique[
+ * feat_t - 1] + 1), the centre of the interval that decodes to the node;
+ * (0.5, 0) for feat_t = 0 or feat_t > F.  tree_decode of the result gives
+ * (feat, tau) back for every tau in [0, n_unique].  Only queues work on the
+ * context's stream.  MH_EINVAL for bad sizes or null pointers. */
+mh_status tree_encode(mh_ctx *ctx, const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                      uint32_t D, uint32_t F, const uint32_t *n_unique, double *genes);
+
 /* ---------------------------------------------------------------------- */
 /* a3-a5. Fitness of P trees (Algorithm 1; eq. opt_c; eq. opt_all; the      */
 /* soft-constraint fitness of Section 3.2).                                  */

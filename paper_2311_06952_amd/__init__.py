@@ -9,9 +9,9 @@ binding, with torch used only for device memory and streams.
 from .capi import (Context, Dataset, MhError, Server, TileSet, autotune, dataset,  # noqa
                    de_init, de_params, de_step, default_context, fitness_eval, load_library,
                    mh_train, predict, rank_encode, server_footprint, split1, subtree_solve,
-                   tree_decode, tree_thresholds)
+                   tree_decode, tree_encode, tree_thresholds)
 
 __all__ = ["Context", "Dataset", "MhError", "Server", "TileSet", "autotune", "dataset", "de_init",
            "de_params", "de_step", "default_context", "fitness_eval", "load_library", "mh_train",
            "predict", "rank_encode", "server_footprint", "split1", "subtree_solve", "tree_decode",
-           "tree_thresholds"]
+           "tree_encode", "tree_thresholds"]

@@ -26,7 +26,7 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
            "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune",
-           "mh_tree_thresholds", "mh_predict")
+           "mh_tree_thresholds", "mh_predict", "tree_encode")
 
 
 class MhError(RuntimeError):
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
                         I32),
         "mh_tree_thresholds": ([V, C.POINTER(DatasetC), V, V, V, U32, V], I32),
         "mh_predict": ([V, V, U32, U32, V, V, V, U32, V, V, V], I32),
+        "tree_encode": ([V, V, V, U32, U32, U32, V, V], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)  # AttributeError if a symbol is missing
@@ -255,6 +256,24 @@ def tree_decode(genes, D: int, F: int, n_unique, ctx: Context | None = None):
     ctx.check(ctx.lib.tree_decode(ctx.h, _ptr(genes), P, D, F, _ptr(n_unique), _ptr(feat),
                                   _ptr(tau)))
     return feat, tau
+
+
+def tree_encode(feat, tau, D: int, F: int, n_unique, ctx: Context | None = None):
+    """tree_encode: trees (feat, tau) [P][SB] -> genes [P][2*SB] float64 on
+    the device (the inverse of tree_decode, for warm starts)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    dev = torch.device("cuda", ctx.device)
+    SB = (1 << D) - 1
+    feat = _on_device(np.asarray(feat).reshape(-1, SB) if not isinstance(feat, torch.Tensor)
+                      else feat.reshape(-1, SB), torch.uint8, dev)
+    tau = tau if isinstance(tau, torch.Tensor) else np.asarray(tau, dtype=np.uint32).view(np.int32)
+    tau = _on_device(tau, torch.int32, dev).reshape(-1, SB)
+    P = int(feat.shape[0])
+    genes = torch.empty((P, 2 * SB), dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.tree_encode(ctx.h, _ptr(feat), _ptr(tau), P, D, F, _ptr(n_unique),
+                                  _ptr(genes)))
+    return genes
 
 
 def fitness_eval(ds: Dataset, feat, tau, D: int, idx=None, n_min: int = 1, alpha: float = 0.0,

@@ -1,7 +1,9 @@
 """Pins of the oracle's tree application to new samples (Section 2 routing
 with the Section 3.1 threshold sets; the test accuracy of Section 4; readings
 R2 and R13): against the paper's literal scaled midpoint sets in exact
-rationals, and against rank routing on the training rows."""
+rationals, and against rank routing on the training rows.  Also the encoding
+of a tree into genes (reading R14), pinned by the decode of eqs. aenc and
+benc."""
 from fractions import Fraction
 
 import numpy as np
