@@ -329,6 +329,18 @@ def test_subtree_solve_depth6_walk_path(mh):
     _same_tree(want, got)
 
 
+@pytest.mark.parametrize("D,n,P,G,M", [(8, 5000, 32, 10, 0.5), (8, 3001, 100, 6, -1.0),
+                                       (10, 2000, 16, 4, 0.5)])
+def test_whole_tree_deep_deoct(mh, D, n, P, G, M):
+    """Whole-tree DEOCT at depth 8 (510 genes) and 10 (2046 genes), the deep
+    setting DEOCT alone is compared in (Section 4), equal to the oracle's."""
+    X, y = synth.random_small(900 + D, n, 9, 4, levels=60)
+    prm = (P, G, M, 0.9, 31 + D)
+    got = mh.subtree_solve(gpu_ds(mh, X, y, 4), D, mh.de_params(*prm))
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 4), D, oracle.de_params(*prm))
+    _same_tree(want, got)
+
+
 def test_fused_and_separate_de_step_agree(mh, monkeypatch):
     """The fused launch (DE step run by the block that completes the counts)
     and the separate DE-step launch give the same DEOCT run."""
