@@ -65,16 +65,19 @@ __global__ void k_decode(const double *__restrict__ genes, uint32_t P, uint32_t 
   tau[e] = th;
 }
 
-// One block per problem, thread r = individual r; trial costs from memory.
-__global__ __launch_bounds__(1024) void k_de_step(StepArgs a) {
+// One block per problem; tpi threads per individual (individual r =
+// threadIdx.x % nr, its lane j = threadIdx.x / nr, nr = blockDim.x / tpi a
+// power of two >= P); trial costs from memory.
+__global__ __launch_bounds__(1024) void k_de_step(StepArgs a, uint32_t tpi) {
   __shared__ double s_cost[1024];
   __shared__ uint32_t s_idx[1024];
   __shared__ uint32_t s_nu[256];
   extern __shared__ double rows[];
-  const uint32_t sub = blockIdx.x, r = threadIdx.x;
+  const uint32_t nr = blockDim.x / tpi;
+  const uint32_t sub = blockIdx.x, r = threadIdx.x % nr, j = threadIdx.x / nr;
   const bool select = a.trial != nullptr;
   const double tc = (select && r < a.P) ? a.trial_cost[(size_t)sub * a.P + r] : 0.0;
-  de_step_body(a, sub, r, 0, 1, select, false, tc, s_cost, s_idx, a.rows_in_lds ? rows : nullptr,
+  de_step_body(a, sub, r, j, tpi, select, false, tc, s_cost, s_idx, a.rows_in_lds ? rows : nullptr,
                s_nu);
 }
 
@@ -272,8 +275,13 @@ mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, ui
                          double *next_trial, uint8_t *feat, uint32_t *tau) {
   StepArgs a = make_args(de, prob_ids, prob_base, g, pop, cost, trial, trial_cost, best,
                          next_trial, feat, tau);
-  const uint32_t threads = step_threads(de.P);
-  k_de_step<<<n_problems, threads, rows_lds_bytes(de.P, de.D), ctx->stream>>>(a);
+  const uint32_t nr = step_threads(de.P);
+  // deep trees: several threads per individual share its nodes (about 32
+  // genes each); shallow ones keep one
+  const uint32_t m = 2u * ((1u << de.D) - 1u);
+  uint32_t tpi = 1;
+  while (tpi * 2u * nr <= 1024u && tpi * 2u * 32u <= m) tpi *= 2u;
+  k_de_step<<<n_problems, nr * tpi, rows_lds_bytes(de.P, de.D), ctx->stream>>>(a, tpi);
   MH_LAUNCHED(ctx, "k_de_step");
   return MH_OK;
 }

@@ -232,9 +232,11 @@ __global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------------------
-// Walk kernel (any depth).  Block = 256 threads over a chunk of samples; for
-// each tree: stage (feat, tau) in LDS, walk every sample of the chunk down
-// the tree, histogram (leaf, class) in LDS, add the histogram to leafcnt.
+// Walk kernel (any depth).  Block = 256 threads over a chunk of samples and
+// every gridDim.y-th tree; for each tree: stage (feat, tau) in LDS, walk
+// every sample of the chunk down the tree, histogram (leaf, class) in LDS,
+// add the histogram to leafcnt.  The trees are spread over the grid's second
+// dimension so that a small sample count still fills the chip.
 // ---------------------------------------------------------------------------
 constexpr uint32_t WALK_THREADS = 256;
 constexpr uint32_t WALK_ITEMS = 8;
@@ -249,23 +251,9 @@ __global__ __launch_bounds__(WALK_THREADS) void k_fitness_walk(
   uint32_t *s_feat = wl;
   uint32_t *s_tau = wl + SB;
   uint32_t *hist = wl + 2 * SB;
-  const uint32_t j0 = blockIdx.x * WALK_THREADS * WALK_ITEMS;
-  uint32_t ii[WALK_ITEMS];
-  uint32_t yy[WALK_ITEMS];
-#pragma unroll
-  for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
-    uint32_t j = j0 + k * WALK_THREADS + threadIdx.x;
-    ii[k] = 0xFFFFFFFFu;
-    yy[k] = 0;
-    if (j < n_sub) {
-      const uint32_t i = idx ? idx[j] : j;
-      if (i < n && labels[i] < K) {  // invalid samples are left out
-        ii[k] = i;
-        yy[k] = labels[i];
-      }
-    }
-  }
-  for (uint32_t r = 0; r < P; ++r) {
+  constexpr uint32_t CHUNK = WALK_THREADS * WALK_ITEMS;
+  const uint32_t n_chunks = (n_sub + CHUNK - 1) / CHUNK;
+  for (uint32_t r = blockIdx.y; r < P; r += gridDim.y) {
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < SB; t += WALK_THREADS) {
       uint32_t f = feat[(size_t)r * SB + t];
@@ -277,20 +265,38 @@ __global__ __launch_bounds__(WALK_THREADS) void k_fitness_walk(
       for (uint32_t e = threadIdx.x; e < SL * K; e += WALK_THREADS) hist[e] = 0;
     __syncthreads();
     uint32_t *dst = leafcnt + (size_t)r * SL * K;
+    // every gridDim.x-th chunk of samples, all into the one LDS histogram
+    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+      uint32_t ii[WALK_ITEMS];
+      uint32_t yy[WALK_ITEMS];
 #pragma unroll
-    for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
-      if (ii[k] == 0xFFFFFFFFu) continue;
-      uint32_t t = 1;
-      while (t <= SB) {
-        uint32_t f = s_feat[t - 1];
-        bool left = f != 0 && ranks[(size_t)(f - 1) * ld + ii[k]] < s_tau[t - 1];
-        t = left ? 2 * t : 2 * t + 1;
+      for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
+        const uint32_t j = c * CHUNK + k * WALK_THREADS + threadIdx.x;
+        ii[k] = 0xFFFFFFFFu;
+        yy[k] = 0;
+        if (j < n_sub) {
+          const uint32_t i = idx ? idx[j] : j;
+          if (i < n && labels[i] < K) {  // invalid samples are left out
+            ii[k] = i;
+            yy[k] = labels[i];
+          }
+        }
       }
-      uint32_t e = (t - SL) * K + yy[k];
-      if (hist_in_lds)
-        atomicAdd(&hist[e], 1u);
-      else
-        atomicAdd(&dst[e], 1u);
+#pragma unroll
+      for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
+        if (ii[k] == 0xFFFFFFFFu) continue;
+        uint32_t t = 1;
+        while (t <= SB) {
+          uint32_t f = s_feat[t - 1];
+          bool left = f != 0 && ranks[(size_t)(f - 1) * ld + ii[k]] < s_tau[t - 1];
+          t = left ? 2 * t : 2 * t + 1;
+        }
+        uint32_t e = (t - SL) * K + yy[k];
+        if (hist_in_lds)
+          atomicAdd(&hist[e], 1u);
+        else
+          atomicAdd(&dst[e], 1u);
+      }
     }
     if (hist_in_lds) {
       __syncthreads();
@@ -300,15 +306,21 @@ __global__ __launch_bounds__(WALK_THREADS) void k_fitness_walk(
   }
 }
 
-// Epilogue from leaf counts (walk path), any depth.  Thread per tree.
-__global__ void k_epilogue_leaves(uint32_t *__restrict__ leafcnt, const uint8_t *__restrict__ feat,
-                                  uint32_t P, uint32_t D, uint32_t K, uint32_t n_min, double alpha,
-                                  FitnessOut out) {
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+// Epilogue from leaf counts (walk path), any depth.  Block per tree: the
+// threads share out the leaves (and the nodes for the split count) and the
+// integer sums meet in a block reduction, so the result does not depend on
+// the order.
+constexpr uint32_t EPI_THREADS = 256;
+
+__global__ __launch_bounds__(EPI_THREADS) void k_epilogue_leaves(
+    uint32_t *__restrict__ leafcnt, const uint8_t *__restrict__ feat, uint32_t P, uint32_t D,
+    uint32_t K, uint32_t n_min, double alpha, FitnessOut out) {
+  __shared__ uint32_t s_red[4][EPI_THREADS / 64];
+  const uint32_t r = blockIdx.x;
   if (r >= P) return;
   const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
   uint32_t correct = 0, nviol = 0, nsplit = 0, n_sub = 0;
-  for (uint32_t l = 0; l < SL; ++l) {
+  for (uint32_t l = threadIdx.x; l < SL; l += EPI_THREADS) {
     uint32_t *c = leafcnt + ((size_t)r * SL + l) * K;
     uint32_t best = 0, bk = 0, nl = 0;
     for (uint32_t k = 0; k < K; ++k) {
@@ -326,7 +338,23 @@ __global__ void k_epilogue_leaves(uint32_t *__restrict__ leafcnt, const uint8_t 
     nviol += (nl > 0 && nl < n_min) ? 1u : 0u;
     if (out.label) out.label[(size_t)r * SL + l] = (uint8_t)bk;
   }
-  for (uint32_t t = 0; t < SB; ++t) nsplit += feat[(size_t)r * SB + t] != 0;
+  for (uint32_t t = threadIdx.x; t < SB; t += EPI_THREADS) nsplit += feat[(size_t)r * SB + t] != 0;
+  uint32_t v4[4] = {correct, nviol, nsplit, n_sub};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (uint32_t o = 32; o > 0; o >>= 1) v4[q] += __shfl_xor(v4[q], o, 64);
+    if ((threadIdx.x & 63u) == 0) s_red[q][threadIdx.x >> 6] = v4[q];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 4; ++q) {
+    v4[q] = 0;
+    for (uint32_t w = 0; w < EPI_THREADS / 64; ++w) v4[q] += s_red[q][w];
+  }
+  correct = v4[0];
+  nviol = v4[1];
+  nsplit = v4[2];
+  n_sub = v4[3];
   if (out.correct) out.correct[r] = correct;
   if (out.cost) {
     double v = (double)(n_sub - correct);
@@ -502,18 +530,26 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   const uint32_t in_lds = hist_cells <= 12288u ? 1u : 0u;
   size_t lds = (size_t)(2 * SB + (in_lds ? hist_cells : 0u)) * 4;
   if (n_sub > 0) {
-    uint32_t blocks = (n_sub + WALK_THREADS * WALK_ITEMS - 1) / (WALK_THREADS * WALK_ITEMS);
+    const uint32_t chunks = (n_sub + WALK_THREADS * WALK_ITEMS - 1) / (WALK_THREADS * WALK_ITEMS);
+    // about 8 blocks per CU in all: one tree per block row where there are
+    // enough trees, the chunks of samples shared out over the rest (each
+    // block adds its histogram to memory once per tree)
+    const uint32_t want = 8u * (uint32_t)ctx->num_cu;
+    const uint32_t gy = std::max(1u, std::min(P, want));
+    const uint32_t blocks = std::max(1u, std::min(chunks, (want + gy - 1) / gy));
     hipEvent_t e0, e1;
     const bool timed = prof_pair(ctx, &e0, &e1);
-    hipExtLaunchKernelGGL(k_fitness_walk, dim3(blocks), dim3(WALK_THREADS), lds, st, e0, e1, 0,
+    hipExtLaunchKernelGGL(k_fitness_walk, dim3(blocks, gy), dim3(WALK_THREADS), lds, st, e0, e1, 0,
                           ds->ranks, ds->ld, ds->labels, idx, n_sub, feat, tau, P, D, ds->F,
                           ds->K, ds->n, leafcnt, in_lds);
     MH_LAUNCHED(ctx, "k_fitness_walk");
     if (timed) ctx->prof_launches += 1;
     ctx->prof_evals += (uint64_t)n_sub * P;
   }
-  k_epilogue_leaves<<<(P + 127) / 128, 128, 0, st>>>(leafcnt, feat, P, D, ds->K, n_min, alpha, out);
-  MH_LAUNCHED(ctx, "k_epilogue_leaves");
+  if (P > 0) {
+    k_epilogue_leaves<<<P, EPI_THREADS, 0, st>>>(leafcnt, feat, P, D, ds->K, n_min, alpha, out);
+    MH_LAUNCHED(ctx, "k_epilogue_leaves");
+  }
   return MH_OK;
 }
 
