@@ -268,6 +268,34 @@ def deep_whole_tree(mh, ctx, w, Xd, yd):
             "s": el, "evals_per_s": P * w.n * (G + 1) / el, "correct": r["correct"]}
 
 
+def alpha_sweep(mh, ctx, w, alphas=(0.0, 3.0, 10.0, 30.0, 100.0, 300.0, 1000.0), D=4):
+    """Choosing the per-split penalty alpha by validation (the sweep of
+    Section 3.2's penalised objective): the plain-scale data split 75/25 into
+    training and validation rows, a depth-4 tree solved per alpha (P = 256,
+    G = 200), scored on the validation rows; the chosen tree's accuracy on the
+    10^6 held-out rows.  Every solve and score runs on the device."""
+    import numpy as np
+    from paper_2311_06952_amd import synth
+    perm = np.random.default_rng(3).permutation(w.n)
+    cut = (3 * w.n) // 4
+    Xtr, ytr = w.X[perm[:cut]], w.y[perm[:cut]]
+    Xva, yva = w.X[perm[cut:]], w.y[perm[cut:]]
+    ds = mh.dataset(Xtr, ytr, w.K, ctx=ctx)
+    rows = []
+    best = None
+    for a in alphas:
+        t = mh.subtree_solve(ds, D, mh.de_params(w.P, w.G, w.M, w.CR, 1001, 1, a), ctx=ctx)
+        thr = mh.tree_thresholds(ds, Xtr, t, ctx=ctx)
+        _, cv = mh.predict(Xva, t, thr, y=yva, ctx=ctx)
+        rows.append({"alpha": a, "splits": int(np.count_nonzero(t["feat"])),
+                     "train_acc": t["correct"] / cut, "val_acc": cv / len(yva)})
+        if best is None or cv > best[0]:
+            best = (cv, a, t, thr)
+    Xh, yh = synth.plain_scale_heldout(1, 1_000_000)
+    _, ch = mh.predict(Xh, best[2], best[3], y=yh, ctx=ctx)
+    return {"depth": D, "sweep": rows, "chosen_alpha": best[1], "heldout_acc": ch / len(yh)}
+
+
 def predict_bench(mh, ctx, w, Xd, yd, tree, reps=16, launches=20):
     """The trained tree on 10^6 held-out rows of the same mixture (test
     accuracy), and k_predict's duration on those rows tiled reps times
@@ -325,6 +353,8 @@ def main():
                     help="only the serving and moving-horizon measurements (for profiler runs)")
     ap.add_argument("--predict-only", action="store_true",
                     help="only one solve and the held-out predict measurement (for profiler runs)")
+    ap.add_argument("--alpha-only", action="store_true",
+                    help="only the alpha sweep with validation")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps fitness-kernel launches "
                          "(for counter runs)")
@@ -366,6 +396,9 @@ def main():
 
     if args.predict_only:
         print(json.dumps({"predict": predict_bench(mh, ctx, w, Xd, yd, step())}), flush=True)
+        return
+    if args.alpha_only:
+        print(json.dumps({"alpha_sweep": alpha_sweep(mh, ctx, w)}), flush=True)
         return
 
     # launch configuration for this shape, timed on short runs (before the
@@ -430,6 +463,7 @@ def main():
     if not args.no_extra:
         out["predict"] = predict_bench(mh, ctx, w, Xd, yd, res)
         out["deep_whole_tree"] = deep_whole_tree(mh, ctx, w, Xd, yd)
+        out["alpha_sweep"] = alpha_sweep(mh, ctx, w)
         out["serving"] = serving(mh)
         # the same forms on a stream of small requests (n log-uniform in
         # [1e3, 2e4]), where a request alone cannot fill the GPU
