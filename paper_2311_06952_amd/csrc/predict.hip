@@ -24,7 +24,8 @@
 // k_predict stages tiles of rows in LDS, routes each row through the tree
 // (also in LDS) and writes the leaf label; with labels given it counts the
 // matches (a register count per thread, one atomic per block).  It reads
-// each row once: HBM-bound at 4F + 2 bytes per sample.
+// each row once, with nontemporal loads: HBM-bound at 4F + 2 bytes per
+// sample.
 #include "internal.h"
 
 namespace mh {
@@ -94,6 +95,8 @@ struct PredArgs {
 
 constexpr uint32_t PRED_TILE_FLOATS = 4096;  // 16 KB of staged rows per block
 constexpr uint32_t PRED_UNROLL = 8;          // loads in flight per lane
+// the streaming loads of X are nontemporal (each row is read once)
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // j / w for j < 2^16 (a tile holds fewer than 2^16 words) and w < 2^8:
 // the multiply-high by ceil(2^32 / w) is exact there.
@@ -137,7 +140,12 @@ __global__ __launch_bounds__(PRED_THREADS) void k_predict(PredArgs a) {
 #pragma unroll
         for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
           const uint32_t j = j0 + u * PRED_THREADS;
-          v[u] = j < cnt ? src4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+          if (j < cnt) {
+            const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(src4) + j);
+            v[u] = make_float4(t.x, t.y, t.z, t.w);
+          } else {
+            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
         }
 #pragma unroll
         for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(PRED_THREADS) void k_predict(PredArgs a) {
 #pragma unroll
         for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
           const uint32_t j = j0 + u * PRED_THREADS;
-          v[u] = j < cnt ? src[j] : 0.0f;
+          v[u] = j < cnt ? __builtin_nontemporal_load(src + j) : 0.0f;
         }
 #pragma unroll
         for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
@@ -258,10 +266,10 @@ mh_status mh_predict(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, const 
   const uint32_t m = w > 1 ? (uint32_t)(((1ull << 32) + w - 1) / w) : 0u;
   PredArgs a{X, feat, thr, label, y, pred, correct, n, F, D, tile_rows, w, m};
   const uint32_t tiles = (n + tile_rows - 1) / tile_rows;
-  // about 27 KB of LDS per block: five resident blocks per CU, four rounds
-  // of them (measured: faster than 32 KB tiles at three per CU and 8 KB
-  // tiles at seven)
-  const uint32_t blocks = std::min<uint32_t>(tiles, 5u * (uint32_t)c->num_cu * 4u);
+  // about 27 KB of LDS per block: five resident blocks per CU, two rounds
+  // of them (measured: faster than 32 KB tiles at three per CU and 8 KB or
+  // 12 KB tiles at seven)
+  const uint32_t blocks = std::min<uint32_t>(tiles, 5u * (uint32_t)c->num_cu * 2u);
   if (vec)
     k_predict<true><<<blocks, PRED_THREADS, 0, c->stream>>>(a);
   else
