@@ -41,6 +41,80 @@ def test_init_ranges_and_warm_starts():
     assert not np.array_equal(pop, oracle.de_init(P, D, F, 42, 1, warm))
 
 
+def _chi2(counts):
+    counts = np.asarray(counts, dtype=np.float64)
+    exp = counts.sum() / len(counts)
+    return float(np.sum((counts - exp) ** 2 / exp))
+
+
+def test_init_genes_cover_their_ranges_uniformly():
+    """Algorithm 4 draws the initial population inside the range limits, and
+    eq. aenc / eq. benc give the range of the feature gene as [0, F + 1) (so
+    that floor picks "no split" or one of the F features) and of the
+    threshold gene as [0, 1]: over 14,336 initial individuals' nodes the
+    decoded feature hits every value 0..F with equal frequency and the
+    threshold gene fills [0, 1) evenly (chi-square at far below the 0.1 %
+    level for these degrees of freedom).  A scale of U * F would never select
+    feature F."""
+    D, F, P = 3, 6, 512
+    SB = (1 << D) - 1
+    a = np.concatenate([oracle.de_init(P, D, F, 77, prob)[:, :SB].ravel() for prob in range(4)])
+    b = np.concatenate([oracle.de_init(P, D, F, 77, prob)[:, SB:].ravel() for prob in range(4)])
+    assert a.size == 4 * P * SB >= 10_000
+    assert (a >= 0).all() and (a < F + 1).all() and (b >= 0).all() and (b < 1).all()
+    feat_hist = np.bincount(np.floor(a).astype(int), minlength=F + 1)
+    assert len(feat_hist) == F + 1 and feat_hist.min() > 0
+    assert _chi2(feat_hist) < 22.5           # 6 degrees of freedom, p = 0.001
+    thr_hist = np.bincount(np.floor(b * 10).astype(int), minlength=10)
+    assert _chi2(thr_hist) < 27.9            # 9 degrees of freedom, p = 0.001
+    # the decoded features (eq. aenc) of one population follow the same law
+    nu = np.full(F, 50, dtype=np.uint32)
+    feat, _ = oracle.decode(oracle.de_init(P, D, F, 78, 0), D, F, nu)
+    assert set(np.unique(feat)) == set(range(F + 1))
+
+
+def test_random_mutation_factor_is_one_draw_per_individual():
+    """With M < 0 the mutation factor is drawn from U[0, 1) (Section 3.3),
+    once per individual and generation (reading R8): for CR = 1 every trial
+    gene is the mutant v_q = s_best,q + M_r (s_r1,q - s_r2,q), so where no
+    clamp bit, (v_q - s_best,q) / (s_r1,q - s_r2,q) is the same number for all
+    genes q of an individual, lies in [0, 1), and is uniform over the
+    individuals of a generation and across generations.  A draw per gene or
+    per generation fails these checks."""
+    D, F, P = 2, 4, 400
+    m = 2 * ((1 << D) - 1)
+    SB = m // 2
+    hi = np.array([F + 1.0] * SB + [1.0] * SB)
+    pop = oracle.de_init(P, D, F, 5, 0)
+    best = 17
+    Ms = []
+    for g in range(1, 26):
+        trial = oracle.de_trial(pop, D, F, -1.0, 1.0, 5, 0, g, best)
+        gen = []
+        for r in range(P):
+            r1, r2, _ = oracle.de_pick(P, m, 5, 0, g, r)
+            d = pop[r1] - pop[r2]
+            ok = (trial[r] > 0) & (trial[r] < hi) & (np.abs(d) > 1e-3)
+            if ok.sum() < 2:
+                continue
+            ratio = (trial[r][ok] - pop[best][ok]) / d[ok]
+            assert ratio.max() - ratio.min() < 1e-9
+            gen.append(ratio.mean())
+        gen = np.array(gen)
+        assert len(gen) > 300 and (gen > -1e-9).all() and (gen < 1.0).all()
+        assert gen.std() > 0.2          # not one factor for the whole generation
+        Ms.append(gen)
+    Ms = np.concatenate(Ms)
+    hist = np.bincount(np.clip(np.floor(Ms * 10), 0, 9).astype(int), minlength=10)
+    assert _chi2(hist) < 27.9           # 9 degrees of freedom, p = 0.001
+    # a fixed M >= 0 gives that factor exactly where no clamp bit
+    trial = oracle.de_trial(pop, D, F, 0.5, 1.0, 5, 0, 3, best)
+    r1, r2, _ = oracle.de_pick(P, m, 5, 0, 3, 0)
+    d = pop[r1] - pop[r2]
+    ok = (trial[0] > 0) & (trial[0] < hi) & (np.abs(d) > 1e-3)
+    np.testing.assert_allclose((trial[0][ok] - pop[best][ok]) / d[ok], 0.5, rtol=0, atol=1e-9)
+
+
 def test_trial_cr_zero_changes_only_q_rand():
     D, F, P = 3, 4, 12
     m = 2 * ((1 << D) - 1)
