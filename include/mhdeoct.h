@@ -239,6 +239,17 @@ mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                         const double *warm, uint32_t W, uint64_t problem_id,
                         mh_tree *out);
 
+/* subtree_solve, and the whole final population of the run (Algorithm 4:
+ * the population after the selection of generation G): pop_out device
+ * [P][2*SB] float64 in the layout of de_init, cost_out device [P] float64,
+ * each individual's objective after that selection.  Either may be NULL.
+ * Same arguments, errors and synchronisation as subtree_solve; the caller
+ * owns both buffers. */
+mh_status subtree_solve_pop(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                            uint32_t n_sub, uint32_t D, const mh_de_params *prm,
+                            const double *warm, uint32_t W, uint64_t problem_id, mh_tree *out,
+                            double *pop_out, double *cost_out);
+
 /* Launch-configuration autotuning for DEOCT runs on a dataset shape: times
  * short runs (G = generations, on all of ds) of each candidate (the whole-run
  * cooperative kernel with one or two tile streams per block and 1, 2 or 4
@@ -324,7 +335,9 @@ typedef struct mh_server mh_server;
 typedef struct {
   uint64_t req_id;
   mh_status status;      /* MH_OK, MH_EINVAL when the request's X held a NaN, MH_EDEVICE
-                            when its cooperative launch gave up at a grid barrier */
+                            when its cooperative launch gave up at a grid barrier,
+                            MH_ECANCELED when it was cancelled (mh_server_cancel or the
+                            time limit of mh_server_set_limits; tree then unset) */
   uint32_t n, F, K;
   mh_tree tree;          /* equal to subtree_solve on the same data, problem id 0 */
   uint64_t t_submit_ns;  /* host steady clock: mh_server_submit */
@@ -351,11 +364,27 @@ void mh_server_destroy(mh_server *srv);
  * mh_server_poll.  Requests are admitted in submission order when a slot is
  * free and the pool has room for the request's footprint (the head of the
  * queue waits; later requests do not pass it).  Returns MH_ENOMEM when the
- * footprint exceeds the whole pool, MH_EINVAL for invalid arguments.
+ * footprint exceeds the whole pool, MH_EBUSY when the queue holds the
+ * limit set by mh_server_set_limits, MH_EINVAL for invalid arguments.
  * Host-only: queues nothing on the device. */
 mh_status mh_server_submit(mh_server *srv, uint64_t req_id, const float *X,
                            const uint8_t *labels, uint32_t n, uint32_t F, uint32_t K,
                            uint32_t D, const mh_de_params *prm);
+/* Back-pressure and time limit of a server (both 0 at creation: none).
+ * max_queued > 0: mh_server_submit refuses a request with MH_EBUSY (and
+ * queues nothing) while max_queued requests wait for admission.
+ * timeout_ns > 0: a request not finished timeout_ns after its submission is
+ * cancelled at the next scheduling round (as by mh_server_cancel).  Host-only. */
+mh_status mh_server_set_limits(mh_server *srv, uint32_t max_queued, uint64_t timeout_ns);
+/* Cancels request req_id.  A queued request leaves the queue; a resident one
+ * stepped generation by generation is dropped at the next scheduling round
+ * (mh_server_pump), and its slot and pool room go to other requests; a
+ * request already running as one whole-request launch, or whose result is
+ * being copied out, finishes on the device.  Either way its result arrives
+ * through mh_server_poll with status MH_ECANCELED.  MH_EINVAL when no queued
+ * or running request has this id (unknown, or already finished).
+ * Host-only: queues nothing on the device. */
+mh_status mh_server_cancel(mh_server *srv, uint64_t req_id);
 /* Device bytes of the pool a request of this shape occupies while resident. */
 mh_status mh_server_footprint(uint32_t n, uint32_t F, uint32_t K, uint32_t D,
                               uint32_t P, uint64_t *bytes);

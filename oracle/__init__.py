@@ -339,6 +339,10 @@ def deoct(ds: Dataset, D: int, prm: DEParams, idx=None, warm=None, prob: int = 0
         out["trace"] = trace
     if with_pop:
         out["pop"] = pop
+        # each final individual's objective, from the oracle's own decode and
+        # fitness (eq. opt_all with the soft constraints of Section 3.2)
+        f, t = decode(pop, D, ds.F, ds.n_unique)
+        out["pop_cost"] = fitness(ds, f, t, D, idx=idx, n_min=prm.n_min, alpha=prm.alpha)[3]
     return out
 
 

@@ -682,6 +682,29 @@ mh_status subtree_solve(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, 
   return deoct_tuned(c, ds, idx, n_sub, D, prm, warm, W, problem_id, out);
 }
 
+mh_status subtree_solve_pop(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                            uint32_t n_sub, uint32_t D, const mh_de_params *prm,
+                            const double *warm, uint32_t W, uint64_t problem_id, mh_tree *out,
+                            double *pop_out, double *cost_out) {
+  mh_status s = subtree_solve(ctx, ds, idx, n_sub, D, prm, warm, W, problem_id, out);
+  if (s) return s;
+  Ctx *c = &ctx->c;
+  const uint32_t P = prm->P, m = 2u * ((1u << D) - 1u);
+  // the run left its final population (gene-major) and costs in the arena
+  if (pop_out) {
+    const double *pop = (const double *)arena_get(c, "ss_pop", (size_t)P * m * 8);
+    if (!pop) return MH_ENOMEM;
+    s = launch_pop_rows(c, pop, P, m, pop_out);
+    if (s) return s;
+  }
+  if (cost_out) {
+    const double *cost = (const double *)arena_get(c, "ss_cost", (size_t)P * 8);
+    if (!cost) return MH_ENOMEM;
+    MH_HIP(c, hipMemcpyAsync(cost_out, cost, (size_t)P * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return wait_stream(c);
+}
+
 mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, const mh_de_params *prm,
                       uint32_t generations, mh_tune_result *out) {
   CTX_OR_FAIL(ctx);

@@ -287,6 +287,26 @@ mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, ui
 }
 
 namespace {
+// Transpose of a gene-major population into rows: element e = r * m + q.
+__global__ void k_pop_rows(const double *__restrict__ gm, uint32_t P, uint32_t m,
+                           double *__restrict__ rows) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (uint64_t)P * m) return;
+  const uint32_t r = (uint32_t)(e / m), q = (uint32_t)(e % m);
+  rows[e] = gm[(size_t)q * P + r];
+}
+}  // namespace
+
+mh_status launch_pop_rows(Ctx *ctx, const double *gene_major, uint32_t P, uint32_t m,
+                          double *rows) {
+  const uint64_t total = (uint64_t)P * m;
+  if (total == 0) return MH_OK;
+  k_pop_rows<<<(uint32_t)((total + 255) / 256), 256, 0, ctx->stream>>>(gene_major, P, m, rows);
+  MH_LAUNCHED(ctx, "k_pop_rows");
+  return MH_OK;
+}
+
+namespace {
 // One solved tree, its labels, correct count, cost and a status word, copied
 // into one record (pinned host memory) so that the host waits once.
 __global__ void k_pack_result(uint32_t D, uint32_t SB, uint32_t SL, const uint8_t *__restrict__ f1,

@@ -318,6 +318,10 @@ struct ResultOut {
 mh_status launch_pack_result(Ctx *ctx, uint32_t D, const uint8_t *f1, const uint32_t *t1,
                              const uint8_t *lab1, const uint32_t *corr1, const double *cost1,
                              const uint32_t *flag_a, const uint32_t *flag_b, ResultOut *out);
+// Copies a gene-major population [m][P] (the layout of the DE loops) into
+// the row-major [P][m] layout of the C ABI.
+mh_status launch_pop_rows(Ctx *ctx, const double *gene_major, uint32_t P, uint32_t m,
+                          double *rows);
 mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, uint32_t F,
                         const uint32_t *n_unique, uint8_t *feat, uint32_t *tau,
                         uint32_t n_problems, const uint32_t *row_sel, bool gene_major);

@@ -39,13 +39,15 @@ def test_split1_subsets_and_pure(mh):
     assert mh.split1(ds, idx=dev(pure)) == oracle.split1(ods, idx=pure) == (0, 0, len(pure))
 
 
-def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9, n_min=1, alpha=0.0):
-    ods = oracle.dataset_from_X(X, y, K)
-    want = oracle.mh_train(ods, D, D_MH, oracle.de_params(P, G, M, CR, seed, n_min, alpha))
-    ds = mh.dataset(X, y, K)
+def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9, n_min=1, alpha=0.0, ctx=None,
+             want=None):
+    if want is None:
+        ods = oracle.dataset_from_X(X, y, K)
+        want = oracle.mh_train(ods, D, D_MH, oracle.de_params(P, G, M, CR, seed, n_min, alpha))
+    ds = mh.dataset(X, y, K, ctx=ctx)
     prm = mh.de_params(P, G, M, CR, seed, n_min, alpha)
-    seq = mh.mh_train(ds, D, D_MH, prm, batched=False)
-    bat = mh.mh_train(ds, D, D_MH, prm, batched=True)
+    seq = mh.mh_train(ds, D, D_MH, prm, batched=False, ctx=ctx)
+    bat = mh.mh_train(ds, D, D_MH, prm, batched=True, ctx=ctx)
     return want, seq, bat
 
 
@@ -81,11 +83,32 @@ def test_mh_train_penalised(mh, n_min, alpha):
     _same(bat, want)
 
 
-def test_mh_train_gaussian_mixture_depth8(mh):
-    """Shape of the batched moving-horizon workload (Gaussian mixture, F = 20,
-    K = 3, depth 8, horizon 3) at n = 20,000 with P = 16, G = 5 so that the
-    oracle runs in seconds."""
-    w = synth.batched_mh(1, n=20_000)
-    want, seq, bat = _mh_both(mh, w.X, w.y, w.K, 8, 3, 16, 5, 1001)
+_FORMS = {"default": {}, "staged": {"MHDEOCT_PERSIST": "1", "MHDEOCT_PERSIST_RESIDENT": "0"},
+          "per_generation": {"MHDEOCT_PERSIST": "0"}}
+_depth8_want = {}
+
+
+@pytest.mark.parametrize("form", list(_FORMS))
+@pytest.mark.parametrize("n,P,G", [(20_000, 16, 5), (200_000, 16, 3)])
+def test_mh_depth8_launch_forms(mh, monkeypatch, form, n, P, G):
+    """The batched moving-horizon workload's shape (Gaussian mixture, F = 20,
+    K = 3, depth 8, horizon 3) in each launch form of a level: the default
+    choice, the whole-level kernel with tiles staged from memory every
+    generation (the form the levels take at n = 10^6, where a block's tiles do
+    not fit its LDS), and the per-generation kernels (the form a level is
+    redone in after a grid barrier gave up).  Sequential and batched runs
+    equal the oracle's tree (Algorithm 2)."""
+    from paper_2311_06952_amd import capi
+    w = synth.batched_mh(1, n=n)
+    key = (n, P, G)
+    if key not in _depth8_want:
+        _depth8_want[key] = oracle.mh_train(oracle.dataset_from_X(w.X, w.y, w.K), 8, 3,
+                                            oracle.de_params(P, G, 0.5, 0.9, 1001))
+    for k, v in _FORMS[form].items():
+        monkeypatch.setenv(k, v)
+    ctx = capi.Context(0)
+    want, seq, bat = _mh_both(mh, w.X, w.y, w.K, 8, 3, P, G, 1001, ctx=ctx,
+                              want=_depth8_want[key])
     _same(seq, want)
     _same(bat, want)
+    ctx.close()

@@ -215,20 +215,28 @@ def _deoct_both(mh, w, seed, G=None, idx=None, P=None, prob=0, warm=None):
     P = w.P if P is None else P
     ods = oracle.dataset_from_X(w.X, w.y, w.K)
     prm_o = oracle.de_params(P, G, w.M, w.CR, seed)
-    want = oracle.deoct(ods, w.D, prm_o, idx=idx, warm=warm, prob=prob)
+    want = oracle.deoct(ods, w.D, prm_o, idx=idx, warm=warm, prob=prob, with_pop=True)
     ds = gpu_ds(mh, w.X, w.y, w.K)
     prm = mh.de_params(P, G, w.M, w.CR, seed)
     got = mh.subtree_solve(ds, w.D, prm, idx=None if idx is None else dev(idx), warm=warm,
-                           prob=prob)
+                           prob=prob, with_pop=True)
     return want, got, ods
 
 
 def _same_tree(want, got):
+    """The best tree, its labels, correct count and cost; and, when either
+    side carries it, the whole final population (float64 genes, bit for bit)
+    and every individual's cost."""
     np.testing.assert_array_equal(got["feat"], want["feat"])
     np.testing.assert_array_equal(got["tau"], want["tau"])
     np.testing.assert_array_equal(got["label"], want["label"])
     assert got["correct"] == want["correct"]
     assert got["cost"] == want["cost"]
+    for key in ("pop", "pop_cost"):
+        if key in got or key in want:
+            a, b = np.asarray(got[key]), np.asarray(want[key])
+            assert a.shape == b.shape
+            np.testing.assert_array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
@@ -253,16 +261,17 @@ def test_async_rank_status(mh):
     status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
     prm = mh.de_params(w.P, w.G, w.M, w.CR, 1007)
     ranks, nu = mh.rank_encode(Xd, status=status)
-    got = mh.subtree_solve(mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status), w.D, prm)
+    got = mh.subtree_solve(mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status), w.D, prm,
+                           with_pop=True)
     assert int(status.item()) == 0
     want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D,
-                        oracle.de_params(w.P, w.G, w.M, w.CR, 1007))
+                        oracle.de_params(w.P, w.G, w.M, w.CR, 1007), with_pop=True)
     _same_tree(want, got)
     Xn = Xd.clone()
     Xn[w.n // 3, 1] = float("nan")
     ranks, nu = mh.rank_encode(Xn, status=status)
     bad = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
-    for call in (lambda: mh.subtree_solve(bad, w.D, prm),
+    for call in (lambda: mh.subtree_solve(bad, w.D, prm, with_pop=True),
                  lambda: mh.mh_train(bad, 3, 2, prm),
                  lambda: mh.autotune(bad, w.D, prm, generations=2)):
         with pytest.raises(mh.MhError) as ei:
@@ -306,8 +315,8 @@ def test_plain_large_full_size(mh):
     for i in range(4):
         np.testing.assert_array_equal(np_(got[i]) if i >= 2 else u32(got[i]), want[i])
     prm = (w.P, 1, w.M, w.CR, 77)
-    got = mh.subtree_solve(ds, w.D, mh.de_params(*prm))
-    _same_tree(oracle.deoct(ods, w.D, oracle.de_params(*prm)), got)
+    got = mh.subtree_solve(ds, w.D, mh.de_params(*prm), with_pop=True)
+    _same_tree(oracle.deoct(ods, w.D, oracle.de_params(*prm), with_pop=True), got)
 
 
 @pytest.mark.parametrize("mode,n,P,G", [("normal", 2000, 100, 600), ("long", 400, 200, 4000)])
@@ -317,8 +326,8 @@ def test_paper_parameter_modes(mh, mode, n, P, G):
     individual and generation): equal to the oracle's run."""
     X, y = synth.random_small(300 + P, n, 6, 3)
     prm = (P, G, -1.0, 0.1, 4242)
-    got = mh.subtree_solve(gpu_ds(mh, X, y, 3), 3, mh.de_params(*prm))
-    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(*prm))
+    got = mh.subtree_solve(gpu_ds(mh, X, y, 3), 3, mh.de_params(*prm), with_pop=True)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(*prm), with_pop=True)
     _same_tree(want, got)
 
 
@@ -336,8 +345,8 @@ def test_whole_tree_deep_deoct(mh, D, n, P, G, M):
     setting DEOCT alone is compared in (Section 4), equal to the oracle's."""
     X, y = synth.random_small(900 + D, n, 9, 4, levels=60)
     prm = (P, G, M, 0.9, 31 + D)
-    got = mh.subtree_solve(gpu_ds(mh, X, y, 4), D, mh.de_params(*prm))
-    want = oracle.deoct(oracle.dataset_from_X(X, y, 4), D, oracle.de_params(*prm))
+    got = mh.subtree_solve(gpu_ds(mh, X, y, 4), D, mh.de_params(*prm), with_pop=True)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 4), D, oracle.de_params(*prm), with_pop=True)
     _same_tree(want, got)
 
 
@@ -353,7 +362,8 @@ def test_fused_and_separate_de_step_agree(mh, monkeypatch):
     out = []
     for ctx in (ctx_sep, ctx_fus):
         ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
-        out.append(mh.subtree_solve(ds, w.D, mh.de_params(100, 30, 0.5, 0.9, 3), ctx=ctx))
+        out.append(mh.subtree_solve(ds, w.D, mh.de_params(100, 30, 0.5, 0.9, 3), ctx=ctx,
+                                    with_pop=True))
     _same_tree(out[0], out[1])
     ctx_sep.close()
     ctx_fus.close()
@@ -373,10 +383,11 @@ def test_persistent_and_per_generation_deoct_agree(mh, monkeypatch, D, P, K, M):
     out = []
     for ctx in (ctx_gen, ctx_per):
         ds = mh.dataset(X, y, K, ctx=ctx)
-        out.append(mh.subtree_solve(ds, D, mh.de_params(P, 12, M, 0.9, 5 + D), prob=3, ctx=ctx))
+        out.append(mh.subtree_solve(ds, D, mh.de_params(P, 12, M, 0.9, 5 + D), prob=3, ctx=ctx,
+                                    with_pop=True))
     _same_tree(out[0], out[1])
     want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 12, M, 0.9, 5 + D),
-                        prob=3)
+                        prob=3, with_pop=True)
     _same_tree(want, out[1])
     ctx_gen.close()
     ctx_per.close()
@@ -397,10 +408,10 @@ def test_penalised_objective_deoct(mh, monkeypatch, D, P, K, n_min, alpha):
         ctx = capi.Context(0)
         ds = mh.dataset(X, y, K, ctx=ctx)
         out.append(mh.subtree_solve(ds, D, mh.de_params(P, 15, 0.5, 0.9, 9 + D, n_min, alpha),
-                                    ctx=ctx))
+                                    ctx=ctx, with_pop=True))
         ctx.close()
     want = oracle.deoct(oracle.dataset_from_X(X, y, K), D,
-                        oracle.de_params(P, 15, 0.5, 0.9, 9 + D, n_min, alpha))
+                        oracle.de_params(P, 15, 0.5, 0.9, 9 + D, n_min, alpha), with_pop=True)
     _same_tree(want, out[0])
     _same_tree(want, out[1])
     if n_min == 1:
@@ -426,13 +437,13 @@ def test_persistent_wave_groups_agree(mh, monkeypatch, halves, resident, D, P, K
     prm = (P, 5, 0.5, 0.9, 17 + D)
     if key not in _group_want:
         _group_want[key] = oracle.deoct(oracle.dataset_from_X(X, y, K), D,
-                                        oracle.de_params(*prm), prob=4)
+                                        oracle.de_params(*prm), prob=4, with_pop=True)
     monkeypatch.setenv("MHDEOCT_PERSIST", "1")
     monkeypatch.setenv("MHDEOCT_PERSIST_HALVES", halves)
     monkeypatch.setenv("MHDEOCT_PERSIST_RESIDENT", resident)
     ctx = capi.Context(0)
     ds = mh.dataset(X, y, K, ctx=ctx)
-    got = mh.subtree_solve(ds, D, mh.de_params(*prm), prob=4, ctx=ctx)
+    got = mh.subtree_solve(ds, D, mh.de_params(*prm), prob=4, ctx=ctx, with_pop=True)
     _same_tree(_group_want[key], got)
     ctx.close()
 
@@ -444,9 +455,9 @@ def test_persistent_deoct_edge_shapes(mh, D, P, K, n):
     populations: the whole-run kernel agrees with the oracle."""
     X, y = synth.random_small(70 + D + n, n, 5, K)
     ds = mh.dataset(X, y, K)
-    got = mh.subtree_solve(ds, D, mh.de_params(P, 7, 0.5, 0.9, 11), prob=1)
+    got = mh.subtree_solve(ds, D, mh.de_params(P, 7, 0.5, 0.9, 11), prob=1, with_pop=True)
     want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 7, 0.5, 0.9, 11),
-                        prob=1)
+                        prob=1, with_pop=True)
     _same_tree(want, got)
 
 
@@ -459,12 +470,13 @@ def test_persistent_large_lds_shapes(mh, monkeypatch, D, P, F, K):
     from paper_2311_06952_amd import capi
     X, y = synth.random_small(90 + D + F, 4000, F, K)
     want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(P, 6, 0.5, 0.9, 13),
-                        prob=2)
+                        prob=2, with_pop=True)
     for persist in ("1", "0"):
         monkeypatch.setenv("MHDEOCT_PERSIST", persist)
         ctx = capi.Context(0)
         ds = mh.dataset(X, y, K, ctx=ctx)
-        got = mh.subtree_solve(ds, D, mh.de_params(P, 6, 0.5, 0.9, 13), prob=2, ctx=ctx)
+        got = mh.subtree_solve(ds, D, mh.de_params(P, 6, 0.5, 0.9, 13), prob=2, ctx=ctx,
+                               with_pop=True)
         _same_tree(want, got)
         ctx.close()
 
@@ -482,8 +494,9 @@ def test_barrier_give_up_recovery(mh, monkeypatch):
     want_r, want_nu = oracle.rank_encode(X)
     np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
     np.testing.assert_array_equal(u32(ds.ranks)[:, :20000], want_r)
-    got = mh.subtree_solve(ds, 3, mh.de_params(64, 6, 0.5, 0.9, 9), ctx=ctx)
-    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(64, 6, 0.5, 0.9, 9))
+    got = mh.subtree_solve(ds, 3, mh.de_params(64, 6, 0.5, 0.9, 9), ctx=ctx, with_pop=True)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, 3), 3, oracle.de_params(64, 6, 0.5, 0.9, 9),
+                        with_pop=True)
     _same_tree(want, got)
     ctx.close()
 
@@ -499,9 +512,9 @@ def test_autotune_keeps_results(mh):
     tuned = mh.autotune(ds, w.D, prm, generations=5, ctx=ctx)
     assert tuned["persist"] in (0, 1) and tuned["halves"] in (1, 2, 4)
     assert len(tuned["ms"]) == 12 and all(t > 0 for t in tuned["ms"])
-    got = mh.subtree_solve(ds, w.D, prm, ctx=ctx)
-    want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D, oracle.de_params(64, 15, 0.5,
-                                                                                     0.9, 21))
+    got = mh.subtree_solve(ds, w.D, prm, ctx=ctx, with_pop=True)
+    want = oracle.deoct(oracle.dataset_from_X(w.X, w.y, w.K), w.D,
+                        oracle.de_params(64, 15, 0.5, 0.9, 21), with_pop=True)
     _same_tree(want, got)
     ctx.close()
 

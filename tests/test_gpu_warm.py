@@ -48,11 +48,14 @@ def test_warm_start_from_greedy_tree(mh, seed, D):
     prm = mh.de_params(16, 3, 0.5, 0.9, seed)
     greedy = mh.mh_train(ds, D, 1, prm)
     warm = mh.tree_encode(greedy["feat"], greedy["tau"], D, 7, ds.n_unique).cpu().numpy()
-    got = mh.subtree_solve(ds, D, mh.de_params(64, 25, 0.5, 0.9, 50 + seed), warm=warm)
+    got = mh.subtree_solve(ds, D, mh.de_params(64, 25, 0.5, 0.9, 50 + seed), warm=warm,
+                           with_pop=True)
     want = oracle.deoct(oracle.dataset_from_X(X, y, 3), D,
-                        oracle.de_params(64, 25, 0.5, 0.9, 50 + seed), warm=warm)
+                        oracle.de_params(64, 25, 0.5, 0.9, 50 + seed), warm=warm, with_pop=True)
     for k in ("feat", "tau", "label"):
         np.testing.assert_array_equal(got[k], want[k])
+    for k in ("pop", "pop_cost"):
+        np.testing.assert_array_equal(got[k].view(np.uint64), want[k].view(np.uint64))
     assert got["correct"] == want["correct"] and got["cost"] == want["cost"]
     assert got["correct"] >= greedy["correct"]
 
@@ -69,12 +72,15 @@ def test_warm_start_from_earlier_run(mh, monkeypatch):
         ds = mh.dataset(X, y, 4, ctx=ctx)
         t1 = mh.subtree_solve(ds, 3, mh.de_params(128, 15, 0.5, 0.9, 1), ctx=ctx)
         warm = mh.tree_encode(t1["feat"], t1["tau"], 3, 8, ds.n_unique, ctx=ctx).cpu().numpy()
-        t2 = mh.subtree_solve(ds, 3, mh.de_params(128, 15, 0.5, 0.9, 2), warm=warm, ctx=ctx)
+        t2 = mh.subtree_solve(ds, 3, mh.de_params(128, 15, 0.5, 0.9, 2), warm=warm, ctx=ctx,
+                              with_pop=True)
         ctx.close()
         want = oracle.deoct(oracle.dataset_from_X(X, y, 4), 3,
-                            oracle.de_params(128, 15, 0.5, 0.9, 2), warm=warm)
+                            oracle.de_params(128, 15, 0.5, 0.9, 2), warm=warm, with_pop=True)
         for k in ("feat", "tau", "label"):
             np.testing.assert_array_equal(t2[k], want[k])
+        for k in ("pop", "pop_cost"):
+            np.testing.assert_array_equal(t2[k].view(np.uint64), want[k].view(np.uint64))
         assert t2["correct"] == want["correct"] >= t1["correct"]
         if first is None:
             first = t2
