@@ -7,8 +7,10 @@ the declared symbols.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -26,7 +28,8 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_tileset_build", "fitness_eval_tiles", "de_init", "de_step", "subtree_solve",
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
            "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune",
-           "mh_tree_thresholds", "mh_predict", "tree_encode")
+           "mh_tree_thresholds", "mh_predict", "tree_encode", "subtree_solve_pop",
+           "mh_server_set_limits", "mh_server_cancel")
 
 
 class MhError(RuntimeError):
@@ -108,11 +111,15 @@ def load_library(path: str = LIB_PATH):
         "mh_server_footprint": ([U32, U32, U32, U32, U32, C.POINTER(U64)], I32),
         "mh_server_pump": ([V, U32, C.POINTER(U32), C.POINTER(U32)], I32),
         "mh_server_poll": ([V, C.POINTER(ResultC), U32, C.POINTER(U32)], I32),
+        "mh_server_set_limits": ([V, U32, U64], I32),
+        "mh_server_cancel": ([V, U64], I32),
         "mh_autotune": ([V, C.POINTER(DatasetC), U32, C.POINTER(DEParamsC), U32, C.POINTER(TuneC)],
                         I32),
         "mh_tree_thresholds": ([V, C.POINTER(DatasetC), V, V, V, U32, V], I32),
         "mh_predict": ([V, V, U32, U32, V, V, V, U32, V, V, V], I32),
         "tree_encode": ([V, V, V, U32, U32, U32, V, V], I32),
+        "subtree_solve_pop": ([V, C.POINTER(DatasetC), V, U32, U32, C.POINTER(DEParamsC), V, U32,
+                               U64, C.POINTER(TreeC), V, V], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)  # AttributeError if a symbol is missing
@@ -120,6 +127,30 @@ def load_library(path: str = LIB_PATH):
         fn.restype = res
     _lib = lib
     return lib
+
+
+# Live contexts and servers.  They are closed by an exit hook, while the HIP
+# runtime (and any profiler attached to it) is still fully up: left to
+# garbage collection at interpreter shutdown, their destroy calls (stream
+# synchronisation, device and pinned-memory frees) could run after the
+# runtime has begun to tear down.
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all() -> None:
+    for srv in list(_live_servers):
+        try:
+            srv.close()
+        except Exception:
+            pass
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+    _default.clear()
 
 
 # --------------------------------------------------------------------------
@@ -152,6 +183,7 @@ class Context:
         if rc != MH_OK:
             raise MhError(rc, self.lib.mh_last_error(None).decode())
         self.h = h
+        _live_contexts.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -370,8 +402,11 @@ def _tree_dict(t: TreeC) -> dict:
 
 
 def subtree_solve(ds: Dataset, D: int, prm: DEParamsC, idx=None, warm=None, prob: int = 0,
-                  ctx: Context | None = None) -> dict:
-    """DEOCT on the device; warm is a host float64 array [W][2*SB]."""
+                  ctx: Context | None = None, with_pop: bool = False) -> dict:
+    """DEOCT on the device; warm is a host float64 array [W][2*SB].  With
+    with_pop the result also holds the final population (`pop`, float64
+    [P][2*SB]) and its costs (`pop_cost`, [P]) as numpy arrays
+    (subtree_solve_pop)."""
     ctx = ctx or default_context()
     n_sub = ds.n if idx is None else int(idx.numel())
     W = 0
@@ -382,9 +417,20 @@ def subtree_solve(ds: Dataset, D: int, prm: DEParamsC, idx=None, warm=None, prob
         wp = warm.ctypes.data_as(C.c_void_p)
     out = TreeC()
     dsc = ds.cstruct()
-    ctx.check(ctx.lib.subtree_solve(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp, W,
-                                    prob, C.byref(out)))
-    return _tree_dict(out)
+    if not with_pop:
+        ctx.check(ctx.lib.subtree_solve(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp,
+                                        W, prob, C.byref(out)))
+        return _tree_dict(out)
+    torch = _torch()
+    dev = torch.device("cuda", ctx.device)
+    pop = torch.empty((prm.P, 2 * ((1 << D) - 1)), dtype=torch.float64, device=dev)
+    pcost = torch.empty(prm.P, dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.subtree_solve_pop(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D, C.byref(prm), wp,
+                                        W, prob, C.byref(out), _ptr(pop), _ptr(pcost)))
+    res = _tree_dict(out)
+    res["pop"] = pop.cpu().numpy()
+    res["pop_cost"] = pcost.cpu().numpy()
+    return res
 
 
 def _on_device(a, dtype, dev):
@@ -491,6 +537,7 @@ class Server:
                                                      C.byref(h)))
         self.h = h
         self._inputs = {}  # req_id -> (X, y): kept alive until the result is polled
+        _live_servers.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -512,6 +559,16 @@ class Server:
         self.ctx.check(self.ctx.lib.mh_server_submit(self.h, int(req_id), _ptr(X), _ptr(y), n, F,
                                                      int(K), int(D), C.byref(prm)))
         self._inputs[int(req_id)] = (X, y)
+
+    def set_limits(self, max_queued: int = 0, timeout_ns: int = 0):
+        """mh_server_set_limits: queue back-pressure (MH_EBUSY) and a time
+        limit after which requests are cancelled (0: none)."""
+        self.ctx.check(self.ctx.lib.mh_server_set_limits(self.h, int(max_queued), int(timeout_ns)))
+
+    def cancel(self, req_id: int):
+        """mh_server_cancel: the request's result comes back with status
+        MH_ECANCELED."""
+        self.ctx.check(self.ctx.lib.mh_server_cancel(self.h, int(req_id)))
 
     def pump(self, ticks: int = 1):
         """Runs up to `ticks` scheduling rounds; returns (resident, queued)."""

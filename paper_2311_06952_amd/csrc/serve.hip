@@ -138,6 +138,7 @@ struct Req {
   uint32_t g = 0;  // next generation index to queue (0..G; G + 1 = done)
   int slot = -1;
   bool solo = false;  // solved whole by one cooperative launch at admission
+  bool cancelled = false;  // by mh_server_cancel or the time limit
 
   template <typename T>
   T *at(size_t o) const {
@@ -188,6 +189,10 @@ struct mh_server {
   // requests with at least this many tiles run whole as one cooperative
   // launch (0: never); MHDEOCT_SERVE_SOLO_TILES, default two per CU
   uint32_t solo_tiles = 0;
+  // mh_server_set_limits: queued requests at most (0: no limit) and the
+  // time from submission after which a request is cancelled (0: none)
+  uint32_t max_queued = 0;
+  uint64_t timeout_ns = 0;
 };
 
 namespace mh {
@@ -296,6 +301,7 @@ mh_status collect(mh_server *s, bool wait) {
     std::memset(&res, 0, sizeof(res));
     res.req_id = q.id;
     res.status = (o.flag & 2u) ? MH_EINVAL : o.flag ? MH_EDEVICE : MH_OK;
+    if (q.cancelled) res.status = MH_ECANCELED;
     res.n = q.n;
     res.F = q.F;
     res.K = q.K;
@@ -403,12 +409,65 @@ mh_status generation(mh_server *s) {
   return MH_OK;
 }
 
+// The result record of a request that ends cancelled: no tree.
+void push_cancelled(mh_server *s, const Req &q) {
+  mh_result res;
+  std::memset(&res, 0, sizeof(res));
+  res.req_id = q.id;
+  res.status = MH_ECANCELED;
+  res.n = q.n;
+  res.F = q.F;
+  res.K = q.K;
+  res.tree.D = q.D;
+  res.t_submit_ns = q.t_submit;
+  res.t_admit_ns = q.t_admit;
+  res.t_done_ns = now_ns();
+  s->done.push_back(res);
+}
+
+// Cancelled requests leave: queued ones at once; resident ones that are
+// still stepped generation by generation give their slot and pool block
+// back (work already queued on the stream that uses the block runs before
+// any later use of it); a whole-request run, or a result already being
+// packed, finishes on the device and is reported cancelled when it lands.
+void drop_cancelled(mh_server *s) {
+  if (s->timeout_ns) {
+    const uint64_t t = now_ns();
+    for (Req &q : s->queue)
+      if (t - q.t_submit > s->timeout_ns) q.cancelled = true;
+    for (Req &q : s->active)
+      if (t - q.t_submit > s->timeout_ns) q.cancelled = true;
+  }
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    if (it->cancelled) {
+      push_cancelled(s, *it);
+      it = s->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  size_t kept = 0;
+  for (size_t i = 0; i < s->active.size(); ++i) {
+    Req &q = s->active[i];
+    if (q.cancelled && !q.solo) {
+      s->pool.release(q.off, q.cv.total);
+      s->free_slots.push_back(q.slot);
+      push_cancelled(s, q);
+      continue;
+    }
+    if (kept != i) s->active[kept] = q;
+    ++kept;
+  }
+  s->active.resize(kept);
+}
+
 // Whether a queued request will run whole at admission.
 bool c_solo(const mh_server *s, const Req &q) {
   return s->c->persist && s->solo_tiles && q.cv.max_tiles >= s->solo_tiles;
 }
 
 mh_status round_once(mh_server *s) {
+  drop_cancelled(s);
   mh_status r = collect(s, s->active.empty() && s->queue.empty());
   if (r) return r;
   // admission, in submission order; at most one whole-request run per round,
@@ -553,9 +612,38 @@ mh_status mh_server_submit(mh_server *s, uint64_t req_id, const float *X, const 
   q.cv = carve(n, F, K, D, prm->P);
   if (q.cv.total > s->pool_bytes)
     return fail(c, MH_ENOMEM, "request footprint exceeds the server's HBM budget");
+  if (s->max_queued && s->queue.size() >= s->max_queued)
+    return fail(c, MH_EBUSY, "the server's queue is full");
   q.t_submit = now_ns();
   s->queue.push_back(q);
   return MH_OK;
+}
+
+mh_status mh_server_set_limits(mh_server *s, uint32_t max_queued, uint64_t timeout_ns) {
+  SRV_OR_FAIL(s);
+  s->max_queued = max_queued;
+  s->timeout_ns = timeout_ns;
+  return MH_OK;
+}
+
+mh_status mh_server_cancel(mh_server *s, uint64_t req_id) {
+  SRV_OR_FAIL(s);
+  for (Req &q : s->queue)
+    if (q.id == req_id && !q.cancelled) {
+      q.cancelled = true;
+      return MH_OK;
+    }
+  for (Req &q : s->active)
+    if (q.id == req_id && !q.cancelled) {
+      q.cancelled = true;
+      return MH_OK;
+    }
+  for (Req &q : s->retiring)
+    if (q.id == req_id && !q.cancelled) {
+      q.cancelled = true;
+      return MH_OK;
+    }
+  return fail(s->c, MH_EINVAL, "no queued or running request has this id");
 }
 
 mh_status mh_server_pump(mh_server *s, uint32_t ticks, uint32_t *n_active, uint32_t *n_queued) {
@@ -568,6 +656,7 @@ mh_status mh_server_pump(mh_server *s, uint32_t ticks, uint32_t *n_active, uint3
       return r;
     }
   }
+  drop_cancelled(s);
   if (mh_status r = collect(s, false)) {
     s->sticky = r;
     return r;

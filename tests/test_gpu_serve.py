@@ -31,6 +31,7 @@ REQUESTS = [
     (8, 7000, 9, 6, 4, 128, 12, -1.0),
     (9, 0, 6, 3, 3, 32, 4, 0.5),
     (10, 2500, 80, 4, 3, 512, 5, 0.5),
+    (11, 250_000, 10, 3, 3, 64, 4, 0.5),   # a large request (runs whole by default)
 ]
 
 
@@ -151,4 +152,74 @@ def test_server_rejects_oversized_and_reports_nan(mh):
     want = oracle.deoct(oracle.dataset_from_X(X0, y0, 2), 2, oracle.de_params(32, 10, 0.5, 0.9,
                                                                               7000))
     _same(res[0]["tree"], want)
+    ctx.close()
+
+
+def test_server_cancel_and_time_limit(mh, monkeypatch):
+    """Failure handling of the served form: a queued request cancelled before
+    admission, a resident request cancelled between its generations, a
+    whole-request run cancelled after its launch, and requests past the
+    server's time limit all come back with MH_ECANCELED; the slots and pool
+    room they held serve later requests, whose results still equal the
+    oracle's."""
+    import torch
+    from paper_2311_06952_amd import capi
+
+    def sub(srv, rid, n, F, K, D, P, G):
+        X, y = _data(rid, n, F, K)
+        srv.submit(rid, torch.as_tensor(X).cuda(), torch.as_tensor(y).cuda(), K, D,
+                   _prm(mh, P, G, 0.5, rid))
+
+    def oracle_tree(rid, n, F, K, D, P, G):
+        X, y = _data(rid, n, F, K)
+        return oracle.deoct(oracle.dataset_from_X(X, y, K), D,
+                            oracle.de_params(P, G, 0.5, 0.9, 7000 + rid))
+
+    # stepped generation by generation: one slot, so the others queue
+    monkeypatch.setenv("MHDEOCT_SERVE_SOLO_TILES", "0")
+    ctx = capi.Context(0)
+    srv = mh.Server(1 << 28, 1, ctx=ctx)
+    sub(srv, 20, 3000, 5, 3, 3, 32, 60)
+    sub(srv, 21, 2000, 4, 2, 2, 32, 10)
+    srv.cancel(21)                      # still queued
+    srv.pump(3)                         # 20 admitted and stepped
+    srv.cancel(20)                      # resident, between generations
+    with pytest.raises(mh.MhError) as ei:
+        srv.cancel(20)                  # already cancelled
+    assert ei.value.code == capi.MH_EINVAL
+    sub(srv, 22, 2500, 6, 3, 3, 32, 8)  # gets the freed slot
+    res = {r["req_id"]: r for r in srv.drain()}
+    assert res[20]["status"] == capi.MH_ECANCELED
+    assert res[21]["status"] == capi.MH_ECANCELED and res[21]["t_admit_ns"] == 0
+    assert res[22]["status"] == 0
+    _same(res[22]["tree"], oracle_tree(22, 2500, 6, 3, 3, 32, 8))
+    with pytest.raises(mh.MhError):
+        srv.cancel(22)                  # finished: no longer cancellable
+    # a time limit of one nanosecond cancels everything at the next round
+    srv.set_limits(0, 1)
+    sub(srv, 23, 1500, 4, 2, 2, 16, 5)
+    res = {r["req_id"]: r for r in srv.drain()}
+    assert res[23]["status"] == capi.MH_ECANCELED
+    srv.set_limits(0, 0)
+    sub(srv, 24, 1500, 4, 2, 2, 16, 5)
+    res = {r["req_id"]: r for r in srv.drain()}
+    assert res[24]["status"] == 0
+    _same(res[24]["tree"], oracle_tree(24, 1500, 4, 2, 2, 16, 5))
+    srv.close()
+    ctx.close()
+
+    # a whole-request run (large request, default threshold) cancelled after
+    # its launch finishes on the device and is reported cancelled
+    monkeypatch.delenv("MHDEOCT_SERVE_SOLO_TILES")
+    ctx = capi.Context(0)
+    srv = mh.Server(1 << 30, 2, ctx=ctx)
+    sub(srv, 30, 100_000, 8, 3, 3, 64, 20)
+    sub(srv, 31, 2000, 4, 2, 2, 16, 6)
+    srv.pump(1)
+    srv.cancel(30)
+    res = {r["req_id"]: r for r in srv.drain()}
+    assert res[30]["status"] == capi.MH_ECANCELED and res[30]["t_admit_ns"] > 0
+    assert res[31]["status"] == 0
+    _same(res[31]["tree"], oracle_tree(31, 2000, 4, 2, 2, 16, 6))
+    srv.close()
     ctx.close()
