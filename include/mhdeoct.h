@@ -186,6 +186,28 @@ mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                        uint32_t *counts, uint32_t *correct, uint8_t *label,
                        double *cost);
 
+/* fitness_eval for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs and errors as fitness_eval, but the tile layout
+ * and counters (tile path: depth <= 5 and F <= 80) or the per-(tree, leaf,
+ * class) counts (walk path) live in one static device array of 64 MiB that
+ * each GPU holds from the library's load until the process ends; the call
+ * calls no allocating routine and only queues kernels on the context's
+ * stream (no memset nodes, no timing events).  An evaluation that needs more
+ * than 64 MiB of that scratch (the tile path needs about 12.2 * F bytes per
+ * sample plus 4 * (2^D - 1) * K * P rounded up; the walk path 4 * P * 2^D * K
+ * bytes) fails with MH_EINVAL and queues nothing.  Every call on one GPU
+ * shares that GPU's array: calls in flight at the same time on different
+ * streams of one GPU race (calls on one stream are ordered).  Each call
+ * clears what it reads before use, so no call depends on an earlier one's
+ * contents.  MH_EDEVICE if the array's device address could not be looked
+ * up. */
+mh_status fitness_eval_static(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                              uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
+                              uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                              uint32_t *counts, uint32_t *correct, uint8_t *label,
+                              double *cost);
+
 /* The tiled sample layout the fitness kernel reads: samples grouped by
  * class into tiles of at most 63, each tile holding, per feature, its ranks
  * in ascending order and the prefix bitmasks of the sample positions in

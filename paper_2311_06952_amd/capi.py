@@ -29,7 +29,7 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
            "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune",
            "mh_tree_thresholds", "mh_predict", "tree_encode", "subtree_solve_pop",
-           "mh_server_set_limits", "mh_server_cancel")
+           "mh_server_set_limits", "mh_server_cancel", "fitness_eval_static")
 
 
 class MhError(RuntimeError):
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH):
         "mh_rank_encode": ([V, V, U32, U32, U32, V, V, V], I32),
         "tree_decode": ([V, V, U32, U32, U32, V, V, V], I32),
         "fitness_eval": ([V, C.POINTER(DatasetC), V, U32, V, V, U32, U32, U32, D, V, V, V, V], I32),
+        "fitness_eval_static": ([V, C.POINTER(DatasetC), V, U32, V, V, U32, U32, U32, D, V, V, V,
+                                 V], I32),
         "mh_tileset_bytes": ([U32, U32, U32, C.POINTER(C.c_size_t)], I32),
         "mh_tileset_build": ([V, C.POINTER(DatasetC), V, U32, V, C.c_size_t], I32),
         "fitness_eval_tiles": ([V, V, V, V, V, U32, U32, U32, D, V, V, V, V], I32),
@@ -309,8 +311,9 @@ def tree_encode(feat, tau, D: int, F: int, n_unique, ctx: Context | None = None)
 
 
 def fitness_eval(ds: Dataset, feat, tau, D: int, idx=None, n_min: int = 1, alpha: float = 0.0,
-                 ctx: Context | None = None, want_counts: bool = True):
-    """fitness_eval: returns (counts [P][SL][K] int32, correct [P] int32,
+                 ctx: Context | None = None, want_counts: bool = True, static: bool = False):
+    """fitness_eval (fitness_eval_static with static=True: no allocation in
+    the library): returns (counts [P][SL][K] int32, correct [P] int32,
     label [P][SL] uint8, cost [P] float64), all on the device."""
     torch = _torch()
     ctx = ctx or default_context()
@@ -326,9 +329,9 @@ def fitness_eval(ds: Dataset, feat, tau, D: int, idx=None, n_min: int = 1, alpha
     cost = torch.zeros(P, dtype=torch.float64, device=dev)
     n_sub = ds.n if idx is None else int(idx.numel())
     dsc = ds.cstruct()
-    ctx.check(ctx.lib.fitness_eval(ctx.h, C.byref(dsc), _ptr(idx), n_sub, _ptr(feat), _ptr(tau),
-                                   P, D, n_min, alpha, _ptr(counts), _ptr(correct), _ptr(label),
-                                   _ptr(cost)))
+    fn = ctx.lib.fitness_eval_static if static else ctx.lib.fitness_eval
+    ctx.check(fn(ctx.h, C.byref(dsc), _ptr(idx), n_sub, _ptr(feat), _ptr(tau), P, D, n_min, alpha,
+                 _ptr(counts), _ptr(correct), _ptr(label), _ptr(cost)))
     return counts, correct, label, cost
 
 

@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "de_body.h"
@@ -15,6 +17,35 @@
 namespace mh {
 
 static thread_local std::string g_create_err;
+
+// Device scratch of fitness_eval_static, the entry point that allocates
+// nothing: the tile layout and counters of one call.  Each GPU the library
+// runs on holds its own copy from the library's load until the process ends.
+// In host code the array's name is not a device address: its per-device
+// address comes from hipGetSymbolAddress, looked up once per device when the
+// first context on that device is created, and only that address is used.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, uint8_t *> g_scratch_addr;
+
+// The current device's copy of `scratch` (the device must be current).
+static hipError_t static_scratch_of(int device, uint8_t **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      *out = nullptr;
+      return e;
+    }
+    it = g_scratch_addr.emplace(device, static_cast<uint8_t *>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
 
 mh_status fail(Ctx *ctx, mh_status code, const std::string &msg) {
   if (ctx) ctx->err = msg;
@@ -212,6 +243,7 @@ struct EvalSet {
   const void *tiles;  // nullptr: walk path
   uint32_t max_tiles;
   uint32_t *cnt;
+  uint32_t *leafcnt;  // walk path: caller scratch for the leaf counts (null: the arena's)
 };
 
 static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, const uint32_t *tau,
@@ -220,22 +252,38 @@ static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, co
   if (es.tiles)
     return launch_fitness_tiles(ctx, es.tiles, es.ds->F, es.ds->K, es.n_sub, 1, es.max_tiles, feat,
                                 tau, P, D, n_min, alpha, es.cnt, out);
-  return launch_fitness_walk(ctx, es.ds, es.idx, es.n_sub, feat, tau, P, D, n_min, alpha, out);
+  return launch_fitness_walk(ctx, es.ds, es.idx, es.n_sub, feat, tau, P, D, n_min, alpha, out,
+                             es.leafcnt);
 }
 
+// Device bytes of the tile layout and counters (tile path) or the leaf
+// counts (walk path) that one fitness evaluation of P depth-D trees over
+// n_sub samples of ds uses, each part 256-byte aligned.
+static size_t eval_scratch_bytes(const mh_dataset *ds, uint32_t n_sub, uint32_t D, uint32_t P) {
+  if (tile_path_ok(D, ds->F))
+    return align256(tile_layout(n_sub, ds->F, ds->K, 1).total_bytes) +
+           align256(cnt_bytes(1, D, ds->K, P));
+  return align256((size_t)P * ((size_t)1 << D) * ds->K * 4);
+}
+
+// static_base: caller-provided scratch of eval_scratch_bytes (null: the
+// context arena's buffers tile_name and cnt_name).
 static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                               uint32_t D, uint32_t P, const char *tile_name, const char *cnt_name,
-                              EvalSet &es) {
+                              EvalSet &es, uint8_t *static_base = nullptr) {
   es.ds = ds;
   es.idx = idx;
   es.n_sub = n_sub;
   es.tiles = nullptr;
   es.cnt = nullptr;
   es.max_tiles = 0;
+  es.leafcnt = tile_path_ok(D, ds->F) ? nullptr : reinterpret_cast<uint32_t *>(static_base);
   if (!tile_path_ok(D, ds->F)) return MH_OK;
   TileHdr h = tile_layout(n_sub, ds->F, ds->K, 1);
-  void *tiles = arena_get(ctx, tile_name, h.total_bytes);
-  uint32_t *cnt = (uint32_t *)arena_get(ctx, cnt_name, cnt_bytes(1, D, ds->K, P));
+  void *tiles = static_base ? static_base : arena_get(ctx, tile_name, h.total_bytes);
+  uint32_t *cnt = static_base
+                      ? reinterpret_cast<uint32_t *>(static_base + align256(h.total_bytes))
+                      : (uint32_t *)arena_get(ctx, cnt_name, cnt_bytes(1, D, ds->K, P));
   if (!tiles || !cnt) return MH_ENOMEM;
   mh_status s = launch_tile_build(ctx, ds, idx, nullptr, n_sub, 1, tiles, h.total_bytes);
   if (s) return s;
@@ -442,6 +490,11 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   mh_ctx *c = new mh_ctx();
   c->c.device = device;
   c->c.stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // (a failed lookup leaves only fitness_eval_static unusable: it reports it)
+  if (static_scratch_of(device, &c->c.static_scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    c->c.static_scratch = nullptr;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)
@@ -564,19 +617,26 @@ static mh_status check_fit_args(Ctx *c, uint32_t P, uint32_t D, const uint8_t *f
   return MH_OK;
 }
 
-mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
-                       const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
-                       uint32_t n_min, double alpha, uint32_t *counts, uint32_t *correct,
-                       uint8_t *label, double *cost) {
-  CTX_OR_FAIL(ctx);
-  Ctx *c = &ctx->c;
+static mh_status fitness_eval_core(Ctx *c, const mh_dataset *ds, const uint32_t *idx,
+                                   uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
+                                   uint32_t P, uint32_t D, uint32_t n_min, double alpha,
+                                   uint32_t *counts, uint32_t *correct, uint8_t *label,
+                                   double *cost, uint8_t *static_base) {
   mh_status s = check_dataset(c, ds);
   if (s) return s;
   s = check_fit_args(c, P, D, feat, tau, n_min, alpha, cost);
   if (s) return s;
   if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  if (static_base) {
+    const size_t need = eval_scratch_bytes(ds, n_sub, D, P);
+    if (need > STATIC_SCRATCH_BYTES)
+      return fail(c, MH_EINVAL,
+                  "fitness_eval_static: this evaluation needs " + std::to_string(need) +
+                      " bytes of scratch, more than its static limit of " +
+                      std::to_string(STATIC_SCRATCH_BYTES) + " (use fitness_eval)");
+  }
   EvalSet es;
-  s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es);
+  s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es, static_base);
   if (s) return s;
   s = launch_zero(c, {{es.cnt, es.cnt ? cnt_bytes(1, D, ds->K, P) : 0}});
   if (s) return s;
@@ -586,6 +646,32 @@ mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, u
   out.label = label;
   out.cost = cost;
   return eval_trees(c, es, feat, tau, P, D, n_min, alpha, out);
+}
+
+mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                       const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                       uint32_t n_min, double alpha, uint32_t *counts, uint32_t *correct,
+                       uint8_t *label, double *cost) {
+  CTX_OR_FAIL(ctx);
+  return fitness_eval_core(&ctx->c, ds, idx, n_sub, feat, tau, P, D, n_min, alpha, counts, correct,
+                           label, cost, nullptr);
+}
+
+mh_status fitness_eval_static(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                              uint32_t n_sub, const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                              uint32_t D, uint32_t n_min, double alpha, uint32_t *counts,
+                              uint32_t *correct, uint8_t *label, double *cost) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  if (!c->static_scratch)
+    return fail(c, MH_EDEVICE, "fitness_eval_static: no address for the static scratch");
+  // no timing events either: the call only queues kernels
+  const bool prof = c->profile;
+  c->profile = false;
+  const mh_status s = fitness_eval_core(c, ds, idx, n_sub, feat, tau, P, D, n_min, alpha, counts,
+                                        correct, label, cost, c->static_scratch);
+  c->profile = prof;
+  return s;
 }
 
 mh_status fitness_eval_tiles(mh_ctx *ctx, const void *tiles, const uint32_t *n_unique,

@@ -519,13 +519,14 @@ mh_status launch_fitness_tiles(Ctx *ctx, const void *tiles, uint32_t F, uint32_t
 
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                               const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
-                              uint32_t n_min, double alpha, const FitnessOut &out) {
+                              uint32_t n_min, double alpha, const FitnessOut &out,
+                              uint32_t *leafcnt) {
   const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
   const size_t cells = (size_t)P * SL * ds->K;
-  uint32_t *leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
+  if (!leafcnt) leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
   if (!leafcnt) return MH_ENOMEM;
   hipStream_t st = ctx->stream;
-  MH_HIP(ctx, hipMemsetAsync(leafcnt, 0, cells * 4, st));
+  if (mh_status zs = launch_zero(ctx, {{leafcnt, cells * 4}})) return zs;
   const uint32_t hist_cells = SL * ds->K;
   const uint32_t in_lds = hist_cells <= 12288u ? 1u : 0u;
   size_t lds = (size_t)(2 * SB + (in_lds ? hist_cells : 0u)) * 4;

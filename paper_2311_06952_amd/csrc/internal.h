@@ -94,6 +94,9 @@ struct Ctx {
   std::vector<std::pair<const void *, uint32_t>> coop_bad;
   const void *last_coop_kern = nullptr;
   uint32_t last_coop_grid = 0;
+  // this device's copy of the allocation-free entry point's static scratch
+  // (null when its address could not be looked up)
+  uint8_t *static_scratch = nullptr;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
@@ -277,10 +280,12 @@ mh_status launch_fitness_jobs(Ctx *ctx, uint32_t D, uint32_t waves, uint32_t F_m
                               const FitJob *jobs, const uint16_t *job_of, uint32_t n_blocks);
 // Direct per-sample walk for any depth (1..10): one tree at a time, leaf
 // counts per (tree, leaf, class), then the same epilogue.
+// leafcnt: P * 2^D * K u32 of device scratch the call may use (null: the
+// context arena's).
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                               uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
                               uint32_t P, uint32_t D, uint32_t n_min, double alpha,
-                              const FitnessOut &out);
+                              const FitnessOut &out, uint32_t *leafcnt = nullptr);
 
 // de.hip
 // Population layouts: row-major [P][m] (the C ABI) or gene-major [m][P]
