@@ -198,6 +198,10 @@ void *arena_get(Ctx *ctx, const char *name, size_t bytes) {
 
 // Tile path limits: depth templates 1..5, one LDS tile <= 64 KiB.
 static bool tile_path_ok(uint32_t D, uint32_t F) { return D >= 1 && D <= 5 && F <= 80; }
+// Fewer trees than this leave most lanes of the tile kernel idle (lane =
+// tree) while it still stages every tile: the walk kernel (lane = sample)
+// evaluates them instead.
+constexpr uint32_t TILE_MIN_TREES = 4;
 
 static mh_status check_dataset(Ctx *ctx, const mh_dataset *ds) {
   if (!ds) return fail(ctx, MH_EINVAL, "dataset is null");
@@ -249,7 +253,7 @@ struct EvalSet {
 static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, const uint32_t *tau,
                             uint32_t P, uint32_t D, uint32_t n_min, double alpha,
                             const FitnessOut &out) {
-  if (es.tiles)
+  if (es.tiles && P >= TILE_MIN_TREES)
     return launch_fitness_tiles(ctx, es.tiles, es.ds->F, es.ds->K, es.n_sub, 1, es.max_tiles, feat,
                                 tau, P, D, n_min, alpha, es.cnt, out);
   return launch_fitness_walk(ctx, es.ds, es.idx, es.n_sub, feat, tau, P, D, n_min, alpha, out,
@@ -260,25 +264,29 @@ static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, co
 // counts (walk path) that one fitness evaluation of P depth-D trees over
 // n_sub samples of ds uses, each part 256-byte aligned.
 static size_t eval_scratch_bytes(const mh_dataset *ds, uint32_t n_sub, uint32_t D, uint32_t P) {
-  if (tile_path_ok(D, ds->F))
+  if (tile_path_ok(D, ds->F) && P >= TILE_MIN_TREES)
     return align256(tile_layout(n_sub, ds->F, ds->K, 1).total_bytes) +
            align256(cnt_bytes(1, D, ds->K, P));
   return align256((size_t)P * ((size_t)1 << D) * ds->K * 4);
 }
 
 // static_base: caller-provided scratch of eval_scratch_bytes (null: the
-// context arena's buffers tile_name and cnt_name).
+// context arena's buffers tile_name and cnt_name).  min_trees: the tile
+// layout is built only for at least this many trees (DEOCT builds it for its
+// population whatever the size: its kernels all read it).
 static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                               uint32_t D, uint32_t P, const char *tile_name, const char *cnt_name,
-                              EvalSet &es, uint8_t *static_base = nullptr) {
+                              EvalSet &es, uint8_t *static_base = nullptr,
+                              uint32_t min_trees = 0) {
   es.ds = ds;
   es.idx = idx;
   es.n_sub = n_sub;
   es.tiles = nullptr;
   es.cnt = nullptr;
   es.max_tiles = 0;
-  es.leafcnt = tile_path_ok(D, ds->F) ? nullptr : reinterpret_cast<uint32_t *>(static_base);
-  if (!tile_path_ok(D, ds->F)) return MH_OK;
+  const bool use_tiles = tile_path_ok(D, ds->F) && P >= min_trees;
+  es.leafcnt = use_tiles ? nullptr : reinterpret_cast<uint32_t *>(static_base);
+  if (!use_tiles) return MH_OK;
   TileHdr h = tile_layout(n_sub, ds->F, ds->K, 1);
   void *tiles = static_base ? static_base : arena_get(ctx, tile_name, h.total_bytes);
   uint32_t *cnt = static_base
@@ -636,7 +644,8 @@ static mh_status fitness_eval_core(Ctx *c, const mh_dataset *ds, const uint32_t 
                       std::to_string(STATIC_SCRATCH_BYTES) + " (use fitness_eval)");
   }
   EvalSet es;
-  s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es, static_base);
+  s = prepare_eval(c, ds, idx, n_sub, D, P, "fe_tiles", "fe_cnt", es, static_base,
+                   TILE_MIN_TREES);
   if (s) return s;
   s = launch_zero(c, {{es.cnt, es.cnt ? cnt_bytes(1, D, ds->K, P) : 0}});
   if (s) return s;

@@ -93,6 +93,133 @@ __global__ __launch_bounds__(LB) void k_de_gen(StepArgs a, GenArgs e) {
                                               a.rows_in_lds ? rows : nullptr, s_nu);
 }
 
+// The same generation split over the chip for large populations (one block
+// of de_gen_body would make every individual's draws and float64 work one
+// after another on a single CU).  Same arithmetic and results.
+//
+// Part 1, thread r = individual r of problem blockIdx.y: the epilogue of the
+// evaluated population's node counts (its cost), then selection (eq.
+// selection, ties to the trial) or, in generation 0, the initial cost; the
+// consumed counters go back to zero.
+constexpr uint32_t SPLIT_THREADS = 256;
+
+template <int D>
+__global__ __launch_bounds__(SPLIT_THREADS) void k_de_select(StepArgs a, GenArgs e) {
+  constexpr int SB = (1 << D) - 1, m = 2 * SB;
+  const uint32_t sub = blockIdx.y, P = a.P, Ppad = pad64(P), K = e.K;
+  const uint32_t r = blockIdx.x * SPLIT_THREADS + threadIdx.x;
+  if (r >= P) return;
+  const size_t rep = cnt_copy_elems(e.n_problems, SB, K, P);
+  const TreeScore sc = epilogue_node_counts<D, CNT_REP>(
+      e.cnt + (size_t)sub * SB * K * Ppad, e.ctot + (size_t)sub * K, K, Ppad, r,
+      a.feat + ((size_t)sub * P + r) * SB, e.n_min, e.alpha, nullptr, nullptr, rep);
+  double *cost = a.cost + (size_t)sub * P;
+  if (e.init) {
+    cost[r] = sc.cost;
+    return;
+  }
+  if (!(sc.cost <= cost[r])) return;
+  cost[r] = sc.cost;
+  const double *tr = a.trial + (size_t)sub * P * m + (size_t)r * a.rs;
+  double *pr = a.pop + (size_t)sub * P * m + (size_t)r * a.rs;
+  constexpr int QB = 10;
+#pragma unroll
+  for (int q0 = 0; q0 < m; q0 += QB) {
+    double v[QB];
+#pragma unroll
+    for (int i = 0; i < QB; ++i)
+      if (q0 + i < m) v[i] = tr[(size_t)(q0 + i) * a.qs];
+#pragma unroll
+    for (int i = 0; i < QB; ++i)
+      if (q0 + i < m) pr[(size_t)(q0 + i) * a.qs] = v[i];
+  }
+}
+
+// Part 2, one thread per (node t, individual r) of problem blockIdx.y, r
+// fastest so that a wave's gene reads coalesce (gene-major population):
+// every block first finds best (lowest index of the minimum cost) itself,
+// block 0 writes it; then DE/best/1 mutation of the node's two genes, clamp,
+// binomial crossover, the trial genes, and the node decoded into (feat, tau).
+template <int D>
+__global__ __launch_bounds__(SPLIT_THREADS) void k_de_mutate(StepArgs a) {
+  constexpr int SB = (1 << D) - 1;
+  __shared__ double s_c[SPLIT_THREADS / 64];
+  __shared__ uint32_t s_i[SPLIT_THREADS / 64];
+  const uint32_t sub = blockIdx.y, P = a.P;
+  const double *cost = a.cost + (size_t)sub * P;
+  double bc = DBL_MAX;
+  uint32_t bi = 0xFFFFFFFFu;
+  for (uint32_t i = threadIdx.x; i < P; i += SPLIT_THREADS) {
+    const double c = cost[i];
+    if (c < bc) {  // ascending i in this thread: ties keep the lower index
+      bc = c;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double c2 = __shfl_xor(bc, o, 64);
+    const uint32_t i2 = __shfl_xor(bi, o, 64);
+    if (c2 < bc || (c2 == bc && i2 < bi)) {
+      bc = c2;
+      bi = i2;
+    }
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    s_c[threadIdx.x >> 6] = bc;
+    s_i[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  bc = s_c[0];
+  bi = s_i[0];
+  for (uint32_t x = 1; x < SPLIT_THREADS / 64; ++x) {
+    if (s_c[x] < bc || (s_c[x] == bc && s_i[x] < bi)) {
+      bc = s_c[x];
+      bi = s_i[x];
+    }
+  }
+  const uint32_t bst = bi;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.best) a.best[sub] = bst;
+  if (!a.next_trial) return;
+  const uint32_t e = blockIdx.x * SPLIT_THREADS + threadIdx.x;
+  if (e >= P * SB) return;
+  const uint32_t t = e / P, r = e % P;
+  constexpr uint32_t m = 2 * SB;
+  const uint64_t key = de_key(a.seed, prob_of(a.prob_ids, a.prob_base, sub));
+  const uint32_t g = a.g;
+  const double Mr = a.M >= 0.0 ? a.M : to_unit(de_draw(key, g, r, 0));
+  uint32_t r1 = to_below(de_draw(key, g, r, 1), P - 1u);
+  r1 += (r1 >= r) ? 1u : 0u;
+  uint32_t r2 = to_below(de_draw(key, g, r, 2), P - 2u);
+  const uint32_t lo = r < r1 ? r : r1, hi = r < r1 ? r1 : r;
+  r2 += (r2 >= lo) ? 1u : 0u;
+  r2 += (r2 >= hi) ? 1u : 0u;
+  const uint32_t qr = to_below(de_draw(key, g, r, 3), m);
+  const double *pop = a.pop + (size_t)sub * P * m;
+  double *out = a.next_trial + (size_t)sub * P * m;
+  const double Fp1 = (double)a.F + 1.0;
+  double gq[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t qq = t + (h ? SB : 0u);
+    const double *row = pop + (size_t)qq * a.qs;
+    const double d = __dsub_rn(row[(size_t)r1 * a.rs], row[(size_t)r2 * a.rs]);
+    double v = __dadd_rn(row[(size_t)bst * a.rs], __dmul_rn(Mr, d));
+    const double hiq = h ? 1.0 : Fp1;
+    if (!(v >= 0.0)) v = 0.0;
+    if (v > hiq) v = hiq;
+    const double u = to_unit(de_draw(key, g, r, 4u + qq));
+    gq[h] = (u <= a.CR || qq == qr) ? v : row[(size_t)r * a.rs];
+    out[(size_t)qq * a.qs + (size_t)r * a.rs] = gq[h];
+  }
+  if (a.feat) {
+    uint32_t f, th;
+    decode_node(gq[0], gq[1], a.F, a.n_unique, f, th);
+    a.feat[((size_t)sub * P + r) * SB + t] = (uint8_t)f;
+    a.tau[((size_t)sub * P + r) * SB + t] = th;
+  }
+}
+
 // One block per job (problem), each with its own population, tile-set
 // counts and generation; threads r < P of the job are its individuals.
 template <int D, int LB>
@@ -138,10 +265,17 @@ mh_status launch_decode(Ctx *ctx, const double *genes, uint32_t P, uint32_t D, u
   return MH_OK;
 }
 
-// LDS for the post-selection population when it fits in 48 KiB, else 0.
-static size_t rows_lds_bytes(uint32_t P, uint32_t D) {
+// LDS for the post-selection population when it fits in `limit` bytes
+// (48 KiB unless the launch has more to give), else 0.
+static size_t rows_lds_bytes(uint32_t P, uint32_t D, size_t limit = 48 * 1024) {
   const size_t b = (size_t)P * 2 * ((1u << D) - 1u) * 8;
-  return b <= 48 * 1024 ? b : 0;
+  return b <= limit ? b : 0;
+}
+// The most dynamic LDS a one-block-per-problem DE kernel may take: the
+// device's per-block limit less its static arrays (argmin scratch, n_unique).
+static size_t de_rows_limit(const Ctx *ctx) {
+  const size_t stat = 1024 * 8 + 1024 * 4 + 256 * 4 + 1024;
+  return ctx->max_lds > stat ? ctx->max_lds - stat : 0;
 }
 
 static StepArgs make_args(const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base,
@@ -174,6 +308,10 @@ static StepArgs make_args(const DeDev &de, const uint64_t *prob_ids, uint64_t pr
   return a;
 }
 
+// From this population size on a generation's DE work runs as two launches
+// spread over the chip instead of one block per problem.
+constexpr uint32_t DE_SPLIT_MIN_P = 256;
+
 static uint32_t step_threads(uint32_t P) {
   uint32_t threads = 64;
   while (threads < P) threads <<= 1;  // power of two for the argmin tree
@@ -190,8 +328,30 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
   const uint32_t rp = step_threads(de.P);
   const uint32_t tpi = 1;  // more threads per individual measured slower
   GenArgs e{cnt, ctot, K, n_min, alpha, init ? 1 : 0, tpi, n_problems};
+  if (de.P >= DE_SPLIT_MIN_P) {
+    // large populations: the generation as two launches spread over the chip
+    hipStream_t st = ctx->stream;
+    const uint32_t SB = (1u << de.D) - 1u;
+    const dim3 g1((de.P + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
+    const dim3 g2((de.P * SB + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
+#define MH_SPLIT(DD)                                                          \
+  k_de_select<DD><<<g1, SPLIT_THREADS, 0, st>>>(a, e);                        \
+  k_de_mutate<DD><<<g2, SPLIT_THREADS, 0, st>>>(a);
+    switch (de.D) {
+      case 1: MH_SPLIT(1) break;
+      case 2: MH_SPLIT(2) break;
+      case 3: MH_SPLIT(3) break;
+      case 4: MH_SPLIT(4) break;
+      case 5: MH_SPLIT(5) break;
+      default: return fail(ctx, MH_EINVAL, "fused DE step supports depth 1..5");
+    }
+#undef MH_SPLIT
+    MH_LAUNCHED(ctx, "k_de_select/k_de_mutate");
+    return MH_OK;
+  }
   const uint32_t threads = rp * tpi;
-  const size_t lds = rows_lds_bytes(de.P, de.D);
+  const size_t lds = rows_lds_bytes(de.P, de.D, de_rows_limit(ctx));
+  a.rows_in_lds = lds > 0;
   hipStream_t st = ctx->stream;
 #define MH_GEN(DD)                                                            \
   if (threads <= 256)                                                         \

@@ -309,10 +309,23 @@ __device__ __forceinline__ void de_gen_body(const StepArgs &a, const GenArgs &e,
         if (take) pop[(size_t)q * qs] = v;
       }
     } else {
-      for (int q = 0; q < m; ++q) {
-        const double v = take ? tr[(size_t)q * qs] : pop[(size_t)q * qs];
-        if (rows) rows[(size_t)q * P + r] = v;
-        if (take) pop[(size_t)q * qs] = v;
+      // batches of loads issued together: a store into pop may alias a later
+      // load of it, so unbatched loads would each wait for the previous store
+      const double *src = take ? tr : pop;
+      constexpr int QB = 10;
+#pragma unroll
+      for (int q0 = 0; q0 < m; q0 += QB) {
+        double v[QB];
+#pragma unroll
+        for (int i = 0; i < QB; ++i)
+          if (q0 + i < m) v[i] = src[(size_t)(q0 + i) * qs];
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
+          if (q0 + i < m) {
+            if (rows) rows[(size_t)(q0 + i) * P + r] = v[i];
+            if (take) pop[(size_t)(q0 + i) * qs] = v[i];
+          }
+        }
       }
     }
   }

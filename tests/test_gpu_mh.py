@@ -112,3 +112,17 @@ def test_mh_depth8_launch_forms(mh, monkeypatch, form, n, P, G):
     _same(seq, want)
     _same(bat, want)
     ctx.close()
+
+
+def test_mh_large_population_per_generation(mh, monkeypatch):
+    """Moving horizon with P = 256 per subproblem on the per-generation kernels
+    (the DE generation of every node of a level split over the chip) equals
+    the oracle's tree."""
+    from paper_2311_06952_amd import capi
+    X, y = synth.random_small(31, 6000, 5, 3, levels=40)
+    monkeypatch.setenv("MHDEOCT_PERSIST", "0")
+    ctx = capi.Context(0)
+    want, seq, bat = _mh_both(mh, X, y, 3, 5, 3, 256, 4, 99, M=-1.0, ctx=ctx)
+    _same(seq, want)
+    _same(bat, want)
+    ctx.close()

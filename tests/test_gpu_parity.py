@@ -518,3 +518,23 @@ def test_autotune_keeps_results(mh):
     _same_tree(want, got)
     ctx.close()
 
+
+
+@pytest.mark.parametrize("D,P,K,M,n_min,alpha", [(1, 256, 2, 0.5, 1, 0.0), (3, 300, 3, -1.0, 1, 0.0),
+                                                 (4, 512, 4, 0.5, 20, 7.5), (5, 1024, 3, 0.5, 1, 0.0),
+                                                 (2, 257, 6, -1.0, 3, 0.0)])
+def test_large_population_generation_split(mh, monkeypatch, D, P, K, M, n_min, alpha):
+    """From P = 256 on, a generation's DE work on the per-generation path runs
+    as a selection launch and a mutation launch spread over the chip; the run
+    (final population included) equals the oracle's."""
+    from paper_2311_06952_amd import capi
+    X, y = synth.random_small(500 + D + P, 7000, 7, K)
+    monkeypatch.setenv("MHDEOCT_PERSIST", "0")
+    ctx = capi.Context(0)
+    ds = mh.dataset(X, y, K, ctx=ctx)
+    prm = (P, 6, M, 0.9, 41 + D, n_min, alpha)
+    got = mh.subtree_solve(ds, D, mh.de_params(*prm), prob=5, ctx=ctx, with_pop=True)
+    want = oracle.deoct(oracle.dataset_from_X(X, y, K), D, oracle.de_params(*prm), prob=5,
+                        with_pop=True)
+    _same_tree(want, got)
+    ctx.close()
