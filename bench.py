@@ -1,12 +1,13 @@
 """Benchmark: sample-tree evaluations per second of the MH-DEOCT fitness path
 on one MI355X.
 
-A step is one DEOCT run (Algorithm 4) on the plain-scale workload: n = 100,000
-samples, F = 16 Gaussian-mixture features, K = 3 classes, depth-3 trees,
-P = 256, G = 200 generations (M = 0.5, CR = 0.9): rank encoding of the
-resident float32 features, the tiled sample layout, initialisation and
-G + 1 population evaluations with the DE step between them, all on the device.
-value = P * n * (G + 1) / (seconds per step).
+A step is one DEOCT run (Algorithm 4) on the large plain workload: n =
+1,000,000 samples, F = 32 float32 features (16 from a 4-component Gaussian
+mixture, 16 uniform noise), K = 4 classes from a planted depth-5 tree with 5 %
+label flips, depth-4 trees, P = 512, G = 100 generations (M = 0.5, CR = 0.9):
+rank encoding of the resident float32 features, the tiled sample layout,
+initialisation and G + 1 population evaluations with the DE step between
+them, all on the device.  value = P * n * (G + 1) / (seconds per step).
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -23,11 +24,66 @@ sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 64 * 2.4e9      # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 HBM_PEAK = 8.0e12                 # bytes/s
+CSRC = os.path.join(ROOT, "paper_2311_06952_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+# the dominant kernel of each form, the sources its code comes from, and the
+# committed counter summary of it
+KERNELS = {
+    "per_generation": dict(
+        sources=("fitness.hip", "fitness_core.h", "epilogue.h", "device_common.h", "de_body.h",
+                 "internal.h"),
+        counters="k_fitness_bits_plain_large_counters.txt"),
+    "persistent": dict(
+        sources=("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "grid_sync.h",
+                 "internal.h"),
+        counters=None),
+}
+C2_TRAFFIC = os.path.join(PROFILES, "k_deoct_persist_plain_scale_traffic.txt")
+C2_SOURCES = KERNELS["persistent"]["sources"]
+
+
+def source_hash(sources):
+    import hashlib
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_summary(path, sources):
+    """Key: value lines of a committed counter summary, or None when it is
+    missing or the kernel's sources changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256_16") != source_hash(sources):
+            return None
+        return kv
+    except OSError:
+        return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(w, seconds=15.0):
-    """The oracle on the host: DEOCT generations on the same workload, as many
-    as fit in about `seconds` (at least one)."""
+    """The oracle on the host cores (its fitness loop over individuals on
+    OpenMP threads): DEOCT runs on the same workload with G = 1, 2, 4, ... as
+    many as fit in about `seconds` (at least one)."""
     import oracle
     ods = oracle.dataset_from_X(w.X, w.y, w.K)
     evals = 0
@@ -43,42 +99,11 @@ def cpu_baseline(w, seconds=15.0):
             break
         G *= 2
     el = time.perf_counter() - t0
-    return dict(value=evals / el, unit="sample-tree evals/s", cores=1, kind="oracle",
-                sample=f"oracle DEOCT runs with G = 1, 2, 4, ... on the full n={w.n} "
-                       f"workload, {evals:.3g} evals in {el:.1f} s, single thread")
-
-
-KERNEL = "k_deoct_persist<3,4,2,true>"
-KERNEL_SOURCES = ("persist.hip", "fitness_core.h", "epilogue.h", "device_common.h", "grid_sync.h",
-                  "internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_deoct_persist_plain_scale_traffic.txt")
-
-
-def kernel_source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2311_06952_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic():
-    """HBM bytes per launch of the DEOCT kernel from the committed counter
-    summary, or None when it is missing or the kernel sources changed since
-    the counters were taken."""
-    try:
-        kv = {}
-        with open(TRAFFIC_FILE) as fh:
-            for line in fh:
-                if ":" in line and not line.startswith(" "):
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
-        if kv.get("kernel_source_sha256_16") != kernel_source_hash():
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+    thr = oracle.threads()
+    return dict(value=evals / el, unit="sample-tree evals/s", cores=thr, kind="oracle",
+                sample=f"oracle DEOCT runs with G = 1, 2, 4, ... on the full {w.name} workload "
+                       f"(rank encoding excluded), {evals:.3g} evals in {el:.1f} s on {thr} "
+                       f"OpenMP threads of {os.cpu_count()} visible CPUs ({cpu_model()})")
 
 
 def ds_of(mh, Xd, yd, w, ctx):
@@ -86,33 +111,58 @@ def ds_of(mh, Xd, yd, w, ctx):
     return mh.Dataset(ranks, yd, nu, w.n, w.F, w.K)
 
 
-def roofline(w, kernel_ms, launches_per_step, kernel=None):
+def kernel_name(w, form, tuned):
+    waves = min(8, max(1, (w.P + 63) // 64))
+    waves = 8 if waves > 4 else (4 if waves > 2 else waves)
+    if form == "persistent":
+        return f"k_deoct_persist<{w.D},{waves},{tuned['halves']},...>"
+    return f"k_fitness_bits<{w.D},{waves},false>"
+
+
+def roofline(w, kernel_ms, launches_per_step, form, kname):
     """The dominant kernel against the int32 VALU roof: D compare-and-descend
-    steps and one count per sample-tree evaluation (Algorithm 1).  With the
-    whole run in one launch, a launch covers all G + 1 population
-    evaluations."""
+    steps and one count per sample-tree evaluation (Algorithm 1).  Per
+    generation the kernel is launched once per population evaluation; the
+    whole-run form covers all G + 1 of them in one launch.  Beside it: the
+    kernel's own VALU instruction rate and its HBM bytes from the committed
+    counter summary (null once the kernel's sources changed)."""
     evals_launch = w.P * w.n * (w.G + 1) // launches_per_step
     ops_per_eval = w.D + 1
-    achieved = ops_per_eval * evals_launch / (kernel_ms * 1e-3)
+    sec = kernel_ms * 1e-3
+    achieved = ops_per_eval * evals_launch / sec
     bytes_launch = (4 * w.F + 1) / w.P * evals_launch
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
-            "kernel": kernel or (KERNEL if launches_per_step == 1 else "k_fitness_bits<3,4,false>"),
-            "kernel_ms_avg": kernel_ms, "launches_per_step": launches_per_step,
-            "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
-            "algorithmic_bytes_per_launch": bytes_launch,
-            "hbm_equiv": {"GB_s": bytes_launch / (kernel_ms * 1e-3) / 1e9,
-                          "frac": bytes_launch / (kernel_ms * 1e-3) / HBM_PEAK}}
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+           "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
+           "kernel": kname, "kernel_ms_avg": kernel_ms, "launches_per_step": launches_per_step,
+           "ops_per_eval": ops_per_eval, "evals_per_launch": evals_launch,
+           "algorithmic_bytes_per_launch": bytes_launch,
+           "hbm_equiv": {"GB_s": bytes_launch / sec / 1e9, "frac": bytes_launch / sec / HBM_PEAK}}
+    k = KERNELS[form]
+    kv = read_summary(os.path.join(PROFILES, k["counters"]), k["sources"]) if k["counters"] else None
+    if kv:
+        traffic = float(kv["traffic_bytes_per_launch"])
+        valu = float(kv["sq_insts_valu_per_launch"]) * 64
+        out["traffic"] = traffic
+        out["counters"] = {
+            "source": k["counters"],
+            "hbm_GB_s": traffic / sec / 1e9, "hbm_frac": traffic / sec / HBM_PEAK,
+            "valu_lane_ops_per_s": valu / sec, "valu_frac": valu / sec / VALU_PEAK,
+            "lds_insts_per_launch": float(kv["sq_insts_lds_per_launch"]),
+            "lds_bank_conflict_cycles_per_cu": float(kv["lds_bank_conflict_cycles_per_cu"]),
+            "note": "rates use this run's kernel duration with the counted per-launch totals"}
+    return out
 
 
 def kernel_only(args):
     """Counter runs: one plain device copy of known size (the calibration for
-    the byte counters), then --steps DEOCT runs on the resident plain-scale
-    dataset.  Prints one JSON line."""
+    the byte counters), then --steps DEOCT runs of --gens generations on the
+    resident workload (the large plain one by default).  Prints one JSON
+    line."""
     import torch
     import paper_2311_06952_amd as mh
     from paper_2311_06952_amd import synth
-    w = synth.plain_scale(1)
+    w = synth.plain_scale(1) if args.workload == "plain_scale" else synth.plain_large(1)
+    G = args.gens if args.gens > 0 else w.G
     ctx = mh.default_context(0)
     dev = torch.device("cuda", 0)
     copy_bytes = 256 << 20
@@ -123,19 +173,89 @@ def kernel_only(args):
     Xd = torch.as_tensor(w.X).to(dev)
     yd = torch.as_tensor(w.y).to(dev)
     ds = ds_of(mh, Xd, yd, w, ctx)
-    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    prm = mh.de_params(w.P, G, w.M, w.CR, 1001)
     ctx.stats(reset=True)
     ctx.profile(True)
     for _ in range(args.steps):
         mh.subtree_solve(ds, w.D, prm, ctx=ctx)
     ctx.profile(False)
     st = ctx.stats(reset=True)
+    print(json.dumps({"workload": w.name, "generations": G, "launches": int(st["launches"]),
+                      "kernel_ms_avg": st["ms"] / max(st["launches"], 1),
+                      "copy_bytes": copy_bytes,
+                      "per_generation_sha256_16": source_hash(KERNELS["per_generation"]["sources"]),
+                      "persistent_sha256_16": source_hash(KERNELS["persistent"]["sources"])}),
+          flush=True)
+
+
+def timed_steps(mh, ctx, w, Xd, yd, steps, warmup, tune=True):
+    """W untimed and K timed steps (rank encoding with an asynchronous status
+    word, tile layout, the whole DEOCT run, the result read-back), then the
+    same K steps again with the fitness launches timed by HIP events on the
+    library's stream.  Returns (ms per step, result of the last step, event
+    milliseconds per fitness launch, fitness launches per step, tuned)."""
+    import torch
+    dev = Xd.device
+    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    enc = mh.rank_encode(Xd, ctx)  # output buffers, written again by every step
+
+    def step():
+        # the rank encoding's NaN check is read back with the solved tree, so
+        # a step waits for the device once
+        ranks, nu = mh.rank_encode(Xd, ctx, status=status, out=enc)
+        return mh.subtree_solve(mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status), w.D, prm,
+                                ctx=ctx)
+
+    # launch configuration for this shape, timed on short runs (it changes
+    # timing only)
+    if tune:
+        tuned = mh.autotune(ds_of(mh, Xd, yd, w, ctx), w.D, prm, generations=10, ctx=ctx)
+    else:
+        tuned = {"persist": 1, "halves": int(os.environ.get("MHDEOCT_PERSIST_HALVES", "2")),
+                 "persist_blocks_per_cu": 0, "fit_blocks_per_cu": 2, "untuned": True}
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # fitness-kernel duration: the population-evaluation launches record
+    # start/stop events themselves (kept out of the timed steps above because
+    # event-carrying launches cost about 3 us each)
+    ctx.stats(reset=True)
+    ctx.profile(True)
+    for _ in range(steps):
+        step()
+    ctx.profile(False)
+    st = ctx.stats(reset=True)
     kernel_ms = st["ms"] / max(st["launches"], 1)
-    lps = max(1, round(st["launches"] / args.steps))
-    print(json.dumps({"kernel": KERNEL, "workload": w.name, "launches": int(st["launches"]),
-                      "kernel_ms_avg": kernel_ms, "copy_bytes": copy_bytes,
-                      "kernel_source_sha256_16": kernel_source_hash(),
-                      "roofline": roofline(w, kernel_ms, lps)}), flush=True)
+    lps = max(1, round(st["launches"] / steps))
+    return el / steps * 1e3, res, kernel_ms, lps, tuned, int(st["launches"])
+
+
+def plain_scale(mh, ctx, steps=5, warmup=1):
+    """The plain-scale workload (n = 100,000, F = 16, K = 3, depth 3, P = 256,
+    G = 200): the whole run is one grid-synchronising launch with the tiles
+    resident in LDS."""
+    import torch
+    from paper_2311_06952_amd import synth
+    w = synth.plain_scale(1)
+    dev = torch.device("cuda", 0)
+    Xd = torch.as_tensor(w.X).to(dev)
+    yd = torch.as_tensor(w.y).to(dev)
+    ms, res, kms, lps, tuned, nl = timed_steps(mh, ctx, w, Xd, yd, steps, warmup)
+    form = "persistent" if lps == 1 else "per_generation"
+    roof = roofline(w, kms, lps, form, kernel_name(w, form, tuned))
+    kv = read_summary(C2_TRAFFIC, C2_SOURCES) if form == "persistent" else None
+    roof["traffic"] = float(kv["traffic_bytes_per_launch"]) if kv else None
+    return {"workload": w.name, "ms_per_step": ms,
+            "evals_per_s": w.P * w.n * (w.G + 1) / (ms * 1e-3), "best_correct": res["correct"],
+            "roofline": roof,
+            "launch_config": {k: tuned[k] for k in ("persist", "halves", "persist_blocks_per_cu",
+                                                    "fit_blocks_per_cu")}}, (w, Xd, yd, res)
 
 
 def _device_requests(torch, reqs):
@@ -348,7 +468,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-configuration tuning (size rules and environment)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the serving and moving-horizon measurements")
+                    help="skip the other workloads (plain-scale, serving, moving horizon, ...)")
     ap.add_argument("--extra-only", action="store_true",
                     help="only the serving and moving-horizon measurements (for profiler runs)")
     ap.add_argument("--predict-only", action="store_true",
@@ -356,8 +476,11 @@ def main():
     ap.add_argument("--alpha-only", action="store_true",
                     help="only the alpha sweep with validation")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="only a calibration copy and --steps fitness-kernel launches "
-                         "(for counter runs)")
+                    help="only a calibration copy and --steps DEOCT runs (for counter runs)")
+    ap.add_argument("--workload", default="plain_large", choices=("plain_large", "plain_scale"),
+                    help="workload of --kernel-only")
+    ap.add_argument("--gens", type=int, default=10,
+                    help="generations per DEOCT run of --kernel-only (0: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -378,68 +501,32 @@ def main():
     import paper_2311_06952_amd as mh
     from paper_2311_06952_amd import synth
 
-    w = synth.plain_scale(1)
     ctx = mh.default_context(0)
     dev = torch.device("cuda", 0)
+    if args.predict_only or args.alpha_only:
+        w2 = synth.plain_scale(1)
+        X2 = torch.as_tensor(w2.X).to(dev)
+        y2 = torch.as_tensor(w2.y).to(dev)
+        if args.alpha_only:
+            print(json.dumps({"alpha_sweep": alpha_sweep(mh, ctx, w2)}), flush=True)
+        else:
+            t = mh.subtree_solve(ds_of(mh, X2, y2, w2, ctx), w2.D,
+                                 mh.de_params(w2.P, w2.G, w2.M, w2.CR, 1001), ctx=ctx)
+            print(json.dumps({"predict": predict_bench(mh, ctx, w2, X2, y2, t)}), flush=True)
+        return
+
+    w = synth.plain_large(1)
     Xd = torch.as_tensor(w.X).to(dev)
     yd = torch.as_tensor(w.y).to(dev)
-    prm = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
-    enc = mh.rank_encode(Xd, ctx)  # output buffers, written again by every step
-
-    def step():
-        # rank encoding's NaN check is read back with the solved tree, so a
-        # step waits for the device once
-        ranks, nu = mh.rank_encode(Xd, ctx, status=status, out=enc)
-        ds = mh.Dataset(ranks, yd, nu, w.n, w.F, w.K, status)
-        return mh.subtree_solve(ds, w.D, prm, ctx=ctx)
-
-    if args.predict_only:
-        print(json.dumps({"predict": predict_bench(mh, ctx, w, Xd, yd, step())}), flush=True)
-        return
-    if args.alpha_only:
-        print(json.dumps({"alpha_sweep": alpha_sweep(mh, ctx, w)}), flush=True)
-        return
-
-    # launch configuration for this shape, timed on short runs (before the
-    # warm-up; it changes timing only)
-    if args.no_tune:
-        tuned = {"persist": 1, "halves": int(os.environ.get("MHDEOCT_PERSIST_HALVES", "2")),
-                 "persist_blocks_per_cu": 0, "fit_blocks_per_cu": 2, "untuned": True}
-    else:
-        tuned = mh.autotune(ds_of(mh, Xd, yd, w, ctx), w.D, prm, generations=20, ctx=ctx)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms = el / args.steps * 1e3
+    ms, res, kernel_ms, lps, tuned, nlaunch = timed_steps(mh, ctx, w, Xd, yd, args.steps,
+                                                          args.warmup, tune=not args.no_tune)
     evals_per_step = w.P * w.n * (w.G + 1)
-    value = evals_per_step * args.steps / el
-
-    # fitness-kernel duration: the same steps again with HIP events that the
-    # population-evaluation launches record themselves on the library's
-    # stream (read back after the region; kept out of the timed steps above
-    # because event-carrying launches cost about 3 us each)
-    ctx.stats(reset=True)
-    ctx.profile(True)
-    for _ in range(args.steps):
-        step()
-    ctx.profile(False)
-    st = ctx.stats(reset=True)
-    kernel_ms = st["ms"] / max(st["launches"], 1)
-    lps = max(1, round(st["launches"] / args.steps))
-    kname = (f"k_deoct_persist<3,4,{tuned['halves']},true>" if lps == 1
-             else "k_fitness_bits<3,4,false>")
-    roof = roofline(w, kernel_ms, lps, kname)
-    roof["timed_launches"] = int(st["launches"])
+    form = "persistent" if lps == 1 else "per_generation"
+    roof = roofline(w, kernel_ms, lps, form, kernel_name(w, form, tuned))
+    roof["timed_launches"] = nlaunch
     out = {
         "metric": "sample-tree evals/s (fitness)",
-        "value": value,
+        "value": evals_per_step / (ms * 1e-3),
         "unit": "sample-tree evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -451,19 +538,24 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "F": w.F, "K": w.K, "D": w.D, "P": w.P,
-                   "G": w.G, "M": w.M, "CR": w.CR, "form": "plain DEOCT, the whole run in "
-                   "one grid-synchronising launch"},
+                   "G": w.G, "M": w.M, "CR": w.CR,
+                   "form": ("plain DEOCT, the whole run in one grid-synchronising launch"
+                            if form == "persistent" else
+                            "plain DEOCT, one fitness launch and two DE launches per generation")},
         "kernel_evals_per_s": roof["evals_per_launch"] / (kernel_ms * 1e-3),
-        "subtree_solves_per_s": args.steps / el,
+        "subtree_solves_per_s": 1e3 / ms,
         "best_correct": res["correct"],
         "roofline": roof,
         "launch_config": {k: tuned[k] for k in ("persist", "halves", "persist_blocks_per_cu",
                                                 "fit_blocks_per_cu")},
     }
+    del Xd, yd
     if not args.no_extra:
-        out["predict"] = predict_bench(mh, ctx, w, Xd, yd, res)
-        out["deep_whole_tree"] = deep_whole_tree(mh, ctx, w, Xd, yd)
-        out["alpha_sweep"] = alpha_sweep(mh, ctx, w)
+        c2, (w2, X2, y2, res2) = plain_scale(mh, ctx)
+        out["plain_scale"] = c2
+        out["predict"] = predict_bench(mh, ctx, w2, X2, y2, res2)
+        out["deep_whole_tree"] = deep_whole_tree(mh, ctx, w2, X2, y2)
+        out["alpha_sweep"] = alpha_sweep(mh, ctx, w2)
         out["serving"] = serving(mh)
         # the same forms on a stream of small requests (n log-uniform in
         # [1e3, 2e4]), where a request alone cannot fill the GPU

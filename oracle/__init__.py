@@ -5,8 +5,9 @@ compared against.  Only the test suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import it; the product package never
 imports, links or calls anything here, and the two share no code.
 
-The arithmetic lives in ``mhdeoct_oracle.c`` (plain C, single thread,
-``-O2 -ffp-contract=off``).  This module only builds it and marshals numpy
+The arithmetic lives in ``mhdeoct_oracle.c`` (plain C, ``-O2
+-ffp-contract=off``; its fitness loop over individuals runs on OpenMP threads,
+which changes no result).  This module only builds it and marshals numpy
 arrays through ctypes.  Each wrapper names the passage of the paper that the C
 function follows; the readings taken where the paper is silent are stated in
 the C source.
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp",
              "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -60,6 +61,8 @@ def _load():
     lib.oracle_splitmix64_next.restype = C.c_uint64
     lib.oracle_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
     lib.oracle_draw.restype = C.c_uint64
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = C.c_int
     lib.oracle_u01.argtypes = [C.c_uint64]
     lib.oracle_u01.restype = C.c_double
     lib.oracle_uint.argtypes = [C.c_uint64, C.c_uint32]
@@ -150,6 +153,11 @@ def splitmix64_sequence(seed: int, count: int) -> list[int]:
     lib = _load()
     st = C.c_uint64(seed)
     return [int(lib.oracle_splitmix64_next(C.byref(st))) for _ in range(count)]
+
+
+def threads() -> int:
+    """Threads of the oracle's parallel fitness loop (OpenMP)."""
+    return int(_load().oracle_threads())
 
 
 def draw(seed: int, prob: int, g: int, r: int, slot: int) -> int:

@@ -1,5 +1,5 @@
 /*
- * mhdeoct_oracle.c -- plain, slow, single-threaded CPU oracle for the
+ * mhdeoct_oracle.c -- plain, slow CPU oracle for the
  * MH-DEOCT fitness-evaluation path (Ren et al., "A GPU-Accelerated
  * Moving-Horizon Algorithm for Training Deep Classification Trees on Large
  * Datasets", arXiv 2311.06952).
@@ -16,8 +16,11 @@
  * notes).  Indices are 0-based here; tree nodes use the paper's 1-based heap
  * numbering t = 1..T internally and are stored at array slot t-1.
  *
- * Build: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction, so that
- * every f64 operation is a single IEEE rounding, exactly as written).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction,
+ * so that every f64 operation is a single IEEE rounding, exactly as written).
+ * The one parallel loop is oracle_fitness's loop over individuals: each
+ * individual's counts, labels and cost are its own, so the thread count
+ * (OMP_NUM_THREADS) never changes a result; everything else is sequential.
  *
  * Parity status per function (pins live in tests/test_oracle_*.py):
  *   oracle_rank_encode   pinned (numpy.unique special case, -0/+0, NaN)
@@ -44,6 +47,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -230,6 +236,15 @@ void oracle_tree_epilogue(const uint32_t *counts, uint32_t K, uint32_t D,
   }
 }
 
+/* Threads the parallel fitness loop uses (1 without OpenMP). */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int oracle_fitness(const uint32_t *ranks, size_t ld, const uint8_t *labels,
                    uint32_t K, const uint32_t *idx, uint32_t n_sub,
                    const uint8_t *feat, const uint32_t *tau, uint32_t P,
@@ -237,6 +252,7 @@ int oracle_fitness(const uint32_t *ranks, size_t ld, const uint8_t *labels,
                    uint32_t *correct, uint8_t *label, double *cost) {
   if (K < 1 || D < 1 || D > 10) return OR_EINVAL;
   uint32_t SL = 1u << D, SB = SL - 1u;
+#pragma omp parallel for schedule(dynamic, 1)
   for (uint32_t r = 0; r < P; ++r) {
     uint32_t *c = counts + (size_t)r * SL * K;
     memset(c, 0, sizeof(uint32_t) * SL * K);
