@@ -387,22 +387,30 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
       if (s) return s;
     }
   } else {
+    // walk path (depth above 5, wide data): per generation the walk kernel
+    // and the leaf epilogue give the trial costs, then one launch makes the
+    // selection, best and the next trial (a thread per node and individual);
+    // the trial population alternates between two buffers
+    double *trial2 = (double *)arena_get(ctx, "ss_trial2", (size_t)P * m * 8);
+    if (!trial2) return MH_ENOMEM;
     FitnessOut fo;
     fo.cost = cost;
     s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, fo);
     if (s) return s;
     // best of generation 0, and the trial population of generation 1
-    s = launch_de_step(ctx, de, nullptr, prob, 1, 1, pop, cost, nullptr, nullptr, best,
-                       prm->G >= 1 ? trial : nullptr, feat, tau);
+    s = launch_de_select_mutate(ctx, de, prob, 1, pop, cost, nullptr, nullptr, best,
+                                prm->G >= 1 ? trial : nullptr, feat, tau);
     if (s) return s;
     FitnessOut ft;
     ft.cost = tcost;
+    double *cur = trial, *nxt = trial2;
     for (uint32_t g = 1; g <= prm->G; ++g) {
       s = eval_trees(ctx, es, feat, tau, P, D, prm->n_min, prm->alpha, ft);
       if (s) return s;
-      s = launch_de_step(ctx, de, nullptr, prob, 1, g + 1, pop, cost, trial, tcost, best,
-                         g < prm->G ? trial : nullptr, feat, tau);
+      s = launch_de_select_mutate(ctx, de, prob, g + 1, pop, cost, cur, tcost, best,
+                                  g < prm->G ? nxt : nullptr, feat, tau);
       if (s) return s;
+      std::swap(cur, nxt);
     }
   }
   if (!persisted) {

@@ -140,9 +140,9 @@ __global__ __launch_bounds__(SPLIT_THREADS) void k_de_select(StepArgs a, GenArgs
 // every block first finds best (lowest index of the minimum cost) itself,
 // block 0 writes it; then DE/best/1 mutation of the node's two genes, clamp,
 // binomial crossover, the trial genes, and the node decoded into (feat, tau).
-template <int D>
+// Any depth (SB = a.SB).
 __global__ __launch_bounds__(SPLIT_THREADS) void k_de_mutate(StepArgs a) {
-  constexpr int SB = (1 << D) - 1;
+  const uint32_t SB = a.SB;
   __shared__ double s_c[SPLIT_THREADS / 64];
   __shared__ uint32_t s_i[SPLIT_THREADS / 64];
   const uint32_t sub = blockIdx.y, P = a.P;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void k_de_mutate(StepArgs a) {
   const uint32_t e = blockIdx.x * SPLIT_THREADS + threadIdx.x;
   if (e >= P * SB) return;
   const uint32_t t = e / P, r = e % P;
-  constexpr uint32_t m = 2 * SB;
+  const uint32_t m = 2 * SB;
   const uint64_t key = de_key(a.seed, prob_of(a.prob_ids, a.prob_base, sub));
   const uint32_t g = a.g;
   const double Mr = a.M >= 0.0 ? a.M : to_unit(de_draw(key, g, r, 0));
@@ -217,6 +217,127 @@ __global__ __launch_bounds__(SPLIT_THREADS) void k_de_mutate(StepArgs a) {
     decode_node(gq[0], gq[1], a.F, a.n_unique, f, th);
     a.feat[((size_t)sub * P + r) * SB + t] = (uint8_t)f;
     a.tau[((size_t)sub * P + r) * SB + t] = th;
+  }
+}
+
+// One DE generation of a problem whose trial costs are already in memory
+// (the walk path), one thread per (node t, individual r), r fastest: the
+// selection of generation g - 1 (eq. selection, ties to the trial) and the
+// trial of generation g in one launch.  Selection is applied where it is
+// read: individual j's post-selection gene is trial[j] when
+// cost_t[j] <= cost[j], else pop[j], and its post-selection cost the smaller
+// rule's pick; every block finds best from those, block 0 writes it.  The
+// thread of (t, r) also stores r's two selected genes into pop (and, for
+// t = 0, r's cost into cost) when the trial won.  These stores race with no
+// read: a taken individual's genes and cost are read from the trial side, and
+// an individual whose trial lost is never written; the cost rule picks the
+// same value before and after its store.  The trial population is read from
+// `trial` and the next one written to a different buffer, next_trial
+// (generation g; null: only the selection and best).  Without trial
+// (generation 1 from the initial population) nothing is selected.
+__global__ __launch_bounds__(SPLIT_THREADS) void k_de_select_mutate(StepArgs a) {
+  const uint32_t SB = a.SB, P = a.P, m = 2 * SB;
+  __shared__ double s_c[SPLIT_THREADS / 64];
+  __shared__ uint32_t s_i[SPLIT_THREADS / 64];
+  double *cost = a.cost;
+  const double *ct = a.trial_cost;
+  const bool sel = a.trial != nullptr;
+  auto post_cost = [&](uint32_t j) {
+    const double c = cost[j];
+    if (!sel) return c;
+    const double t = ct[j];
+    return t <= c ? t : c;
+  };
+  double bc = DBL_MAX;
+  uint32_t bi = 0xFFFFFFFFu;
+  for (uint32_t i = threadIdx.x; i < P; i += SPLIT_THREADS) {
+    const double c = post_cost(i);
+    if (c < bc) {  // ascending i in this thread: ties keep the lower index
+      bc = c;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double c2 = __shfl_xor(bc, o, 64);
+    const uint32_t i2 = __shfl_xor(bi, o, 64);
+    if (c2 < bc || (c2 == bc && i2 < bi)) {
+      bc = c2;
+      bi = i2;
+    }
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    s_c[threadIdx.x >> 6] = bc;
+    s_i[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  bc = s_c[0];
+  bi = s_i[0];
+  for (uint32_t x = 1; x < SPLIT_THREADS / 64; ++x) {
+    if (s_c[x] < bc || (s_c[x] == bc && s_i[x] < bi)) {
+      bc = s_c[x];
+      bi = s_i[x];
+    }
+  }
+  const uint32_t bst = bi;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.best) a.best[0] = bst;
+  const uint32_t e = blockIdx.x * SPLIT_THREADS + threadIdx.x;
+  if (e >= P * SB) return;
+  const uint32_t t = e / P, r = e % P;
+  double *pop = a.pop;
+  const double *tr = a.trial;
+  auto taken = [&](uint32_t j) { return sel && ct[j] <= cost[j]; };
+  // gene q of individual j after selection (gene-major: q * P + j)
+  auto gene = [&](uint32_t j, bool tk, uint32_t q) {
+    const size_t o = (size_t)q * P + j;
+    return tk ? tr[o] : pop[o];
+  };
+  const bool tk_r = taken(r);
+  if (!a.next_trial) {
+    if (tk_r) {
+      pop[(size_t)t * P + r] = tr[(size_t)t * P + r];
+      pop[(size_t)(SB + t) * P + r] = tr[(size_t)(SB + t) * P + r];
+      if (t == 0) cost[r] = ct[r];
+    }
+    return;
+  }
+  const uint64_t key = de_key(a.seed, a.prob_base);
+  const uint32_t g = a.g;
+  const double Mr = a.M >= 0.0 ? a.M : to_unit(de_draw(key, g, r, 0));
+  uint32_t r1 = to_below(de_draw(key, g, r, 1), P - 1u);
+  r1 += (r1 >= r) ? 1u : 0u;
+  uint32_t r2 = to_below(de_draw(key, g, r, 2), P - 2u);
+  const uint32_t lo = r < r1 ? r : r1, hi = r < r1 ? r1 : r;
+  r2 += (r2 >= lo) ? 1u : 0u;
+  r2 += (r2 >= hi) ? 1u : 0u;
+  const uint32_t qr = to_below(de_draw(key, g, r, 3), m);
+  const bool tk_b = taken(bst), tk_1 = taken(r1), tk_2 = taken(r2);
+  const double Fp1 = (double)a.F + 1.0;
+  double gq[2], own[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t qq = t + (h ? SB : 0u);
+    own[h] = gene(r, tk_r, qq);
+    const double d = __dsub_rn(gene(r1, tk_1, qq), gene(r2, tk_2, qq));
+    double v = __dadd_rn(gene(bst, tk_b, qq), __dmul_rn(Mr, d));
+    const double hiq = h ? 1.0 : Fp1;
+    if (!(v >= 0.0)) v = 0.0;
+    if (v > hiq) v = hiq;
+    const double u = to_unit(de_draw(key, g, r, 4u + qq));
+    gq[h] = (u <= a.CR || qq == qr) ? v : own[h];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t qq = t + (h ? SB : 0u);
+    a.next_trial[(size_t)qq * P + r] = gq[h];
+    if (tk_r) pop[(size_t)qq * P + r] = own[h];
+  }
+  if (tk_r && t == 0) cost[r] = ct[r];
+  if (a.feat) {
+    uint32_t f, th;
+    decode_node(gq[0], gq[1], a.F, a.n_unique, f, th);
+    a.feat[(size_t)r * SB + t] = (uint8_t)f;
+    a.tau[(size_t)r * SB + t] = th;
   }
 }
 
@@ -336,7 +457,7 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
     const dim3 g2((de.P * SB + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
 #define MH_SPLIT(DD)                                                          \
   k_de_select<DD><<<g1, SPLIT_THREADS, 0, st>>>(a, e);                        \
-  k_de_mutate<DD><<<g2, SPLIT_THREADS, 0, st>>>(a);
+  k_de_mutate<<<g2, SPLIT_THREADS, 0, st>>>(a);
     switch (de.D) {
       case 1: MH_SPLIT(1) break;
       case 2: MH_SPLIT(2) break;
@@ -427,6 +548,19 @@ FuseArgs make_fuse(const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base
 bool fusable(uint32_t P, uint32_t D, uint32_t F) {
   return D >= 1 && D <= 5 && F <= 80 && fused_threads(P) <= fitness_block_threads(P) &&
          fitness_block_threads(P) >= pad64(P);
+}
+
+mh_status launch_de_select_mutate(Ctx *ctx, const DeDev &de, uint64_t prob, uint32_t g,
+                                 double *pop, double *cost, const double *trial,
+                                 const double *trial_cost, uint32_t *best, double *next_trial,
+                                 uint8_t *feat, uint32_t *tau) {
+  StepArgs a = make_args(de, nullptr, prob, g, pop, cost, trial, trial_cost, best, next_trial,
+                         feat, tau);
+  const uint32_t SB = (1u << de.D) - 1u;
+  const uint32_t blocks = (de.P * SB + SPLIT_THREADS - 1) / SPLIT_THREADS;
+  k_de_select_mutate<<<blocks, SPLIT_THREADS, 0, ctx->stream>>>(a);
+  MH_LAUNCHED(ctx, "k_de_select_mutate");
+  return MH_OK;
 }
 
 mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uint64_t prob_base,

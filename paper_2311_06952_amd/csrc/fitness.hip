@@ -232,77 +232,217 @@ __global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------------------
-// Walk kernel (any depth).  Block = 256 threads over a chunk of samples and
-// every gridDim.y-th tree; for each tree: stage (feat, tau) in LDS, walk
-// every sample of the chunk down the tree, histogram (leaf, class) in LDS,
-// add the histogram to leafcnt.  The trees are spread over the grid's second
-// dimension so that a small sample count still fills the chip.
+// Walk kernel (any depth): lane = sample.  A block owns a range of samples
+// and a group of up to TG trees.  It stages its samples tile by tile in LDS
+// (every rank column and the labels, coalesced 16-byte loads), then walks
+// each tile through every tree of its group (Algorithm 1: t <- 2t if
+// rank < tau else 2t + 1, D steps), adding one to the (tree, leaf, class)
+// histogram in LDS; each tile is read from memory once for the whole group.
+// A node is one 64-bit LDS word: tau above, and below the byte offset of its
+// rank column in the tile (a no-split node reads column 0 with tau = 0, so
+// every sample goes right).  A walk keeps the LDS address of its current
+// node and advances it directly (node t at base + 8 (t - 1), so that child
+// 2t + b sits at 2 addr - base + 8 + 8b).  With the tile in LDS as [F][T],
+// lane i reads word f * T + i whatever feature its node splits on, so the
+// rank reads of a wave never conflict.  Each thread walks GI trees at once
+// (independent chains of dependent LDS reads).  The histogram goes to memory
+// once per block (global atomics directly when it does not fit).  With many
+// features (a tile of 256 samples over 48 KiB) only the labels are staged
+// and the ranks are read from memory at each step (the node then holds the
+// column index).
 // ---------------------------------------------------------------------------
-constexpr uint32_t WALK_THREADS = 256;
-constexpr uint32_t WALK_ITEMS = 8;
+constexpr uint32_t WT_THREADS = 256;
 
-__global__ __launch_bounds__(WALK_THREADS) void k_fitness_walk(
-    const uint32_t *__restrict__ ranks, uint32_t ld, const uint8_t *__restrict__ labels,
-    const uint32_t *__restrict__ idx, uint32_t n_sub, const uint8_t *__restrict__ feat,
-    const uint32_t *__restrict__ tau, uint32_t P, uint32_t D, uint32_t F, uint32_t K, uint32_t n,
-    uint32_t *__restrict__ leafcnt, uint32_t hist_in_lds) {
+struct WalkArgs {
+  const uint32_t *ranks;
+  uint32_t ld;
+  const uint8_t *labels;
+  const uint32_t *idx;
+  uint32_t n_sub, n;
+  const uint8_t *feat;
+  const uint32_t *tau;
+  uint32_t P, D, F, K;
+  uint32_t T;       // samples per tile (a multiple of WT_THREADS)
+  uint32_t TG;      // trees per block
+  uint32_t ranges;  // sample ranges (gridDim.x)
+  uint32_t hist_in_lds;
+  uint32_t vec4;  // rank columns readable as 16-byte chunks (aligned, ld % 4 == 0)
+  uint32_t *leafcnt;  // [P][2^D][K]
+};
+
+template <int IT, bool STAGED>
+__global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
+  constexpr int GI = IT >= 2 ? 4 : 8;  // trees walked together
+  constexpr uint32_t PFV = 12;         // prefetched 16-byte chunks per thread
   extern __shared__ __align__(16) uint32_t wl[];
-  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
-  uint32_t *s_feat = wl;
-  uint32_t *s_tau = wl + SB;
-  uint32_t *hist = wl + 2 * SB;
-  constexpr uint32_t CHUNK = WALK_THREADS * WALK_ITEMS;
-  const uint32_t n_chunks = (n_sub + CHUNK - 1) / CHUNK;
-  for (uint32_t r = blockIdx.y; r < P; r += gridDim.y) {
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < SB; t += WALK_THREADS) {
-      uint32_t f = feat[(size_t)r * SB + t];
-      f = f <= F ? f : 0u;
-      s_feat[t] = f;
-      s_tau[t] = f ? tau[(size_t)r * SB + t] : 0u;
-    }
-    if (hist_in_lds)
-      for (uint32_t e = threadIdx.x; e < SL * K; e += WALK_THREADS) hist[e] = 0;
-    __syncthreads();
-    uint32_t *dst = leafcnt + (size_t)r * SL * K;
-    // every gridDim.x-th chunk of samples, all into the one LDS histogram
-    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-      uint32_t ii[WALK_ITEMS];
-      uint32_t yy[WALK_ITEMS];
+  const uint32_t SB = (1u << a.D) - 1u, SL = 1u << a.D, T = a.T, K = a.K;
+  const uint32_t FT = STAGED ? a.F * T : 0u;
+  uint32_t *tile = wl;                                   // [F][T] when staged
+  uint8_t *ylab = reinterpret_cast<uint8_t *>(wl + FT);  // [T]
+  uint64_t *nodes = reinterpret_cast<uint64_t *>(wl + FT + T / 4);  // [TG][SB]
+  uint32_t *hist = reinterpret_cast<uint32_t *>(nodes + (size_t)a.TG * SB);  // [TG][SL][K]
+  // absolute LDS byte addresses
+  const uint32_t lds0 = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint32_t *)wl);
+  const uint32_t node0 = lds0 + 4u * (FT + T / 4);
+  const uint32_t r0 = blockIdx.y * a.TG;
+  const uint32_t tg = min(a.TG, a.P - r0);
+  // this block's trees: nodes into LDS, histogram cleared
+  for (uint32_t e = threadIdx.x; e < tg * SB; e += WT_THREADS) {
+    const uint32_t g = e / SB, t = e % SB;
+    uint32_t f = a.feat[(size_t)(r0 + g) * SB + t];
+    f = f <= a.F ? f : 0u;
+    const uint32_t th = f ? a.tau[(size_t)(r0 + g) * SB + t] : 0u;
+    const uint32_t col = f ? f - 1u : 0u;
+    nodes[e] = ((uint64_t)th << 32) | (STAGED ? col * T * 4u : col);
+  }
+  if (a.hist_in_lds)
+    for (uint32_t e = threadIdx.x; e < tg * SL * K; e += WT_THREADS) hist[e] = 0;
+  // the block's sample range, in tiles (a whole number of tiles, so that
+  // every tile starts at a multiple of 4 samples for the 16-byte loads)
+  const uint32_t per = ((a.n_sub + a.ranges - 1) / a.ranges + T - 1) / T * T;
+  const uint32_t s0 = blockIdx.x * per, s1 = min(a.n_sub, s0 + per);
+  // whole tiles of contiguous samples move as 16-byte chunks, prefetched into
+  // registers one tile ahead (while the current tile is walked)
+  const uint32_t T4 = T / 4, nch = STAGED ? a.F * T4 : 0u;
+  const bool pf_ok = STAGED && a.vec4 && !a.idx && nch <= PFV * WT_THREADS;
+  uint4 pf[PFV];
+  auto prefetch = [&](uint32_t b) {
 #pragma unroll
-      for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
-        const uint32_t j = c * CHUNK + k * WALK_THREADS + threadIdx.x;
-        ii[k] = 0xFFFFFFFFu;
-        yy[k] = 0;
-        if (j < n_sub) {
-          const uint32_t i = idx ? idx[j] : j;
-          if (i < n && labels[i] < K) {  // invalid samples are left out
-            ii[k] = i;
-            yy[k] = labels[i];
+    for (uint32_t u = 0; u < PFV; ++u) {
+      const uint32_t c = threadIdx.x + u * WT_THREADS;
+      if (c < nch)
+        pf[u] = *reinterpret_cast<const uint4 *>(a.ranks + (size_t)(c / T4) * a.ld + b +
+                                                 4u * (c % T4));
+    }
+  };
+  bool have = false;
+  if (pf_ok && s0 < s1 && s1 - s0 >= T) {
+    prefetch(s0);
+    have = true;
+  }
+  for (uint32_t base = s0; base < s1; base += T) {
+    const uint32_t cnt = min(T, s1 - base);
+    __syncthreads();  // the previous tile (and the node set-up) is done
+    for (uint32_t i = threadIdx.x; i < T; i += WT_THREADS) {
+      uint32_t y = 0xFFu;
+      if (i < cnt) {
+        const uint32_t smp = a.idx ? a.idx[base + i] : base + i;
+        if (smp < a.n && a.labels[smp] < K) y = a.labels[smp];  // invalid samples are left out
+      }
+      ylab[i] = (uint8_t)y;
+    }
+    // the tile's ranks, SG loads in flight per thread before their stores
+    constexpr uint32_t SG = 8;
+    if (!STAGED) {
+    } else if (have) {
+      uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
+#pragma unroll
+      for (uint32_t u = 0; u < PFV; ++u) {
+        const uint32_t c = threadIdx.x + u * WT_THREADS;
+        if (c < nch) tile4[c] = pf[u];
+      }
+    } else if (a.idx) {
+      for (uint32_t e0 = threadIdx.x; e0 < a.F * T; e0 += SG * WT_THREADS) {
+        uint32_t v[SG];
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u) {
+          const uint32_t e = e0 + u * WT_THREADS, f = e / T, i = e % T;
+          v[u] = 0;
+          if (e < a.F * T && i < cnt) {
+            const uint32_t smp = a.idx[base + i];
+            if (smp < a.n) v[u] = a.ranks[(size_t)f * a.ld + smp];
+          }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u)
+          if (e0 + u * WT_THREADS < a.F * T) tile[e0 + u * WT_THREADS] = v[u];
+      }
+    } else if (a.vec4 && cnt == T) {
+      // whole tile, 16-byte chunks: chunk c is ranks 4i..4i+3 of column f
+      const uint32_t T4 = T / 4, nch = a.F * T4;
+      uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
+      for (uint32_t c0 = threadIdx.x; c0 < nch; c0 += SG * WT_THREADS) {
+        uint4 v[SG];
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u) {
+          const uint32_t c = c0 + u * WT_THREADS;
+          if (c < nch)
+            v[u] = *reinterpret_cast<const uint4 *>(a.ranks + (size_t)(c / T4) * a.ld + base +
+                                                    4u * (c % T4));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u)
+          if (c0 + u * WT_THREADS < nch) tile4[c0 + u * WT_THREADS] = v[u];
+      }
+    } else {
+      for (uint32_t e0 = threadIdx.x; e0 < a.F * T; e0 += SG * WT_THREADS) {
+        uint32_t v[SG];
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u) {
+          const uint32_t e = e0 + u * WT_THREADS, f = e / T, i = e % T;
+          v[u] = (e < a.F * T && i < cnt) ? a.ranks[(size_t)f * a.ld + base + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < SG; ++u)
+          if (e0 + u * WT_THREADS < a.F * T) tile[e0 + u * WT_THREADS] = v[u];
+      }
+    }
+    __syncthreads();
+    have = pf_ok && base + T < s1 && s1 - (base + T) >= T;
+    if (have) prefetch(base + T);
+    uint32_t yk[IT], sk[IT], lane_off[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = threadIdx.x + k * WT_THREADS;
+      yk[k] = ylab[i];
+      lane_off[k] = lds0 + 4u * i;  // the sample's rank in column 0
+      // (unstaged ranks: the sample itself; in range whenever its label is valid)
+      sk[k] = (!STAGED && yk[k] != 0xFFu) ? (a.idx ? a.idx[base + i] : base + i) : 0u;
+    }
+    // GI trees at a time; a group past the last tree repeats the last one
+    // and leaves its count out
+    for (uint32_t g0 = 0; g0 < tg; g0 += GI) {
+      uint32_t nb[GI], na[GI][IT];
+#pragma unroll
+      for (int gg = 0; gg < GI; ++gg) {
+        nb[gg] = node0 + 8u * SB * min(g0 + gg, tg - 1);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) na[gg][k] = nb[gg];
+      }
+      for (uint32_t lv = 0; lv < a.D; ++lv) {
+#pragma unroll
+        for (int gg = 0; gg < GI; ++gg) {
+#pragma unroll
+          for (int k = 0; k < IT; ++k) {
+            const uint64_t w = lds_rd64(na[gg][k]);
+            const uint32_t lo = (uint32_t)w, th = (uint32_t)(w >> 32);
+            const uint32_t rk =
+                STAGED ? lds_rd32(lo + lane_off[k]) : a.ranks[(size_t)lo * a.ld + sk[k]];
+            na[gg][k] = 2u * na[gg][k] - nb[gg] + (rk < th ? 8u : 16u);
           }
         }
       }
 #pragma unroll
-      for (uint32_t k = 0; k < WALK_ITEMS; ++k) {
-        if (ii[k] == 0xFFFFFFFFu) continue;
-        uint32_t t = 1;
-        while (t <= SB) {
-          uint32_t f = s_feat[t - 1];
-          bool left = f != 0 && ranks[(size_t)(f - 1) * ld + ii[k]] < s_tau[t - 1];
-          t = left ? 2 * t : 2 * t + 1;
+      for (int gg = 0; gg < GI; ++gg) {
+        const uint32_t g = g0 + gg;
+        if (g >= tg) continue;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+          if (yk[k] == 0xFFu) continue;
+          const uint32_t leaf = (na[gg][k] - nb[gg]) / 8u + 1u - SL;
+          const uint32_t e = leaf * K + yk[k];
+          if (a.hist_in_lds)
+            atomicAdd(&hist[(size_t)g * SL * K + e], 1u);
+          else
+            atomicAdd(&a.leafcnt[(size_t)(r0 + g) * SL * K + e], 1u);
         }
-        uint32_t e = (t - SL) * K + yy[k];
-        if (hist_in_lds)
-          atomicAdd(&hist[e], 1u);
-        else
-          atomicAdd(&dst[e], 1u);
       }
     }
-    if (hist_in_lds) {
-      __syncthreads();
-      for (uint32_t e = threadIdx.x; e < SL * K; e += WALK_THREADS)
-        if (hist[e]) atomicAdd(&dst[e], hist[e]);
-    }
+  }
+  if (a.hist_in_lds) {
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < tg * SL * K; e += WT_THREADS)
+      if (hist[e]) atomicAdd(&a.leafcnt[(size_t)r0 * SL * K + e], hist[e]);
   }
 }
 
@@ -521,35 +661,97 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
                               const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
                               uint32_t n_min, double alpha, const FitnessOut &out,
                               uint32_t *leafcnt) {
-  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
-  const size_t cells = (size_t)P * SL * ds->K;
-  if (!leafcnt) leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D, K = ds->K, F = ds->F;
+  const size_t cells = (size_t)P * SL * K;
+  // only the context's own buffer is known to stay clear between calls (a
+  // caller's scratch may have held anything since)
+  const bool own = leafcnt == nullptr;
+  if (own) leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
   if (!leafcnt) return MH_ENOMEM;
   hipStream_t st = ctx->stream;
-  if (mh_status zs = launch_zero(ctx, {{leafcnt, cells * 4}})) return zs;
-  const uint32_t hist_cells = SL * ds->K;
-  const uint32_t in_lds = hist_cells <= 12288u ? 1u : 0u;
-  size_t lds = (size_t)(2 * SB + (in_lds ? hist_cells : 0u)) * 4;
-  if (n_sub > 0) {
-    const uint32_t chunks = (n_sub + WALK_THREADS * WALK_ITEMS - 1) / (WALK_THREADS * WALK_ITEMS);
-    // about 8 blocks per CU in all: one tree per block row where there are
-    // enough trees, the chunks of samples shared out over the rest (each
-    // block adds its histogram to memory once per tree)
-    const uint32_t want = 8u * (uint32_t)ctx->num_cu;
-    const uint32_t gy = std::max(1u, std::min(P, want));
-    const uint32_t blocks = std::max(1u, std::min(chunks, (want + gy - 1) / gy));
+  if (!(own && ctx->walk_zero == leafcnt && ctx->walk_zero_bytes >= cells * 4))
+    if (mh_status zs = launch_zero(ctx, {{leafcnt, cells * 4}})) return zs;
+  if (own) ctx->walk_zero = nullptr;
+  if (n_sub > 0 && P > 0 && ds->n > 0) {
+    WalkArgs a;
+    a.ranks = ds->ranks;
+    a.ld = ds->ld;
+    a.labels = ds->labels;
+    a.idx = idx;
+    a.n_sub = n_sub;
+    a.n = ds->n;
+    a.feat = feat;
+    a.tau = tau;
+    a.P = P;
+    a.D = D;
+    a.F = F;
+    a.K = K;
+    a.leafcnt = leafcnt;
+    a.vec4 = (ds->ld % 4 == 0 && ((uintptr_t)ds->ranks & 15u) == 0) ? 1u : 0u;
+    // LDS: the tile ([F][T] ranks and T labels), TG trees' nodes and, when
+    // it fits, their histograms, within a budget that leaves three blocks per
+    // CU; samples per thread: tiles of at most 16 KiB where the features allow
+    const size_t budget = std::max<size_t>(48 * 1024, (ctx->max_lds - 4096) / 3);
+    const bool staged = (size_t)F * WT_THREADS * 4 <= 48 * 1024;
+    uint32_t IT = 4;
+    while (IT > 1 && (size_t)F * WT_THREADS * IT * 4 > 16 * 1024) IT /= 2;
+    a.T = WT_THREADS * IT;
+    const size_t tile_bytes = (staged ? (size_t)F * a.T * 4 : 0) + a.T;
+    const size_t tree_nodes = (size_t)SB * 8, tree_hist = (size_t)SL * K * 4;
+    a.hist_in_lds = 1;
+    size_t TG = budget > tile_bytes ? (budget - tile_bytes) / (tree_nodes + tree_hist) : 0;
+    if (TG == 0) {
+      // histograms in memory: the nodes alone decide the trees per block
+      a.hist_in_lds = 0;
+      TG = budget > tile_bytes ? (budget - tile_bytes) / tree_nodes : 1;
+    }
+    TG = std::max<size_t>(1, std::min<size_t>({TG, 32, P}));
+    a.TG = (uint32_t)TG;
+    const uint32_t groups = (P + a.TG - 1) / a.TG;
+    const size_t lds =
+        tile_bytes + TG * tree_nodes + (a.hist_in_lds ? TG * tree_hist : 0);
+    const size_t lds_al = (lds + 15) & ~(size_t)15;
+    // sample ranges: one round of resident blocks in all, at least one tile
+    // each
+    const uint32_t per_cu = std::max<uint32_t>(
+        1u, std::min<uint32_t>(4u, (uint32_t)(ctx->max_lds / std::max<size_t>(lds_al, 1))));
+    const uint32_t want = per_cu * (uint32_t)ctx->num_cu;
+    const uint32_t tiles = (n_sub + a.T - 1) / a.T;
+    a.ranges = std::max(1u, std::min(tiles, want / groups));
+    // a multiple of 8 ranges puts every block of one range on the same XCD
+    // (blocks go round-robin over the 8 XCDs in launch order), so each XCD's
+    // L2 holds only its ranges' ranks
+    if (a.ranges >= 8) a.ranges &= ~7u;
     hipEvent_t e0, e1;
     const bool timed = prof_pair(ctx, &e0, &e1);
-    hipExtLaunchKernelGGL(k_fitness_walk, dim3(blocks, gy), dim3(WALK_THREADS), lds, st, e0, e1, 0,
-                          ds->ranks, ds->ld, ds->labels, idx, n_sub, feat, tau, P, D, ds->F,
-                          ds->K, ds->n, leafcnt, in_lds);
-    MH_LAUNCHED(ctx, "k_fitness_walk");
+    const dim3 grid(a.ranges, groups);
+#define MH_WALK(ITV)                                                                   \
+  if (staged)                                                                          \
+    hipExtLaunchKernelGGL(k_walk_tiles<ITV, true>, grid, dim3(WT_THREADS), lds_al, st,  \
+                          e0, e1, 0, a);                                               \
+  else                                                                                 \
+    hipExtLaunchKernelGGL(k_walk_tiles<ITV, false>, grid, dim3(WT_THREADS), lds_al, st, \
+                          e0, e1, 0, a);
+    if (IT == 4) {
+      MH_WALK(4)
+    } else if (IT == 2) {
+      MH_WALK(2)
+    } else {
+      MH_WALK(1)
+    }
+#undef MH_WALK
+    MH_LAUNCHED(ctx, "k_walk_tiles");
     if (timed) ctx->prof_launches += 1;
     ctx->prof_evals += (uint64_t)n_sub * P;
   }
   if (P > 0) {
-    k_epilogue_leaves<<<P, EPI_THREADS, 0, st>>>(leafcnt, feat, P, D, ds->K, n_min, alpha, out);
+    k_epilogue_leaves<<<P, EPI_THREADS, 0, st>>>(leafcnt, feat, P, D, K, n_min, alpha, out);
     MH_LAUNCHED(ctx, "k_epilogue_leaves");
+    // (it read and cleared every count of the P trees)
+    if (own) {
+      ctx->walk_zero = leafcnt;
+      ctx->walk_zero_bytes = cells * 4;
+    }
   }
   return MH_OK;
 }

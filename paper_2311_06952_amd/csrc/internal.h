@@ -97,6 +97,11 @@ struct Ctx {
   // this device's copy of the allocation-free entry point's static scratch
   // (null when its address could not be looked up)
   uint8_t *static_scratch = nullptr;
+  // the walk path's leaf-count buffer (and its bytes) when the last queued
+  // epilogue left it all zero (it clears what it reads): the next evaluation
+  // into it needs no clearing launch
+  const void *walk_zero = nullptr;
+  size_t walk_zero_bytes = 0;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
@@ -360,6 +365,16 @@ mh_status launch_de_jobs(Ctx *ctx, uint32_t D, const GenJob *jobs, uint32_t n_jo
                          uint32_t P_max);
 // One DE step for n_problems problems (block per problem).  When feat/tau are
 // given, the new trial population is also decoded into them.
+// The DE generation of one problem whose trial costs are in memory (the walk
+// path) in one launch spread over the chip: the selection of the trial
+// population `trial` (costs trial_cost; null trial: none, generation 1),
+// best, and the trial population of generation g into next_trial (a buffer
+// other than trial; null: only the selection and best), decoded into
+// feat/tau.  pop and cost are updated in place.  Gene-major populations.
+mh_status launch_de_select_mutate(Ctx *ctx, const DeDev &de, uint64_t prob, uint32_t g,
+                                 double *pop, double *cost, const double *trial,
+                                 const double *trial_cost, uint32_t *best, double *next_trial,
+                                 uint8_t *feat, uint32_t *tau);
 mh_status launch_de_step(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids,
                          uint64_t prob_base, uint32_t n_problems, uint32_t g, double *pop,
                          double *cost, const double *trial, const double *trial_cost,

@@ -124,6 +124,42 @@ def test_fitness(mh, seed, n, F, K, D, P, levels):
     np.testing.assert_array_equal(np_(got[3]), want[3])
 
 
+# (seed, n, F, K, D, P, subset, huge_tau): the walk kernel's forms --
+# staged tiles with several trees per block, ranks read from memory when the
+# feature set is wide, histograms in memory when they do not fit in LDS,
+# thresholds above every rank, subsets, fewer trees than the tile kernel
+# takes, ragged tails
+WALK_CASES = [
+    (21, 5000, 16, 3, 8, 37, False, False),
+    (22, 4099, 6, 4, 7, 100, True, True),
+    (23, 3000, 60, 3, 6, 9, False, True),      # 60 features: ranks from memory
+    (24, 2500, 5, 200, 10, 6, True, False),    # 2^10 leaves x 200 classes: counts in memory
+    (25, 1, 3, 2, 9, 3, False, False),
+    (26, 30_000, 12, 5, 4, 2, False, True),    # two trees: walk kernel at depth 4
+    (27, 777, 100, 3, 3, 1, True, False),      # one tree, wide data
+]
+
+
+@pytest.mark.parametrize("seed,n,F,K,D,P,subset,huge", WALK_CASES)
+def test_walk_kernel_forms(mh, seed, n, F, K, D, P, subset, huge):
+    X, y = synth.random_small(seed, n, F, K, levels=None if seed % 2 else 50)
+    ods = oracle.dataset_from_X(X, y, K)
+    rng = np.random.default_rng(seed)
+    feat, tau = random_trees(rng, P, D, F, ods.n_unique)
+    if huge:  # thresholds past every rank send every sample left
+        tau[rng.random(tau.shape) < 0.2] = 0xFFFFFFFF
+    idx = np.sort(rng.choice(n, size=max(1, n // 3), replace=False)).astype(np.uint32) \
+        if subset else None
+    want = oracle.fitness(ods, feat, tau, D, idx=idx, n_min=2, alpha=1.5)
+    ds = gpu_ds(mh, X, y, K)
+    got = mh.fitness_eval(ds, dev(feat), dev(tau), D, idx=None if idx is None else dev(idx),
+                          n_min=2, alpha=1.5)
+    np.testing.assert_array_equal(u32(got[0]), want[0])
+    np.testing.assert_array_equal(u32(got[1]), want[1])
+    np.testing.assert_array_equal(np_(got[2]), want[2])
+    np.testing.assert_array_equal(np_(got[3]), want[3])
+
+
 @pytest.mark.parametrize("D", [2, 4, 6])
 def test_fitness_subset_and_penalties(mh, D):
     X, y = synth.random_small(11, 3000, 5, 3, 40)
