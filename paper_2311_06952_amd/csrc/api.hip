@@ -267,7 +267,7 @@ static size_t eval_scratch_bytes(const mh_dataset *ds, uint32_t n_sub, uint32_t 
   if (tile_path_ok(D, ds->F) && P >= TILE_MIN_TREES)
     return align256(tile_layout(n_sub, ds->F, ds->K, 1).total_bytes) +
            align256(cnt_bytes(1, D, ds->K, P));
-  return align256((size_t)P * ((size_t)1 << D) * ds->K * 4);
+  return align256(walk_scratch_bytes(P, D, ds->K));
 }
 
 // static_base: caller-provided scratch of eval_scratch_bytes (null: the
@@ -528,6 +528,8 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_DEBUG")) c->c.debug = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_WALK_LDS"))
+    c->c.walk_lds = atoi(v) > 0 ? (size_t)std::min(std::max(atoi(v), 8192), 150 * 1024) : 0;
   if (const char *v = std::getenv("MHDEOCT_COOP_LAUNCH")) c->c.coop_api = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_WAIT_TICKS"))
     c->c.wait_ticks = std::min<uint64_t>(strtoull(v, nullptr, 10), 200000000ull);

@@ -24,6 +24,10 @@
 
 namespace mh {
 
+size_t walk_scratch_bytes(uint32_t P, uint32_t D, uint32_t K) {
+  return (size_t)P * ((size_t)1 << D) * K * 4;
+}
+
 size_t cnt_bytes(uint32_t n_problems, uint32_t D, uint32_t K, uint32_t P) {
   return CNT_REP * cnt_copy_elems(n_problems, (1u << D) - 1u, K, P) * 4;
 }
@@ -231,6 +235,70 @@ __global__ void k_epilogue_nodes(uint32_t *__restrict__ cnt, const uint32_t *__r
   if (out.cost) out.cost[tr] = sc.cost;
 }
 
+constexpr uint32_t EPI_THREADS = 256;
+
+// One tree's epilogue from its leaf counts [SL][K] (eq. opt_c, eq. opt_all
+// and the soft-constraint fitness of Section 3.2), by a block of EPI_THREADS
+// threads: labels (lowest class of the largest count, an empty leaf class
+// 0), correct count and cost, and the counts cleared after they are read.
+// COH: the counts were added by other blocks of the same launch (read with
+// agent-scope loads).  Called by every thread of the block.  (Scoring a
+// group's trees in the walk launch's last block instead of this separate
+// launch was measured slower: that block's coherent loads ran one after
+// another at the end of the launch.)
+template <bool COH>
+__device__ __forceinline__ void leaf_epilogue_tree(uint32_t *__restrict__ leafcnt,
+                                                   const uint8_t *__restrict__ feat, uint32_t r,
+                                                   uint32_t D, uint32_t K, uint32_t n_min,
+                                                   double alpha, const FitnessOut &out,
+                                                   uint32_t (*s_red)[EPI_THREADS / 64]) {
+  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
+  uint32_t correct = 0, nviol = 0, nsplit = 0, n_sub = 0;
+  for (uint32_t l = threadIdx.x; l < SL; l += EPI_THREADS) {
+    uint32_t *c = leafcnt + ((size_t)r * SL + l) * K;
+    uint32_t best = 0, bk = 0, nl = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+      const uint32_t v = cnt_load<COH>(c + k);
+      c[k] = 0;
+      if (out.counts) out.counts[((size_t)r * SL + l) * K + k] = v;
+      nl += v;
+      if (v > best) {
+        best = v;
+        bk = k;
+      }
+    }
+    n_sub += nl;
+    correct += best;
+    nviol += (nl > 0 && nl < n_min) ? 1u : 0u;
+    if (out.label) out.label[(size_t)r * SL + l] = (uint8_t)bk;
+  }
+  for (uint32_t t = threadIdx.x; t < SB; t += EPI_THREADS) nsplit += feat[(size_t)r * SB + t] != 0;
+  uint32_t v4[4] = {correct, nviol, nsplit, n_sub};
+  __syncthreads();  // s_red may still be read from an earlier call
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (uint32_t o = 32; o > 0; o >>= 1) v4[q] += __shfl_xor(v4[q], o, 64);
+    if ((threadIdx.x & 63u) == 0) s_red[q][threadIdx.x >> 6] = v4[q];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 4; ++q) {
+    v4[q] = 0;
+    for (uint32_t w = 0; w < EPI_THREADS / 64; ++w) v4[q] += s_red[q][w];
+  }
+  correct = v4[0];
+  nviol = v4[1];
+  nsplit = v4[2];
+  n_sub = v4[3];
+  if (out.correct) out.correct[r] = correct;
+  if (out.cost) {
+    double v = (double)(n_sub - correct);
+    v = __dadd_rn(v, __dmul_rn(alpha, (double)nsplit));
+    v = __dadd_rn(v, (double)nviol);
+    out.cost[r] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Walk kernel (any depth): lane = sample.  A block owns a range of samples
 // and a group of up to TG trees.  It stages its samples tile by tile in LDS
@@ -270,10 +338,8 @@ struct WalkArgs {
   uint32_t *leafcnt;  // [P][2^D][K]
 };
 
-template <int IT, bool STAGED>
+template <int IT, int GI, bool STAGED>
 __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
-  constexpr int GI = IT >= 2 ? 4 : 8;  // trees walked together
-  constexpr uint32_t PFV = 12;         // prefetched 16-byte chunks per thread
   extern __shared__ __align__(16) uint32_t wl[];
   const uint32_t SB = (1u << a.D) - 1u, SL = 1u << a.D, T = a.T, K = a.K;
   const uint32_t FT = STAGED ? a.F * T : 0u;
@@ -301,25 +367,6 @@ __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
   // every tile starts at a multiple of 4 samples for the 16-byte loads)
   const uint32_t per = ((a.n_sub + a.ranges - 1) / a.ranges + T - 1) / T * T;
   const uint32_t s0 = blockIdx.x * per, s1 = min(a.n_sub, s0 + per);
-  // whole tiles of contiguous samples move as 16-byte chunks, prefetched into
-  // registers one tile ahead (while the current tile is walked)
-  const uint32_t T4 = T / 4, nch = STAGED ? a.F * T4 : 0u;
-  const bool pf_ok = STAGED && a.vec4 && !a.idx && nch <= PFV * WT_THREADS;
-  uint4 pf[PFV];
-  auto prefetch = [&](uint32_t b) {
-#pragma unroll
-    for (uint32_t u = 0; u < PFV; ++u) {
-      const uint32_t c = threadIdx.x + u * WT_THREADS;
-      if (c < nch)
-        pf[u] = *reinterpret_cast<const uint4 *>(a.ranks + (size_t)(c / T4) * a.ld + b +
-                                                 4u * (c % T4));
-    }
-  };
-  bool have = false;
-  if (pf_ok && s0 < s1 && s1 - s0 >= T) {
-    prefetch(s0);
-    have = true;
-  }
   for (uint32_t base = s0; base < s1; base += T) {
     const uint32_t cnt = min(T, s1 - base);
     __syncthreads();  // the previous tile (and the node set-up) is done
@@ -334,13 +381,6 @@ __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
     // the tile's ranks, SG loads in flight per thread before their stores
     constexpr uint32_t SG = 8;
     if (!STAGED) {
-    } else if (have) {
-      uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
-#pragma unroll
-      for (uint32_t u = 0; u < PFV; ++u) {
-        const uint32_t c = threadIdx.x + u * WT_THREADS;
-        if (c < nch) tile4[c] = pf[u];
-      }
     } else if (a.idx) {
       for (uint32_t e0 = threadIdx.x; e0 < a.F * T; e0 += SG * WT_THREADS) {
         uint32_t v[SG];
@@ -366,6 +406,7 @@ __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
 #pragma unroll
         for (uint32_t u = 0; u < SG; ++u) {
           const uint32_t c = c0 + u * WT_THREADS;
+          v[u] = make_uint4(0u, 0u, 0u, 0u);
           if (c < nch)
             v[u] = *reinterpret_cast<const uint4 *>(a.ranks + (size_t)(c / T4) * a.ld + base +
                                                     4u * (c % T4));
@@ -388,8 +429,6 @@ __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
       }
     }
     __syncthreads();
-    have = pf_ok && base + T < s1 && s1 - (base + T) >= T;
-    if (have) prefetch(base + T);
     uint32_t yk[IT], sk[IT], lane_off[IT];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
@@ -450,58 +489,12 @@ __global__ __launch_bounds__(WT_THREADS) void k_walk_tiles(WalkArgs a) {
 // threads share out the leaves (and the nodes for the split count) and the
 // integer sums meet in a block reduction, so the result does not depend on
 // the order.
-constexpr uint32_t EPI_THREADS = 256;
-
 __global__ __launch_bounds__(EPI_THREADS) void k_epilogue_leaves(
     uint32_t *__restrict__ leafcnt, const uint8_t *__restrict__ feat, uint32_t P, uint32_t D,
     uint32_t K, uint32_t n_min, double alpha, FitnessOut out) {
   __shared__ uint32_t s_red[4][EPI_THREADS / 64];
-  const uint32_t r = blockIdx.x;
-  if (r >= P) return;
-  const uint32_t SB = (1u << D) - 1u, SL = 1u << D;
-  uint32_t correct = 0, nviol = 0, nsplit = 0, n_sub = 0;
-  for (uint32_t l = threadIdx.x; l < SL; l += EPI_THREADS) {
-    uint32_t *c = leafcnt + ((size_t)r * SL + l) * K;
-    uint32_t best = 0, bk = 0, nl = 0;
-    for (uint32_t k = 0; k < K; ++k) {
-      uint32_t v = c[k];
-      c[k] = 0;
-      if (out.counts) out.counts[((size_t)r * SL + l) * K + k] = v;
-      nl += v;
-      if (v > best) {
-        best = v;
-        bk = k;
-      }
-    }
-    n_sub += nl;
-    correct += best;
-    nviol += (nl > 0 && nl < n_min) ? 1u : 0u;
-    if (out.label) out.label[(size_t)r * SL + l] = (uint8_t)bk;
-  }
-  for (uint32_t t = threadIdx.x; t < SB; t += EPI_THREADS) nsplit += feat[(size_t)r * SB + t] != 0;
-  uint32_t v4[4] = {correct, nviol, nsplit, n_sub};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    for (uint32_t o = 32; o > 0; o >>= 1) v4[q] += __shfl_xor(v4[q], o, 64);
-    if ((threadIdx.x & 63u) == 0) s_red[q][threadIdx.x >> 6] = v4[q];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int q = 0; q < 4; ++q) {
-    v4[q] = 0;
-    for (uint32_t w = 0; w < EPI_THREADS / 64; ++w) v4[q] += s_red[q][w];
-  }
-  correct = v4[0];
-  nviol = v4[1];
-  nsplit = v4[2];
-  n_sub = v4[3];
-  if (out.correct) out.correct[r] = correct;
-  if (out.cost) {
-    double v = (double)(n_sub - correct);
-    v = __dadd_rn(v, __dmul_rn(alpha, (double)nsplit));
-    v = __dadd_rn(v, (double)nviol);
-    out.cost[r] = v;
-  }
+  if (blockIdx.x >= P) return;
+  leaf_epilogue_tree<false>(leafcnt, feat, blockIdx.x, D, K, n_min, alpha, out, s_red);
 }
 
 // Launches on st; when e0/e1 are given the launch records them at the
@@ -665,12 +658,13 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   const size_t cells = (size_t)P * SL * K;
   // only the context's own buffer is known to stay clear between calls (a
   // caller's scratch may have held anything since)
+  const size_t bytes = walk_scratch_bytes(P, D, K);
   const bool own = leafcnt == nullptr;
-  if (own) leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", cells * 4);
+  if (own) leafcnt = (uint32_t *)arena_get(ctx, "walk_leafcnt", bytes);
   if (!leafcnt) return MH_ENOMEM;
   hipStream_t st = ctx->stream;
-  if (!(own && ctx->walk_zero == leafcnt && ctx->walk_zero_bytes >= cells * 4))
-    if (mh_status zs = launch_zero(ctx, {{leafcnt, cells * 4}})) return zs;
+  if (!(own && ctx->walk_zero == leafcnt && ctx->walk_zero_bytes >= bytes))
+    if (mh_status zs = launch_zero(ctx, {{leafcnt, bytes}})) return zs;
   if (own) ctx->walk_zero = nullptr;
   if (n_sub > 0 && P > 0 && ds->n > 0) {
     WalkArgs a;
@@ -691,7 +685,8 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
     // LDS: the tile ([F][T] ranks and T labels), TG trees' nodes and, when
     // it fits, their histograms, within a budget that leaves three blocks per
     // CU; samples per thread: tiles of at most 16 KiB where the features allow
-    const size_t budget = std::max<size_t>(48 * 1024, (ctx->max_lds - 4096) / 3);
+    size_t budget = std::max<size_t>(48 * 1024, (ctx->max_lds - 4096) / 3);
+    if (ctx->walk_lds) budget = ctx->walk_lds;
     const bool staged = (size_t)F * WT_THREADS * 4 <= 48 * 1024;
     uint32_t IT = 4;
     while (IT > 1 && (size_t)F * WT_THREADS * IT * 4 > 16 * 1024) IT /= 2;
@@ -706,6 +701,10 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
       TG = budget > tile_bytes ? (budget - tile_bytes) / tree_nodes : 1;
     }
     TG = std::max<size_t>(1, std::min<size_t>({TG, 32, P}));
+    // trees walked together per thread: 8, or 4 for small groups; a group
+    // is a whole number of them where it can be
+    const uint32_t GI = TG >= 8 ? 8u : 4u;
+    if (TG > GI) TG -= TG % GI;
     a.TG = (uint32_t)TG;
     const uint32_t groups = (P + a.TG - 1) / a.TG;
     const size_t lds =
@@ -714,7 +713,7 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
     // sample ranges: one round of resident blocks in all, at least one tile
     // each
     const uint32_t per_cu = std::max<uint32_t>(
-        1u, std::min<uint32_t>(4u, (uint32_t)(ctx->max_lds / std::max<size_t>(lds_al, 1))));
+        1u, std::min<uint32_t>(8u, (uint32_t)(ctx->max_lds / std::max<size_t>(lds_al, 1))));
     const uint32_t want = per_cu * (uint32_t)ctx->num_cu;
     const uint32_t tiles = (n_sub + a.T - 1) / a.T;
     a.ranges = std::max(1u, std::min(tiles, want / groups));
@@ -725,13 +724,19 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
     hipEvent_t e0, e1;
     const bool timed = prof_pair(ctx, &e0, &e1);
     const dim3 grid(a.ranges, groups);
-#define MH_WALK(ITV)                                                                   \
-  if (staged)                                                                          \
-    hipExtLaunchKernelGGL(k_walk_tiles<ITV, true>, grid, dim3(WT_THREADS), lds_al, st,  \
-                          e0, e1, 0, a);                                               \
-  else                                                                                 \
-    hipExtLaunchKernelGGL(k_walk_tiles<ITV, false>, grid, dim3(WT_THREADS), lds_al, st, \
+#define MH_WALK2(ITV, GIV)                                                                  \
+  if (staged)                                                                               \
+    hipExtLaunchKernelGGL(k_walk_tiles<ITV, GIV, true>, grid, dim3(WT_THREADS), lds_al, st,  \
+                          e0, e1, 0, a);                                                    \
+  else                                                                                      \
+    hipExtLaunchKernelGGL(k_walk_tiles<ITV, GIV, false>, grid, dim3(WT_THREADS), lds_al, st, \
                           e0, e1, 0, a);
+#define MH_WALK(ITV)    \
+  if (GI == 8) {        \
+    MH_WALK2(ITV, 8)    \
+  } else {              \
+    MH_WALK2(ITV, 4)    \
+  }
     if (IT == 4) {
       MH_WALK(4)
     } else if (IT == 2) {
@@ -740,6 +745,7 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
       MH_WALK(1)
     }
 #undef MH_WALK
+#undef MH_WALK2
     MH_LAUNCHED(ctx, "k_walk_tiles");
     if (timed) ctx->prof_launches += 1;
     ctx->prof_evals += (uint64_t)n_sub * P;
@@ -747,11 +753,11 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   if (P > 0) {
     k_epilogue_leaves<<<P, EPI_THREADS, 0, st>>>(leafcnt, feat, P, D, K, n_min, alpha, out);
     MH_LAUNCHED(ctx, "k_epilogue_leaves");
-    // (it read and cleared every count of the P trees)
-    if (own) {
-      ctx->walk_zero = leafcnt;
-      ctx->walk_zero_bytes = cells * 4;
-    }
+  }
+  // (the epilogue read and cleared every count of the P trees)
+  if (own && P > 0) {
+    ctx->walk_zero = leafcnt;
+    ctx->walk_zero_bytes = bytes;
   }
   return MH_OK;
 }

@@ -102,6 +102,9 @@ struct Ctx {
   // into it needs no clearing launch
   const void *walk_zero = nullptr;
   size_t walk_zero_bytes = 0;
+  // LDS bytes per block of the walk kernel (MHDEOCT_WALK_LDS; 0 = a third of
+  // the CU's LDS, at least 48 KiB)
+  size_t walk_lds = 0;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);
@@ -285,8 +288,9 @@ mh_status launch_fitness_jobs(Ctx *ctx, uint32_t D, uint32_t waves, uint32_t F_m
                               const FitJob *jobs, const uint16_t *job_of, uint32_t n_blocks);
 // Direct per-sample walk for any depth (1..10): one tree at a time, leaf
 // counts per (tree, leaf, class), then the same epilogue.
-// leafcnt: P * 2^D * K u32 of device scratch the call may use (null: the
-// context arena's).
+// leafcnt: walk_scratch_bytes(P, D, K) of device scratch the call may use
+// (null: the context arena's): the leaf counts.
+size_t walk_scratch_bytes(uint32_t P, uint32_t D, uint32_t K);
 mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                               uint32_t n_sub, const uint8_t *feat, const uint32_t *tau,
                               uint32_t P, uint32_t D, uint32_t n_min, double alpha,
