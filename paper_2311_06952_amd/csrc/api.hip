@@ -528,6 +528,7 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
     c->c.persist_blocks_per_cu = (uint32_t)std::max(1, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_RANK_COOP")) c->c.rank_coop = atoi(v) != 0;
   if (const char *v = std::getenv("MHDEOCT_DEBUG")) c->c.debug = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_WALK_IT")) c->c.walk_it = (uint32_t)std::max(0, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_WALK_LDS"))
     c->c.walk_lds = atoi(v) > 0 ? (size_t)std::min(std::max(atoi(v), 8192), 150 * 1024) : 0;
   if (const char *v = std::getenv("MHDEOCT_COOP_LAUNCH")) c->c.coop_api = atoi(v) != 0;

@@ -690,6 +690,7 @@ mh_status launch_fitness_walk(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
     const bool staged = (size_t)F * WT_THREADS * 4 <= 48 * 1024;
     uint32_t IT = 4;
     while (IT > 1 && (size_t)F * WT_THREADS * IT * 4 > 16 * 1024) IT /= 2;
+    if (ctx->walk_it == 1 || ctx->walk_it == 2 || ctx->walk_it == 4) IT = ctx->walk_it;
     a.T = WT_THREADS * IT;
     const size_t tile_bytes = (staged ? (size_t)F * a.T * 4 : 0) + a.T;
     const size_t tree_nodes = (size_t)SB * 8, tree_hist = (size_t)SL * K * 4;

@@ -105,6 +105,9 @@ struct Ctx {
   // LDS bytes per block of the walk kernel (MHDEOCT_WALK_LDS; 0 = a third of
   // the CU's LDS, at least 48 KiB)
   size_t walk_lds = 0;
+  // samples per thread of the walk kernel (MHDEOCT_WALK_IT: 1, 2 or 4; 0 = by
+  // the tile size)
+  uint32_t walk_it = 0;
 };
 // 64 pinned host words of the context, or nullptr (error set).
 uint32_t *host_words(Ctx *ctx);

@@ -16,10 +16,14 @@
 //   flags every position whose value differs from its predecessor, counts the
 //   flags per block, and after a barrier writes each sample's rank (the
 //   flags up to it, minus one) and each feature's distinct-value count.
-// * separate launches (any size): all F columns sorted together by the
-//   composite key (feature << 32 | value bits) with the sample as payload,
-//   by a stable LSD radix sort (8 bits per pass), then distinct-key flags, an
-//   inclusive scan, and the rank scatter.
+// * separate launches (any size): feature f's (value bits << 32 | sample)
+//   pairs form segment f of one array, transposed from X through LDS.  Four
+//   stable LSD radix passes of 8 bits sort every segment: per pass a
+//   histogram launch (block digit counts, digit-major per feature), one
+//   exclusive scan over them all (feature f's part starts at f n, the first
+//   position of its segment), and a scatter launch in which a block sorts its
+//   pairs by digit in LDS and writes each digit's run contiguously.  Then
+//   distinct-value flags, an inclusive scan, and the rank scatter.
 #include "device_common.h"
 #include "grid_sync.h"
 #include "internal.h"
@@ -179,46 +183,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// rank encoding
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t orderable_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  if (x == 0.0f) u = 0u;  // -0 == +0
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__global__ void k_rank_keys(const float *__restrict__ X, uint32_t n, uint32_t F,
-                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                            uint32_t *__restrict__ nan_flag) {
-  uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (uint64_t)n * F) return;
-  uint32_t f = (uint32_t)(e / n), i = (uint32_t)(e % n);
-  float x = X[(size_t)i * F + f];
-  if (x != x) atomicOr(nan_flag, 1u);
-  keys[e] = ((uint64_t)f << 32) | orderable_bits(x);
-  vals[e] = i;
-}
-
-__global__ void k_rank_flags(const uint64_t *__restrict__ keys, uint32_t total,
-                             uint32_t *__restrict__ flags) {
-  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= total) return;
-  flags[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1u : 0u;
-}
-
-__global__ void k_rank_write(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ U,
-                             uint32_t n, uint32_t total, uint32_t ld, uint32_t *__restrict__ ranks,
-                             uint32_t *__restrict__ n_unique) {
-  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= total) return;
-  uint32_t f = j / n;
-  uint32_t first = U[f * n];
-  ranks[(size_t)f * ld + vals[j]] = U[j] - first;
-  if (j == f * n + n - 1) n_unique[f] = U[j] - first + 1u;
-}
-
-
-// ---------------------------------------------------------------------------
 // cooperative form
 // ---------------------------------------------------------------------------
 constexpr uint32_t RC_THREADS = 256;
@@ -275,6 +239,175 @@ __device__ __forceinline__ uint32_t rc_block_exscan(uint32_t v, uint32_t *tmp, u
   __syncthreads();
   *total = all;
   return before + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// separate launches, per-feature segments
+// ---------------------------------------------------------------------------
+constexpr uint32_t SG_THREADS = 256;
+constexpr uint32_t SG_ITEMS = 16;                  // pairs per thread
+constexpr uint32_t SG_R = SG_THREADS * SG_ITEMS;   // positions per block
+constexpr uint32_t SG_WSPAN = SG_R / (SG_THREADS / 64);  // positions per wave
+
+// Pairs of rows [r0, r0 + rows) for every feature: the rows come in
+// coalesced (row-major X) into LDS, padded to F + 1 words per row, and each
+// feature's run of positions f n + r0 .. goes out contiguously.
+__global__ __launch_bounds__(SG_THREADS) void k_seg_keys(const float *__restrict__ X, uint32_t n,
+                                                         uint32_t F, uint32_t rows,
+                                                         uint64_t *__restrict__ out,
+                                                         uint32_t *__restrict__ nan_flag) {
+  extern __shared__ __align__(16) uint32_t sk[];
+  const uint32_t r0 = blockIdx.x * rows;
+  const uint32_t cnt = min(rows, n - r0);
+  bool nan = false;
+  for (uint32_t e = threadIdx.x; e < cnt * F; e += SG_THREADS) {
+    const float x = X[(size_t)r0 * F + e];
+    nan |= x != x;
+    uint32_t u = __float_as_uint(x);
+    if (x == 0.0f) u = 0u;  // -0 == +0
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    sk[(e / F) * (F + 1) + e % F] = u;
+  }
+  if (__ballot(nan) && (threadIdx.x & 63u) == 0) atomicOr(nan_flag, 1u);
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < cnt * F; e += SG_THREADS) {
+    const uint32_t f = e / cnt, r = e % cnt;
+    out[(size_t)f * n + r0 + r] = ((uint64_t)sk[r * (F + 1) + f] << 32) | (uint64_t)(r0 + r);
+  }
+}
+
+// Digit counts of block (f, j): positions [j SG_R, (j + 1) SG_R) of segment f,
+// into hist[(f 256 + digit) nbf + j].
+__global__ __launch_bounds__(SG_THREADS) void k_seg_hist(const uint64_t *__restrict__ src,
+                                                         uint32_t n, uint32_t nbf, uint32_t shift,
+                                                         uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[SG_THREADS / 64][256];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t lo = j * SG_R, hi = min(n, lo + SG_R);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) h[w][q * 64 + lane] = 0;
+  __syncthreads();
+  const uint64_t *seg = src + (size_t)f * n;
+  uint32_t d[SG_ITEMS];
+#pragma unroll
+  for (uint32_t k = 0; k < SG_ITEMS; ++k) {
+    const uint32_t q = lo + k * SG_THREADS + threadIdx.x;
+    d[k] = q < hi ? (uint32_t)(seg[q] >> shift) & 0xFFu : 256u;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < SG_ITEMS; ++k)
+    if (d[k] < 256u) atomicAdd(&h[w][d[k]], 1u);
+  __syncthreads();
+  uint32_t t = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < SG_THREADS / 64; ++q) t += h[q][threadIdx.x];
+  hist[((size_t)f * 256 + threadIdx.x) * nbf + j] = t;
+}
+
+// Block (f, j) of a pass: its pairs (wave w holds the span of SG_WSPAN
+// positions w SG_WSPAN ..., 64 at a time in registers) stably sorted by digit
+// into LDS (a wave's digit counts and their offsets in the block's order,
+// then each pair's rank among the earlier pairs of its wave with the same
+// digit by ballot match), and written out: digit d's run goes to offs[(f 256
+// + d) nbf + j], the global position the scan gave it.
+__global__ __launch_bounds__(SG_THREADS) void k_seg_scatter(const uint64_t *__restrict__ src,
+                                                            uint64_t *__restrict__ dst,
+                                                            uint32_t n, uint32_t nbf,
+                                                            uint32_t shift,
+                                                            const uint32_t *__restrict__ offs) {
+  __shared__ uint64_t kv[SG_R];
+  __shared__ uint32_t wc[SG_THREADS / 64][256];
+  __shared__ uint32_t gpos[256];
+  __shared__ uint32_t tmp[SG_THREADS / 64 + 1];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t lo = j * SG_R, cnt = min(n - lo, SG_R);
+  const uint64_t *seg = src + (size_t)f * n + lo;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  constexpr uint32_t RND = SG_WSPAN / 64;
+  uint64_t v[RND];
+  uint32_t d[RND];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) wc[w][k * 64 + lane] = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k) {
+    const uint32_t q = w * SG_WSPAN + k * 64 + lane;
+    v[k] = q < cnt ? seg[q] : 0ull;
+    d[k] = q < cnt ? (uint32_t)(v[k] >> shift) & 0xFFu : 256u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k)
+    if (d[k] < 256u) atomicAdd(&wc[w][d[k]], 1u);
+  __syncthreads();
+  // block order: digit-major, then wave; wc[w][d] becomes wave w's first slot
+  // of digit d, gpos[d] the global position of the block's slot 0 of digit d
+  {
+    uint32_t c[SG_THREADS / 64], tot = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < SG_THREADS / 64; ++q) {
+      c[q] = wc[q][threadIdx.x];
+      tot += c[q];
+    }
+    uint32_t all;
+    const uint32_t start = rc_block_exscan(tot, tmp, &all);
+    uint32_t run = start;
+#pragma unroll
+    for (uint32_t q = 0; q < SG_THREADS / 64; ++q) {
+      wc[q][threadIdx.x] = run;
+      run += c[q];
+    }
+    gpos[threadIdx.x] = offs[((size_t)f * 256 + threadIdx.x) * nbf + j] - start;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k) {
+    const bool valid = d[k] < 256u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (uint32_t bit = 0; bit < 8; ++bit) {
+      const bool on = (d[k] >> bit) & 1u;
+      const uint64_t bal = __ballot(on);
+      peers &= on ? bal : ~bal;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t slot = valid ? wc[w][d[k]] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      kv[slot + below] = v[k];
+      if (below == 0) wc[w][d[k]] = slot + (uint32_t)__popcll(peers);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < cnt; q += SG_THREADS) {
+    const uint64_t x = kv[q];
+    dst[gpos[(uint32_t)(x >> shift) & 0xFFu] + q] = x;
+  }
+}
+
+// Distinct-value flags of the sorted segments: position p starts a value when
+// it is its segment's first or its value bits differ from position p - 1's.
+__global__ void k_seg_flags(const uint64_t *__restrict__ src, uint32_t n, uint32_t total,
+                            uint32_t *__restrict__ flags) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  flags[p] = (p % n == 0 || (uint32_t)(src[p] >> 32) != (uint32_t)(src[p - 1] >> 32)) ? 1u : 0u;
+}
+
+// rank = distinct values up to and including the position, minus the count
+// before the segment's first position (U inclusive scan of the flags).
+__global__ void k_seg_rank_write(const uint64_t *__restrict__ src, const uint32_t *__restrict__ U,
+                                 uint32_t n, uint32_t total, uint32_t ld,
+                                 uint32_t *__restrict__ ranks, uint32_t *__restrict__ n_unique) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const uint32_t f = p / n;
+  const uint32_t first = U[(size_t)f * n];
+  const uint32_t i = (uint32_t)src[p];
+  ranks[(size_t)f * ld + i] = U[p] - first;
+  if (p == f * n + n - 1) n_unique[f] = U[p] - first + 1u;
 }
 
 __global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
@@ -594,26 +727,34 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
   if (!done) {
     uint64_t *ka = (uint64_t *)arena_get(ctx, "re_keys_a", (size_t)total * 8);
     uint64_t *kb = (uint64_t *)arena_get(ctx, "re_keys_b", (size_t)total * 8);
-    uint32_t *va = (uint32_t *)arena_get(ctx, "re_vals_a", (size_t)total * 4);
-    uint32_t *vb = (uint32_t *)arena_get(ctx, "re_vals_b", (size_t)total * 4);
+    const uint32_t nbf = (n + SG_R - 1) / SG_R, nh = F * 256 * nbf;
+    uint32_t *hist = (uint32_t *)arena_get(ctx, "re_seg_hist", (size_t)nh * 4);
     uint32_t *flags = (uint32_t *)arena_get(ctx, "re_flags", (size_t)total * 4 + 256);
-    if (!ka || !kb || !va || !vb || !flags) return MH_ENOMEM;
-    uint32_t blocks = (total + 255) / 256;
-    k_rank_keys<<<blocks, 256, 0, st>>>(X, n, F, ka, va, nan_flag);
-    MH_LAUNCHED(ctx, "k_rank_keys");
-    uint32_t fbits = 32;
-    while ((1u << (fbits - 32)) < F && fbits < 40) fbits += 1;  // bits for the feature id
-    uint32_t key_bits = ((fbits + 7) / 8) * 8;
-    uint64_t *keys = ka;
-    uint32_t *vals = va;
-    mh_status s = radix_sort_pairs(ctx, &keys, &vals, kb, vb, total, key_bits);
+    if (!ka || !kb || !hist || !flags) return MH_ENOMEM;
+    // rows per transposing block: an LDS tile of rows x (F + 1) words
+    const uint32_t rows = std::max(1u, std::min(256u, (uint32_t)(16384u / (F + 1u))));
+    const uint32_t kblocks = (n + rows - 1) / rows;
+    k_seg_keys<<<kblocks, SG_THREADS, (size_t)rows * (F + 1) * 4, st>>>(X, n, F, rows, ka,
+                                                                        nan_flag);
+    MH_LAUNCHED(ctx, "k_seg_keys");
+    uint64_t *a = ka, *b = kb;
+    for (uint32_t pass = 0; pass < 4; ++pass) {
+      const uint32_t shift = 32 + 8 * pass;
+      k_seg_hist<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, shift, hist);
+      MH_LAUNCHED(ctx, "k_seg_hist");
+      mh_status s = scan_u32(ctx, hist, hist, nh, false);
+      if (s) return s;
+      k_seg_scatter<<<F * nbf, SG_THREADS, 0, st>>>(a, b, n, nbf, shift, hist);
+      MH_LAUNCHED(ctx, "k_seg_scatter");
+      std::swap(a, b);
+    }
+    const uint32_t blocks = (total + 255) / 256;
+    k_seg_flags<<<blocks, 256, 0, st>>>(a, n, total, flags);
+    MH_LAUNCHED(ctx, "k_seg_flags");
+    mh_status s = scan_u32(ctx, flags, flags, total, true);
     if (s) return s;
-    k_rank_flags<<<blocks, 256, 0, st>>>(keys, total, flags);
-    MH_LAUNCHED(ctx, "k_rank_flags");
-    s = scan_u32(ctx, flags, flags, total, true);
-    if (s) return s;
-    k_rank_write<<<blocks, 256, 0, st>>>(vals, flags, n, total, ld, ranks, n_unique);
-    MH_LAUNCHED(ctx, "k_rank_write");
+    k_seg_rank_write<<<blocks, 256, 0, st>>>(a, flags, n, total, ld, ranks, n_unique);
+    MH_LAUNCHED(ctx, "k_seg_rank_write");
   }
   if (nan_out) return MH_OK;
   uint32_t *h = host_words(ctx);
