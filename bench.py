@@ -343,6 +343,136 @@ def serving(mh, count=96, seed=11, n_hi=1e7, slots=64):
     }
 
 
+def _gen_request(torch, q, stream):
+    """One request's dataset generated on the device on `stream` (torch's
+    Philox generator seeded with the request's seed): K class means ~ N(0,
+    2I), y uniform, x ~ N(mu_y, I).  Returns (X, y, event recorded after)."""
+    with torch.cuda.stream(stream):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(q.seed)
+        mu = torch.randn((q.K, q.F), generator=g, device="cuda") * (2.0 ** 0.5)
+        y = torch.randint(q.K, (q.n,), generator=g, device="cuda")
+        X = (mu[y] + torch.randn((q.n, q.F), generator=g, device="cuda")).contiguous()
+        y8 = y.to(torch.uint8)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+    return X, y8, ev
+
+
+def serving_full(mh, count=2000, seed=21, rates=(0.5, 0.8, 1.2), slots=64):
+    """The served configuration at its stated size: `count` requests (n
+    log-uniform in [1e3, 1e7], F 4..32, K 2..10, D 2..4, P = 128, G = 100),
+    each request's data generated on the device when it is submitted (on a
+    stream of its own, which the solving stream waits for).  Forms: (1) one
+    request after another with subtree_solve (the plain form); (2) the server
+    fed as fast as it admits (at most 2 x slots waiting: its capacity); (3)
+    Poisson arrivals at each of `rates` x that capacity (latency from arrival
+    to the result).  Then the moving-horizon run on n = 10^7, F = 8, K = 2,
+    depth 8, horizon 3, batched and node by node."""
+    import torch
+    from paper_2311_06952_amd import capi, synth
+    reqs = synth.request_stream(seed, count, 1.0, n_hi=1e7)
+    evals = sum(q.n * q.P * (q.G + 1) for q in reqs)
+    prm = [mh.de_params(q.P, q.G, 0.5, 0.9, 5000 + q.rid) for q in reqs]
+    gen_stream = torch.cuda.Stream()
+    out = {"workload": f"{count} requests, n log-uniform [1e3, 1e7], F 4..32, K 2..10, D 2..4, "
+                       f"P 128, G 100; data generated on the device at submit time",
+           "evals": evals}
+
+    # (1) plain
+    run_stream = torch.cuda.Stream()
+    ctx = capi.Context(0, stream=run_stream)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, p in zip(reqs, prm):
+        X, y, ev = _gen_request(torch, q, gen_stream)
+        run_stream.wait_event(ev)
+        X.record_stream(run_stream)  # freed only after the solving stream is done with it
+        y.record_stream(run_stream)
+        if q.rid % 250 == 0:
+            print(f"serving_full: plain, request {q.rid}", file=sys.stderr, flush=True)
+        with torch.cuda.stream(run_stream):
+            ranks, nu = mh.rank_encode(X, ctx, status=status)
+            mh.subtree_solve(mh.Dataset(ranks, y, nu, q.n, q.F, q.K, status), q.D, p, ctx=ctx)
+        del X, y, ranks, nu
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ctx.close()
+    out["plain"] = {"s": t_plain, "evals_per_s": evals / t_plain, "solves_per_s": count / t_plain}
+
+    budget = 96 << 30
+
+    def run(arrivals, max_wait=None):
+        srv_stream = torch.cuda.Stream()
+        sctx = capi.Context(0, stream=srv_stream)
+        srv = mh.Server(budget, slots, ctx=sctx)
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns()
+        nxt, done, queued = 0, [], 0
+        while len(done) < count:
+            now = time.monotonic_ns() - t0
+            while nxt < count and (arrivals is None or arrivals[nxt] <= now) and \
+                    (max_wait is None or queued < max_wait):
+                q = reqs[nxt]
+                X, y, ev = _gen_request(torch, q, gen_stream)
+                srv_stream.wait_event(ev)
+                srv.submit(q.rid, X, y, q.K, q.D, prm[nxt])
+                nxt += 1
+                queued += 1
+                if nxt % 250 == 0:
+                    print(f"serving_full: served, {nxt} submitted, {len(done)} done",
+                          file=sys.stderr, flush=True)
+            act, queued = srv.pump(1)
+            done += srv.poll(256)
+            if act == 0 and queued == 0 and nxt < count and arrivals is not None:
+                time.sleep(max(0.0, (arrivals[nxt] - (time.monotonic_ns() - t0)) * 1e-9))
+        el = (time.monotonic_ns() - t0) * 1e-9
+        srv.close()
+        sctx.close()
+        arr = arrivals if arrivals is not None else [0] * count
+        lat = sorted((r["t_done_ns"] - (t0 + arr[r["req_id"]])) * 1e-6 for r in done)
+        bad = [r["req_id"] for r in done if r["status"] != 0]
+        pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100 * (len(lat) - 1))))]
+        return el, {"p50_ms": pct(50), "p99_ms": pct(99), "max_ms": lat[-1]}, bad
+
+    el_c, _, bad = run(None, max_wait=2 * slots)
+    cap = count / el_c
+    out["server"] = {"hbm_budget_bytes": budget, "max_slots": slots}
+    out["served_capacity"] = {"s": el_c, "evals_per_s": evals / el_c, "solves_per_s": cap}
+    out["failed"] = bad
+    out["poisson"] = []
+    for f in rates:
+        rate = f * cap
+        arr = [int(q.arrival / rate * 1e9) for q in reqs]   # the unit-rate stream rescaled
+        el, lat, bad = run(arr)
+        out["poisson"].append({"load": f, "rate_per_s": rate, "s": el,
+                               "evals_per_s": evals / el, "solves_per_s": count / el, **lat})
+        out["failed"] += bad
+    # the moving-horizon run of the served configuration
+    print("serving_full: moving horizon", file=sys.stderr, flush=True)
+    w = synth.served_mh(1)
+    ctx = mh.default_context(0)
+    ds = mh.dataset(w.X, w.y, w.K, ctx=ctx)
+    p = mh.de_params(w.P, w.G, w.M, w.CR, 1001)
+    mhr = {"workload": w.name}
+    trees = {}
+    for name, batched in (("batched", True), ("sequential", False)):
+        mh.mh_train(ds, w.D, w.D_MH, p, batched=batched, ctx=ctx)
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trees[name] = mh.mh_train(ds, w.D, w.D_MH, p, batched=batched, ctx=ctx)
+        el = time.perf_counter() - t0
+        st = ctx.stats(reset=True)
+        mhr[name] = {"s": el, "evals": int(st["evals"]), "evals_per_s": st["evals"] / el}
+    mhr["same_tree"] = bool(all((trees["batched"][k] == trees["sequential"][k]).all()
+                                for k in ("feat", "tau", "label")))
+    mhr["correct"] = trees["batched"]["correct"]
+    out["moving_horizon"] = mhr
+    return out
+
+
 def moving_horizon(mh, ctx):
     """Moving-horizon training of a depth-8 tree with horizon 3 on n = 10^6,
     F = 20, K = 3 (P = 128, G = 100): the level-batched form against the
@@ -477,6 +607,9 @@ def main():
                     help="only the alpha sweep with validation")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps DEOCT runs (for counter runs)")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="only the served configuration at its stated size (2,000 requests at "
+                         "three loads, and the 10^7-sample moving-horizon run)")
     ap.add_argument("--workload", default="plain_large", choices=("plain_large", "plain_scale"),
                     help="workload of --kernel-only")
     ap.add_argument("--gens", type=int, default=10,
@@ -488,6 +621,10 @@ def main():
 
     if args.kernel_only:
         kernel_only(args)
+        return
+    if args.serving_full:
+        import paper_2311_06952_amd as mh
+        print(json.dumps({"serving_full": serving_full(mh)}), flush=True)
         return
     if args.extra_only:
         import paper_2311_06952_amd as mh

@@ -150,6 +150,15 @@ def batched_mh(seed: int = 1, n: int = 1_000_000) -> Workload:
     return Workload("batched_mh_n1M_F20_K3_D8_H3_P128_G100", X, y, 3, 8, 128, 100, D_MH=3)
 
 
+def served_mh(seed: int = 1, n: int = 10_000_000) -> Workload:
+    """The served configuration's moving-horizon run: n = 10,000,000, F = 8
+    Gaussian-mixture features, K = 2; final depth 8, horizon 3, P = 128, 100
+    generations."""
+    rng = _rng(seed)
+    X, y = gaussian_mixture(rng, n, 8, 2)
+    return Workload("served_mh_n10M_F8_K2_D8_H3_P128_G100", X, y, 2, 8, 128, 100, D_MH=3)
+
+
 def random_small(seed: int, n: int, F: int, K: int, levels: int | None = None,
                  dtype=np.float32) -> tuple[np.ndarray, np.ndarray]:
     """Small test data.  With `levels`, feature values are drawn from
