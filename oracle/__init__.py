@@ -112,10 +112,15 @@ def _load():
     lib.oracle_tree_encode.restype = None
     lib.oracle_mh_train.argtypes = [_u32p, C.c_size_t, _u32p, C.c_uint32, _u8p,
                                     C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
-                                    C.POINTER(DEParams), _u8p, _u32p, _u8p,
+                                    C.POINTER(DEParams), C.c_uint32, _u8p, _u32p, _u8p,
                                     C.POINTER(C.c_uint32), C.POINTER(C.c_double)]
+    lib.oracle_subtree.argtypes = [_u8p, _u32p, C.c_uint32, C.c_uint32, C.c_uint32, _u8p,
+                                   _u32p]
+    lib.oracle_cart.argtypes = [_u32p, C.c_size_t, _u32p, C.c_uint32, _u8p, C.c_uint32, V,
+                                C.c_uint32, C.c_uint32, _u8p, _u32p]
     for name in ("oracle_rank_encode", "oracle_fitness", "oracle_split1", "oracle_opt2",
-                 "oracle_greedy_tree", "oracle_deoct", "oracle_mh_train"):
+                 "oracle_greedy_tree", "oracle_deoct", "oracle_mh_train", "oracle_cart",
+                 "oracle_subtree"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -257,6 +262,30 @@ def opt2(ds: Dataset, idx=None):
     return int(c.value), feat, tau
 
 
+def cart(ds: Dataset, D: int, idx=None):
+    """CART of depth D (Gini, reading R15) on the samples idx (all if None):
+    (feat [SB], tau [SB])."""
+    SB = (1 << D) - 1
+    idx, idx_p = _idx_arg(idx)
+    n_sub = ds.n if idx is None else len(idx)
+    feat = np.zeros(SB, dtype=np.uint8)
+    tau = np.zeros(SB, dtype=np.uint32)
+    _check(_load().oracle_cart(ds.ranks, ds.n, ds.n_unique, ds.F, ds.labels, ds.K, idx_p, n_sub,
+                               D, feat, tau), "cart")
+    return feat, tau
+
+
+def subtree(feat, tau, D: int, t: int, De: int):
+    """The depth-De subtree rooted at heap node t (1-based) of a depth-D
+    tree: (feat [2^De - 1], tau [2^De - 1])."""
+    SBe = (1 << De) - 1
+    sf = np.zeros(SBe, dtype=np.uint8)
+    st = np.zeros(SBe, dtype=np.uint32)
+    _load().oracle_subtree(np.ascontiguousarray(feat, dtype=np.uint8),
+                           np.ascontiguousarray(tau, dtype=np.uint32), D, t, De, sf, st)
+    return sf, st
+
+
 def greedy_tree(ds: Dataset, D: int, n_min: int = 1):
     SB = (1 << D) - 1
     feat = np.zeros(SB, dtype=np.uint8)
@@ -354,9 +383,13 @@ def deoct(ds: Dataset, D: int, prm: DEParams, idx=None, warm=None, prob: int = 0
     return out
 
 
-def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParams):
-    """Algorithm 2 (sequential, node by node).  Returns a dict with the tree,
-    leaf labels, correct and cost."""
+MH_WS_CART, MH_WS_DEOCT, MH_WS_DEOCT_CART = 2, 4, 8
+
+
+def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParams, flags: int = 0):
+    """Algorithm 2 (sequential, node by node), with the warm starts of `flags`
+    (MH_WS_CART, MH_WS_DEOCT, MH_WS_DEOCT_CART).  Returns a dict with the
+    tree, leaf labels, correct and cost."""
     SB = (1 << D) - 1
     feat = np.zeros(SB, dtype=np.uint8)
     tau = np.zeros(SB, dtype=np.uint32)
@@ -364,8 +397,8 @@ def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParams):
     correct = C.c_uint32()
     cost = C.c_double()
     _check(_load().oracle_mh_train(ds.ranks, ds.n, ds.n_unique, ds.F, ds.labels, ds.K, ds.n,
-                                   D, D_MH, C.byref(prm), feat, tau, label, C.byref(correct),
-                                   C.byref(cost)), "mh_train")
+                                   D, D_MH, C.byref(prm), flags, feat, tau, label,
+                                   C.byref(correct), C.byref(cost)), "mh_train")
     return dict(feat=feat, tau=tau, label=label, correct=int(correct.value),
                 cost=float(cost.value))
 

@@ -453,6 +453,129 @@ int oracle_greedy_tree(const uint32_t *ranks, size_t ld,
 }
 
 /* ------------------------------------------------------------------------ */
+/* CART, the warm start of Algorithm 2 (the CART solution of a moving-      */
+/* horizon subtree) and of the plain DEOCT runs of Section 4.  The paper    */
+/* names the CART package it uses, not the impurity; reading R15: Gini.     */
+/* Top down in heap order, each node u on its subset S: when S holds more   */
+/* than one class and some threshold sends samples both ways, u takes the   */
+/* first strict maximum, over features f = 1..F and thresholds              */
+/* tau = 1..n_f - 1 with both sides non-empty, of the Gini score            */
+/*   g = sum_k L_k^2 / |L| + sum_k R_k^2 / |R|                               */
+/* (|S| minus the children's weighted Gini impurity), in float64 as         */
+/* (double)A / (double)|L| + (double)B / (double)|R| with A and B the       */
+/* integer sums of squares.  Otherwise u gets no split (every sample goes   */
+/* right, so its right child sees the same subset).                         */
+/* ------------------------------------------------------------------------ */
+static int or_cart_split(const uint32_t *ranks, size_t ld, const uint32_t *n_unique,
+                         uint32_t F, const uint8_t *labels, uint32_t K, const uint32_t *S,
+                         uint32_t nS, uint8_t *f_out, uint32_t *t_out) {
+  *f_out = 0;
+  *t_out = 0;
+  uint32_t *tot = (uint32_t *)calloc(K, sizeof(uint32_t));
+  uint32_t *left = (uint32_t *)calloc(K, sizeof(uint32_t));
+  if (!tot || !left) {
+    free(tot);
+    free(left);
+    return OR_ENOMEM;
+  }
+  for (uint32_t j = 0; j < nS; ++j) tot[labels[S[j]]] += 1;
+  uint32_t classes = 0;
+  for (uint32_t k = 0; k < K; ++k) classes += tot[k] ? 1u : 0u;
+  double best = -1.0;
+  for (uint32_t f = 1; f <= F && classes > 1; ++f) {
+    uint32_t nf = n_unique[f - 1];
+    if (nf < 2) continue;
+    uint32_t *hist = (uint32_t *)calloc((size_t)nf * K, sizeof(uint32_t));
+    if (!hist) {
+      free(tot);
+      free(left);
+      return OR_ENOMEM;
+    }
+    for (uint32_t j = 0; j < nS; ++j) {
+      uint32_t i = S[j];
+      hist[(size_t)ranks[(size_t)(f - 1) * ld + i] * K + labels[i]] += 1;
+    }
+    memset(left, 0, sizeof(uint32_t) * K);
+    uint32_t nL = 0;
+    for (uint32_t th = 1; th < nf; ++th) {
+      for (uint32_t k = 0; k < K; ++k) {
+        left[k] += hist[(size_t)(th - 1) * K + k];
+        nL += hist[(size_t)(th - 1) * K + k];
+      }
+      uint32_t nR = nS - nL;
+      if (nL == 0 || nR == 0) continue;
+      uint64_t A = 0, B = 0;
+      for (uint32_t k = 0; k < K; ++k) {
+        uint64_t l = left[k], r = tot[k] - left[k];
+        A += l * l;
+        B += r * r;
+      }
+      double g = (double)A / (double)nL + (double)B / (double)nR;
+      if (g > best) {
+        best = g;
+        *f_out = (uint8_t)f;
+        *t_out = th;
+      }
+    }
+    free(hist);
+  }
+  free(tot);
+  free(left);
+  return OR_OK;
+}
+
+static int or_cart_rec(const uint32_t *ranks, size_t ld, const uint32_t *n_unique, uint32_t F,
+                       const uint8_t *labels, uint32_t K, uint32_t *S, uint32_t nS, uint32_t u,
+                       uint32_t depth, uint32_t D, uint8_t *feat, uint32_t *tau) {
+  if (depth == D) return OR_OK;
+  uint8_t f = 0;
+  uint32_t th = 0;
+  int rc = or_cart_split(ranks, ld, n_unique, F, labels, K, S, nS, &f, &th);
+  if (rc) return rc;
+  feat[u - 1] = f;
+  tau[u - 1] = th;
+  uint32_t *A = (uint32_t *)malloc(sizeof(uint32_t) * (nS ? nS : 1));
+  uint32_t *B = (uint32_t *)malloc(sizeof(uint32_t) * (nS ? nS : 1));
+  if (!A || !B) {
+    free(A);
+    free(B);
+    return OR_ENOMEM;
+  }
+  uint32_t na = 0, nb = 0;
+  for (uint32_t j = 0; j < nS; ++j) {
+    uint32_t i = S[j];
+    if (f != 0 && ranks[(size_t)(f - 1) * ld + i] < th)
+      A[na++] = i;
+    else
+      B[nb++] = i;
+  }
+  rc = or_cart_rec(ranks, ld, n_unique, F, labels, K, A, na, 2 * u, depth + 1, D, feat, tau);
+  if (!rc)
+    rc = or_cart_rec(ranks, ld, n_unique, F, labels, K, B, nb, 2 * u + 1, depth + 1, D, feat,
+                     tau);
+  free(A);
+  free(B);
+  return rc;
+}
+
+/* The CART tree of depth D on the samples idx[0..n_sub) (all n if idx is
+ * NULL): feat / tau [2^D - 1]. */
+int oracle_cart(const uint32_t *ranks, size_t ld, const uint32_t *n_unique, uint32_t F,
+                const uint8_t *labels, uint32_t K, const uint32_t *idx, uint32_t n_sub,
+                uint32_t D, uint8_t *feat, uint32_t *tau) {
+  if (D < 1 || D > 10 || K < 1) return OR_EINVAL;
+  uint32_t SB = (1u << D) - 1u;
+  memset(feat, 0, SB);
+  memset(tau, 0, sizeof(uint32_t) * SB);
+  uint32_t *S = (uint32_t *)malloc(sizeof(uint32_t) * (n_sub ? n_sub : 1));
+  if (!S) return OR_ENOMEM;
+  for (uint32_t j = 0; j < n_sub; ++j) S[j] = idx ? idx[j] : j;
+  int rc = or_cart_rec(ranks, ld, n_unique, F, labels, K, S, n_sub, 1, 0, D, feat, tau);
+  free(S);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Differential evolution for OCT (Section 2 eqs. mutation / crossover /    */
 /* selection; Section 3.3; Algorithm 4; reading R8).                         */
 /* ------------------------------------------------------------------------ */
@@ -639,9 +762,40 @@ done:
 /* no-warm-start variant).  Leaf labels come from the final tree over all   */
 /* training samples.                                                         */
 /* ------------------------------------------------------------------------ */
+void oracle_tree_encode(const uint8_t *feat, const uint32_t *tau, uint32_t P, uint32_t D,
+                        uint32_t F, const uint32_t *n_unique, double *genes);
+
+/* The subtree of depth De rooted at heap node t of a depth-D tree (the
+ * shape and location a moving-horizon subproblem at t covers): subtree node
+ * u at depth k of the subtree (2^k <= u < 2^(k+1)) is tree node
+ * t 2^k + (u - 2^k).  Subtree nodes below the tree's last split level get
+ * no split. */
+void oracle_subtree(const uint8_t *feat, const uint32_t *tau, uint32_t D, uint32_t t,
+                    uint32_t De, uint8_t *sf, uint32_t *st) {
+  uint32_t SB = (1u << D) - 1u, SBe = (1u << De) - 1u;
+  for (uint32_t u = 1; u <= SBe; ++u) {
+    uint32_t k = 0;
+    while ((2u << k) <= u) k += 1u;
+    uint64_t v = ((uint64_t)t << k) + (u - (1u << k));
+    sf[u - 1] = v <= SB ? feat[v - 1] : 0;
+    st[u - 1] = v <= SB ? tau[v - 1] : 0;
+  }
+}
+
+/* Warm starts of the moving horizon (Algorithm 2's warm-start branch and
+ * the variants of Section 4's ablation), bits of `flags`:
+ *   2 (CART)        the CART tree of each DE-solved node's subtree, on the
+ *                   node's subset, is added to its DEOCT warm starts;
+ *   4 (DEOCT)       a DEOCT run on the whole tree (depth D, all samples,
+ *                   problem id 0) gives warm-start trees: node t's DEOCT gets
+ *                   the run's subtree with the same shape and location;
+ *   8 (DEOCT_CART)  that whole-tree run is itself warm-started with the
+ *                   CART tree of depth D.
+ * A node's warm starts come in the order of Algorithm 2: the retrieved
+ * subtree first, then the CART solution. */
 int oracle_mh_train(const uint32_t *ranks, size_t ld, const uint32_t *n_unique,
                     uint32_t F, const uint8_t *labels, uint32_t K, uint32_t n,
-                    uint32_t D, uint32_t D_MH, const oracle_de_params *prm,
+                    uint32_t D, uint32_t D_MH, const oracle_de_params *prm, uint32_t flags,
                     uint8_t *feat, uint32_t *tau, uint8_t *label_out,
                     uint32_t *correct_out, double *cost_out) {
   if (D < 1 || D > 10 || D_MH < 1) return OR_EINVAL;
@@ -651,6 +805,30 @@ int oracle_mh_train(const uint32_t *ranks, size_t ld, const uint32_t *n_unique,
   memset(feat, 0, SB);
   memset(tau, 0, sizeof(uint32_t) * SB);
   int rc = OR_OK;
+  /* the whole-tree DEOCT warm-start tree */
+  uint8_t wf[1023];
+  uint32_t wt[1023];
+  if (flags & 4u) {
+    double wg[2 * 1023];
+    uint32_t Wd = 0;
+    if (flags & 8u) {
+      uint8_t cf[1023];
+      uint32_t ct[1023];
+      rc = oracle_cart(ranks, ld, n_unique, F, labels, K, NULL, n, D, cf, ct);
+      if (rc) {
+        free(S);
+        return rc;
+      }
+      oracle_tree_encode(cf, ct, 1, D, F, n_unique, wg);
+      Wd = 1;
+    }
+    rc = oracle_deoct(ranks, ld, n_unique, F, labels, K, NULL, n, D, prm, Wd ? wg : NULL, Wd, 0,
+                      NULL, wf, wt, NULL, NULL, NULL, NULL, NULL);
+    if (rc) {
+      free(S);
+      return rc;
+    }
+  }
   for (uint32_t t = 1; t <= SB && rc == OR_OK; ++t) {
     uint32_t dt = 0;
     while ((2u << dt) <= t) dt += 1u; /* depth of node t: floor(log2 t) */
@@ -673,8 +851,23 @@ int oracle_mh_train(const uint32_t *ranks, size_t ld, const uint32_t *n_unique,
       if (De != 1) {
         uint8_t sf[1023];
         uint32_t st[1023];
+        /* warm starts: the whole-tree run's subtree at t (node u of depth k
+         * of the subtree is node t 2^k + u - 2^k of the tree), then CART */
+        uint32_t SBe = (1u << De) - 1u, W = 0;
+        double warm[2 * 2 * 1023];
+        if (flags & 4u) {
+          oracle_subtree(wf, wt, D, t, De, sf, st);
+          oracle_tree_encode(sf, st, 1, De, F, n_unique, warm + (size_t)W * 2 * SBe);
+          W += 1;
+        }
+        if (flags & 2u) {
+          rc = oracle_cart(ranks, ld, n_unique, F, labels, K, S, nS, De, sf, st);
+          if (rc) break;
+          oracle_tree_encode(sf, st, 1, De, F, n_unique, warm + (size_t)W * 2 * SBe);
+          W += 1;
+        }
         rc = oracle_deoct(ranks, ld, n_unique, F, labels, K, S, nS, De, prm,
-                          NULL, 0, (uint64_t)t, NULL, sf, st, NULL, NULL, NULL,
+                          W ? warm : NULL, W, (uint64_t)t, NULL, sf, st, NULL, NULL, NULL,
                           NULL, NULL);
         feat[t - 1] = sf[0];
         tau[t - 1] = st[0];
