@@ -296,13 +296,24 @@ mh_status mh_autotune(mh_ctx *ctx, const mh_dataset *ds, uint32_t D,
 
 #define MH_SEQUENTIAL 0u  /* node by node in heap order, as in Algorithm 2 */
 #define MH_BATCHED 1u     /* every node of a level in one batched launch */
+/* Warm starts of the subtree solves (Algorithm 2's warm-start branch; the
+ * warm-start factors of Section 4's ablation table), OR-ed into flags: */
+#define MH_WS_CART 2u       /* the CART subtree (cart_tree) of the node's subset */
+#define MH_WS_DEOCT 4u      /* the subtree at the node's location of a DEOCT
+                               run on the whole tree (depth D, all samples,
+                               problem id 0) made before the first level */
+#define MH_WS_DEOCT_CART 8u /* that whole-tree run warm-started with the
+                               depth-D CART tree; needs MH_WS_DEOCT */
 
 /* Trains a depth-D tree node by node: each branch node whose subset has
  * more than n_min samples and more than one class gets the first node of a
  * DEOCT subtree of depth min(D_MH, D - depth(t)) (problem id t), or the
  * exact best depth-1 split when that depth is 1; other nodes get no split.
- * The batched form solves all nodes of a level together and returns the
- * identical tree.  Fills *out (host).  Synchronises. */
+ * A subtree solve's warm starts, by the MH_WS_* bits of flags, come in the
+ * order: whole-tree run's subtree, then CART subtree.  The batched form
+ * solves all nodes of a level together and returns the identical tree.
+ * Fills *out (host).  Synchronises.  MH_EINVAL for unknown flags or
+ * MH_WS_DEOCT_CART without MH_WS_DEOCT. */
 mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
                    const mh_de_params *prm, uint32_t flags, mh_tree *out);
 
@@ -312,6 +323,19 @@ mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
  * feat/tau/correct to host.  Synchronises. */
 mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                  uint32_t n_sub, uint8_t *feat, uint32_t *tau, uint32_t *correct);
+
+/* CART of depth D with the Gini impurity (Breiman et al., the method the
+ * paper's DEOCT and MH-DEOCT take warm starts from; Section 4, Algorithm 2)
+ * on the samples idx[0..n_sub) (device, distinct indices < n; all of ds
+ * when idx is NULL and n_sub == n).  Top down in heap order a node whose
+ * subset holds two or more classes takes the first strict maximum, over
+ * features 1..F and thresholds 1..n_f-1 ascending that send samples both
+ * ways, of sum_k L_k^2/|L| + sum_k R_k^2/|R| in float64 (each division and
+ * the sum correctly rounded); other nodes get no split (feat = tau = 0).
+ * Writes feat [2^D - 1] and tau [2^D - 1] to HOST memory the caller owns.
+ * Synchronises.  MH_EINVAL for bad sizes or null pointers. */
+mh_status cart_tree(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
+                    uint32_t n_sub, uint32_t D, uint8_t *feat, uint32_t *tau);
 
 /* ---------------------------------------------------------------------- */
 /* Applying a trained tree to held-out samples (Section 2 split rule with   */

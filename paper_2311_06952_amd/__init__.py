@@ -6,12 +6,13 @@ The computation lives in the HIP library ``libmhdeoct.so`` (C ABI in
 binding, with torch used only for device memory and streams.
 :mod:`paper_2311_06952_amd.synth` generates seeded synthetic inputs.
 """
-from .capi import (Context, Dataset, MhError, Server, TileSet, autotune, dataset,  # noqa
+from .capi import (Context, Dataset, MhError, Server, TileSet, autotune, cart, dataset,  # noqa
                    de_init, de_params, de_step, default_context, fitness_eval, load_library,
                    mh_train, predict, rank_encode, server_footprint, split1, subtree_solve,
                    tree_decode, tree_encode, tree_thresholds)
 
-__all__ = ["Context", "Dataset", "MhError", "Server", "TileSet", "autotune", "dataset", "de_init",
+__all__ = ["Context", "Dataset", "MhError", "Server", "TileSet", "autotune", "cart", "dataset",
+           "de_init",
            "de_params", "de_step", "default_context", "fitness_eval", "load_library", "mh_train",
            "predict", "rank_encode", "server_footprint", "split1", "subtree_solve", "tree_decode",
            "tree_encode", "tree_thresholds"]

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libmhdeoct.so")
 MH_OK, MH_EINVAL, MH_ENOMEM, MH_EDEVICE, MH_EBUSY, MH_ECANCELED = 0, -1, -2, -3, -4, -5
 MH_MAX_DEPTH = 10
 MH_SEQUENTIAL, MH_BATCHED = 0, 1
+MH_WS_CART, MH_WS_DEOCT, MH_WS_DEOCT_CART = 2, 4, 8
 
 # Every entry point the header declares (checked by the CPU test suite).
 EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh_ctx_profile",
@@ -29,7 +30,7 @@ EXPORTS = ("mh_version", "mh_ctx_create", "mh_ctx_destroy", "mh_last_error", "mh
            "mh_train", "split1", "mh_server_create", "mh_server_destroy", "mh_server_submit",
            "mh_server_footprint", "mh_server_pump", "mh_server_poll", "mh_autotune",
            "mh_tree_thresholds", "mh_predict", "tree_encode", "subtree_solve_pop",
-           "mh_server_set_limits", "mh_server_cancel", "fitness_eval_static")
+           "mh_server_set_limits", "mh_server_cancel", "fitness_eval_static", "cart_tree")
 
 
 class MhError(RuntimeError):
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH):
                       C.POINTER(TreeC)], I32),
         "split1": ([V, C.POINTER(DatasetC), V, U32, C.POINTER(C.c_uint8), C.POINTER(U32),
                     C.POINTER(U32)], I32),
+        "cart_tree": ([V, C.POINTER(DatasetC), V, U32, U32, V, V], I32),
         "mh_server_create": ([V, U64, U32, C.POINTER(V)], I32),
         "mh_server_destroy": ([V], None),
         "mh_server_submit": ([V, U64, V, V, U32, U32, U32, U32, C.POINTER(DEParamsC)], I32),
@@ -500,13 +502,29 @@ def autotune(ds: Dataset, D: int, prm: DEParamsC, generations: int = 20,
 
 
 def mh_train(ds: Dataset, D: int, D_MH: int, prm: DEParamsC, batched: bool = False,
-             ctx: Context | None = None) -> dict:
+             ctx: Context | None = None, warm: int = 0) -> dict:
+    """Moving-horizon DEOCT; warm: MH_WS_* bits (warm starts of the subtree
+    solves)."""
     ctx = ctx or default_context()
     out = TreeC()
     dsc = ds.cstruct()
-    ctx.check(ctx.lib.mh_train(ctx.h, C.byref(dsc), D, D_MH, C.byref(prm),
-                               MH_BATCHED if batched else MH_SEQUENTIAL, C.byref(out)))
+    flags = (MH_BATCHED if batched else MH_SEQUENTIAL) | int(warm)
+    ctx.check(ctx.lib.mh_train(ctx.h, C.byref(dsc), D, D_MH, C.byref(prm), flags, C.byref(out)))
     return _tree_dict(out)
+
+
+def cart(ds: Dataset, D: int, idx=None, ctx: Context | None = None):
+    """CART (Gini) of depth D on the samples idx (device tensor, all if None):
+    (feat [2^D - 1] uint8, tau [2^D - 1] uint32) numpy arrays."""
+    ctx = ctx or default_context()
+    n_sub = ds.n if idx is None else int(idx.numel())
+    SB = (1 << D) - 1
+    feat = np.zeros(SB, dtype=np.uint8)
+    tau = np.zeros(SB, dtype=np.uint32)
+    dsc = ds.cstruct()
+    ctx.check(ctx.lib.cart_tree(ctx.h, C.byref(dsc), _ptr(idx), n_sub, D,
+                                C.c_void_p(feat.ctypes.data), C.c_void_p(tau.ctypes.data)))
+    return feat, tau
 
 
 def split1(ds: Dataset, idx=None, ctx: Context | None = None):

@@ -326,7 +326,8 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
   if (W > 0) {
     warm = (double *)arena_get(ctx, "ss_warm", (size_t)W * m * 8);
     if (!warm) return MH_ENOMEM;
-    MH_HIP(ctx, hipMemcpyAsync(warm, warm_host, (size_t)W * m * 8, hipMemcpyHostToDevice, st));
+    // host genes from the C ABI; device genes from the moving horizon
+    MH_HIP(ctx, hipMemcpyAsync(warm, warm_host, (size_t)W * m * 8, hipMemcpyDefault, st));
   }
   if (!pop || !trial || !cost || !tcost || !feat || !tau || !best || !f1 || !t1 || !lab1 ||
       !corr1 || !cost1)
@@ -461,7 +462,8 @@ static mh_status deoct(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint
 // Sequential moving-horizon step: DEOCT on the samples at node t, problem id
 // t; returns the root of the best subtree.
 static mh_status solve_node(Ctx *ctx, const mh_dataset *ds, const uint32_t *node_of, uint32_t t,
-                            uint32_t De, const mh_de_params *prm, uint8_t *feat, uint32_t *tau) {
+                            uint32_t De, const mh_de_params *prm, const double *warm, uint32_t W,
+                            uint8_t *feat, uint32_t *tau) {
   uint32_t *idx = (uint32_t *)arena_get(ctx, "mh_idx", (size_t)(ds->n ? ds->n : 1) * 4);
   uint32_t *cursor = nullptr;
   if (!idx) return MH_ENOMEM;
@@ -472,11 +474,16 @@ static mh_status solve_node(Ctx *ctx, const mh_dataset *ds, const uint32_t *node
   MH_HIP(ctx, hipMemcpyAsync(&n_t, cursor, 4, hipMemcpyDeviceToHost, ctx->stream));
   MH_HIP(ctx, hipStreamSynchronize(ctx->stream));
   mh_tree tr;
-  s = deoct(ctx, ds, idx, n_t, De, prm, nullptr, 0, t, &tr);
+  s = deoct(ctx, ds, idx, n_t, De, prm, warm, W, t, &tr);
   if (s) return s;
   *feat = tr.feat[0];
   *tau = tr.tau[0];
   return MH_OK;
+}
+
+static mh_status solve_all(Ctx *ctx, const mh_dataset *ds, uint32_t D, const mh_de_params *prm,
+                           const double *warm, uint32_t W, mh_tree *out) {
+  return deoct(ctx, ds, nullptr, ds->n, D, prm, warm, W, 0, out);
 }
 
 }  // namespace mh
@@ -898,12 +905,15 @@ mh_status mh_train(mh_ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
   if (s) return s;
   if (!out) return fail(c, MH_EINVAL, "out is null");
   if (D_MH < 1) return fail(c, MH_EINVAL, "D_MH must be >= 1");
-  if (flags & ~MH_BATCHED) return fail(c, MH_EINVAL, "unknown flags");
+  if (flags & ~(MH_BATCHED | MH_WS_CART | MH_WS_DEOCT | MH_WS_DEOCT_CART))
+    return fail(c, MH_EINVAL, "unknown flags");
+  if ((flags & MH_WS_DEOCT_CART) && !(flags & MH_WS_DEOCT))
+    return fail(c, MH_EINVAL, "MH_WS_DEOCT_CART needs MH_WS_DEOCT");
   if ((flags & MH_BATCHED) && (std::min(D_MH, D) > 5 || ds->F > 80))
     return fail(c, MH_EINVAL, "the batched form needs subtree depth <= 5 and F <= 80");
   s = check_ds_status(c, ds);
   if (s) return s;
-  return mh_train_impl(c, ds, D, D_MH, prm, flags, out, solve_node);
+  return mh_train_impl(c, ds, D, D_MH, prm, flags, out, solve_node, solve_all);
 }
 
 mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
@@ -915,6 +925,20 @@ mh_status split1(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_
   if (!feat || !tau || !correct) return fail(c, MH_EINVAL, "null output");
   if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
   return split1_subset(c, ds, idx, n_sub, feat, tau, correct);
+}
+
+mh_status cart_tree(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                    uint32_t D, uint8_t *feat, uint32_t *tau) {
+  CTX_OR_FAIL(ctx);
+  Ctx *c = &ctx->c;
+  mh_status s = check_dataset(c, ds);
+  if (s) return s;
+  if (D < 1 || D > MH_MAX_DEPTH) return fail(c, MH_EINVAL, "D must be in 1..10");
+  if (!feat || !tau) return fail(c, MH_EINVAL, "null output");
+  if (!idx && n_sub > ds->n) return fail(c, MH_EINVAL, "n_sub > n without idx");
+  s = check_ds_status(c, ds);
+  if (s) return s;
+  return cart_subset(c, ds, idx, n_sub, D, feat, tau);
 }
 
 }  // extern "C"

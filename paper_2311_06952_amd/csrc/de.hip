@@ -36,7 +36,7 @@ __global__ void k_de_init(uint32_t P, uint32_t SB, uint32_t F, uint64_t seed,
   const uint32_t sub = (uint32_t)(e / ((uint64_t)m * P));
   double v;
   if (r < W) {
-    v = warm[(size_t)r * m + q];
+    v = warm[((size_t)sub * W + r) * m + q];  // each problem's own warm starts
   } else {
     const uint64_t key = de_key(seed, prob_of(prob_ids, prob_base, sub));
     const double u = to_unit(de_draw(key, 0, r, q));

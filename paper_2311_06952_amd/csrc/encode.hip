@@ -32,6 +32,18 @@ __global__ __launch_bounds__(256) void k_tree_encode(const uint8_t *__restrict__
 }
 
 }  // namespace
+
+mh_status launch_tree_encode(Ctx *ctx, const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                             uint32_t D, uint32_t F, const uint32_t *n_unique, double *genes) {
+  const uint32_t SB = (1u << D) - 1u;
+  const uint64_t total = (uint64_t)P * SB;
+  if (total == 0) return MH_OK;
+  k_tree_encode<<<(uint32_t)((total + 255) / 256), 256, 0, ctx->stream>>>(feat, tau, P, SB, F,
+                                                                            n_unique, genes);
+  MH_LAUNCHED(ctx, "k_tree_encode");
+  return MH_OK;
+}
+
 }  // namespace mh
 
 using namespace mh;
@@ -47,11 +59,7 @@ extern "C" mh_status tree_encode(mh_ctx *ctx, const uint8_t *feat, const uint32_
   if (F == 0 || F > MH_MAX_FEATURES) return fail(c, MH_EINVAL, "F must be in 1..255");
   if (P == 0) return MH_OK;
   if (!feat || !tau || !n_unique || !genes) return fail(c, MH_EINVAL, "null pointer");
-  const uint32_t SB = (1u << D) - 1u;
-  const uint64_t total = (uint64_t)P * SB;
+  const uint64_t total = (uint64_t)P * ((1u << D) - 1u);
   if (total > (1ull << 31)) return fail(c, MH_EINVAL, "P * (2^D - 1) must be <= 2^31");
-  k_tree_encode<<<(uint32_t)((total + 255) / 256), 256, 0, c->stream>>>(feat, tau, P, SB, F,
-                                                                          n_unique, genes);
-  MH_LAUNCHED(c, "k_tree_encode");
-  return MH_OK;
+  return launch_tree_encode(c, feat, tau, P, D, F, n_unique, genes);
 }

@@ -427,19 +427,29 @@ mh_status launch_deoct_persist_multi(Ctx *ctx, const void *tiles, uint32_t F, ui
 // Exact best depth-1 split (Algorithm 2, horizon-1 branch) of every subset
 // {i : sub_of[i] == s}, s < nsub (samples with sub_of >= nsub are ignored;
 // sub_of == nullptr puts every sample in subset 0).  tot: device [nsub][K]
-// class totals of the subsets.  Writes feat/tau/correct (device, [nsub]).
+// class totals of the subsets.  Writes feat/tau/correct (device, [nsub];
+// correct may be null).  gini: CART's Gini split instead (correct gets 0).
 mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
-                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct);
+                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct,
+                        bool gini = false);
 // DEOCT for n_problems subproblems at once (problem ids prob_ids, device),
 // samples assigned by sub_of (device [n], >= n_problems = not in any).
 // Writes the decoded best tree of each problem to feat_out/tau_out (device,
 // [n_problems][SB]) and its cost to cost_out (device [n_problems]).
 // class_counts (HOST [n_problems][K], may be null) lets the whole run go to
 // one cooperative launch.
+// warm: device [n_problems][W][2 SB] warm-start genes (W may be 0).
 mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
                         uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
                         const mh_de_params *prm, const uint32_t *class_counts,
-                        uint8_t *feat_out, uint32_t *tau_out);
+                        const double *warm, uint32_t W, uint8_t *feat_out, uint32_t *tau_out);
+// CART (Gini) of depth D on each subset {i : sub_of[i] == s}, s < nsub:
+// feat / tau device [nsub][2^D - 1].  cart_subset: one explicit subset, host
+// outputs, synchronises.
+mh_status cart_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
+                       uint32_t D, uint8_t *feat, uint32_t *tau);
+mh_status cart_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                      uint32_t D, uint8_t *feat, uint32_t *tau);
 
 // Sequential-form helpers: the samples at node t (device idx, atomics
 // order), the exact split of an explicit subset (host outputs), and the
@@ -447,11 +457,17 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
 mh_status launch_compact(Ctx *ctx, const uint32_t *node_of, uint32_t n, uint32_t t, uint32_t *idx);
 mh_status split1_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
                         uint8_t *feat, uint32_t *tau, uint32_t *correct);
+typedef mh_status (*SolveNodeFn)(Ctx *, const mh_dataset *, const uint32_t *node_of, uint32_t t,
+                                 uint32_t De, const mh_de_params *, const double *warm,
+                                 uint32_t W, uint8_t *feat, uint32_t *tau);
+typedef mh_status (*SolveAllFn)(Ctx *, const mh_dataset *, uint32_t D, const mh_de_params *,
+                                const double *warm, uint32_t W, mh_tree *out);
 mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
                         const mh_de_params *prm, uint32_t flags, mh_tree *out,
-                        mh_status (*solve_one)(Ctx *, const mh_dataset *, const uint32_t *,
-                                               uint32_t, uint32_t, const mh_de_params *,
-                                               uint8_t *, uint32_t *));
+                        SolveNodeFn solve_one, SolveAllFn solve_all);
+// encode.hip: P trees (device [P][SB]) into genes (device [P][2 SB]).
+mh_status launch_tree_encode(Ctx *ctx, const uint8_t *feat, const uint32_t *tau, uint32_t P,
+                             uint32_t D, uint32_t F, const uint32_t *n_unique, double *genes);
 
 }  // namespace mh
 

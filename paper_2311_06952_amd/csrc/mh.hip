@@ -84,6 +84,13 @@ __global__ void k_route_level(uint32_t *__restrict__ node_of, uint32_t n, uint32
 // strict maximum in the order (no split, then feature, then tau): the largest
 // correct count, ties to the smallest (feature, tau), and no split unless a
 // split is strictly better.
+//
+// The same machinery gives CART's split (Gini impurity): the candidate's
+// score is sum_k L_k^2 / |L| + sum_k R_k^2 / |R| in f64 (the integer sums of
+// squares divided by the side sizes, then added, each correctly rounded), the
+// winner the first strict maximum over (feature, tau); a subset splits iff it
+// holds two or more classes and has a candidate.  Scores are positive, so
+// their bit patterns order as u64.
 // ---------------------------------------------------------------------------
 __global__ void k_split_keys(const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
                              const uint32_t *__restrict__ ranks, uint32_t ld, uint32_t F,
@@ -132,17 +139,35 @@ __device__ __forceinline__ uint32_t split_correct(const uint32_t *__restrict__ p
   return ml + mr;
 }
 
-// pass 1: the best correct count per subset (atomicMax over candidates).
+__device__ __forceinline__ uint64_t split_gini_bits(const uint32_t *__restrict__ pk, uint32_t N,
+                                                    uint32_t K, uint32_t lo, uint32_t j,
+                                                    uint32_t hi) {
+  uint64_t A = 0, B = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t *p = pk + (size_t)k * N;
+    const uint32_t base = lo ? p[lo - 1] : 0u;
+    const uint64_t L = p[j] - base, R = p[hi] - base - (uint32_t)L;
+    A += L * L;
+    B += R * R;
+  }
+  const double g = __dadd_rn(__ddiv_rn((double)A, (double)(j + 1 - lo)),
+                             __ddiv_rn((double)B, (double)(hi - j)));
+  return (uint64_t)__double_as_longlong(g);
+}
+
+// pass 1: the best score per subset (atomicMax over candidates): the correct
+// count (GINI false) or the Gini score's bits (GINI true).
 // pass 2: the smallest (feature + 1, tau) among candidates attaining it.
+template <bool GINI>
 __global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
                              const uint32_t *__restrict__ pk, uint32_t K,
                              const uint32_t *__restrict__ seg_lo, const uint32_t *__restrict__ seg_hi,
-                             uint32_t fbits, uint32_t pass, uint32_t *__restrict__ best_c,
+                             uint32_t fbits, uint32_t pass, unsigned long long *__restrict__ best_c,
                              unsigned long long *__restrict__ best_ft) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   bool cand = false;
-  uint32_t s = 0xFFFFFFFFu, c = 0;
-  uint64_t ft = ~0ull;
+  uint32_t s = 0xFFFFFFFFu;
+  uint64_t c = 0, ft = ~0ull;
   if (j < N) {
     const uint64_t key = keys[j];
     const uint64_t sid = key >> 32;
@@ -151,7 +176,8 @@ __global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
     // a boundary: the rank changes between j and j + 1 inside the segment
     if (j != hi && (keys[j + 1] & 0xFFFFFFFFull) != (key & 0xFFFFFFFFull)) {
       const uint32_t f = (uint32_t)(sid & ((1u << fbits) - 1u));
-      c = split_correct(pk, N, K, seg_lo[sid], j, hi);
+      c = GINI ? split_gini_bits(pk, N, K, seg_lo[sid], j, hi)
+               : (uint64_t)split_correct(pk, N, K, seg_lo[sid], j, hi);
       ft = ((uint64_t)(f + 1) << 32) | ((key & 0xFFFFFFFFull) + 1);
       cand = pass == 0 || c == best_c[s];
     }
@@ -161,51 +187,57 @@ __global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
   const bool uniform = __ballot(j < N && s != s0) == 0ull;
   const bool any_cand = __ballot(cand) != 0ull;
   if (uniform) {
-    uint32_t vc = cand ? c : 0u;
+    uint64_t vc = cand ? c : 0u;
     uint64_t vf = cand ? ft : ~0ull;
     for (int d = 32; d > 0; d >>= 1) {
-      const uint32_t oc = __shfl_xor(vc, d, 64);
+      const uint64_t oc = __shfl_xor(vc, d, 64);
       const uint64_t of = __shfl_xor(vf, d, 64);
       vc = oc > vc ? oc : vc;
       vf = of < vf ? of : vf;
     }
     if ((threadIdx.x & 63u) == 0 && s0 != 0xFFFFFFFFu && any_cand) {
-      if (pass == 0) atomicMax(&best_c[s0], vc);
+      if (pass == 0) atomicMax(&best_c[s0], (unsigned long long)vc);
       else atomicMin(&best_ft[s0], (unsigned long long)vf);
     }
   } else if (cand) {
-    if (pass == 0) atomicMax(&best_c[s], c);
+    if (pass == 0) atomicMax(&best_c[s], (unsigned long long)c);
     else atomicMin(&best_ft[s], (unsigned long long)ft);
   }
 }
 
 __global__ void k_split_init(const uint32_t *__restrict__ tot, uint32_t nsub, uint32_t K,
-                             uint32_t *__restrict__ best_c, unsigned long long *__restrict__ best_ft) {
+                             uint32_t gini, unsigned long long *__restrict__ best_c,
+                             unsigned long long *__restrict__ best_ft) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsub) return;
   uint32_t m = 0;
-  for (uint32_t k = 0; k < K; ++k) m = tot[s * K + k] > m ? tot[s * K + k] : m;
-  best_c[s] = m;            // no split
-  best_ft[s] = ~0ull;       // no split unless a split is strictly better
+  for (uint32_t k = 0; k < K; ++k) m = tot[(size_t)s * K + k] > m ? tot[(size_t)s * K + k] : m;
+  best_c[s] = gini ? 0ull : m;  // no split (misclassification) / no candidate (Gini)
+  best_ft[s] = ~0ull;           // no split unless a split is strictly better
 }
 
 __global__ void k_split_final(const uint32_t *__restrict__ tot, uint32_t nsub, uint32_t K,
-                              const uint32_t *__restrict__ best_c,
+                              uint32_t gini, const unsigned long long *__restrict__ best_c,
                               const unsigned long long *__restrict__ best_ft, uint8_t *__restrict__ feat,
                               uint32_t *__restrict__ tau, uint32_t *__restrict__ correct) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsub) return;
-  uint32_t m = 0;
-  for (uint32_t k = 0; k < K; ++k) m = tot[s * K + k] > m ? tot[s * K + k] : m;
+  uint32_t m = 0, classes = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t v = tot[(size_t)s * K + k];
+    m = v > m ? v : m;
+    classes += v ? 1u : 0u;
+  }
   const uint64_t ft = best_ft[s];
-  if (best_c[s] > m && ft != ~0ull) {
+  const bool split = gini ? (classes > 1 && ft != ~0ull) : (best_c[s] > m && ft != ~0ull);
+  if (split) {
     feat[s] = (uint8_t)(ft >> 32);
     tau[s] = (uint32_t)ft;
   } else {
     feat[s] = 0;
     tau[s] = 0;
   }
-  correct[s] = best_c[s];
+  if (correct) correct[s] = gini ? 0u : (uint32_t)best_c[s];
 }
 
 // Scatter the root node of each problem's best tree into the full tree.
@@ -243,7 +275,113 @@ __global__ void k_mark_subset(const uint32_t *__restrict__ idx, uint32_t n_sub, 
   atomicAdd(&tot[labels[i]], 1u);
 }
 
+// ---------------------------------------------------------------------------
+// CART of depth D on each of nsub subsets at once, level by level: loc[i] is
+// the node (heap numbering inside its subset's tree) sample i sits at; the
+// nodes of a level are split subproblems s = sub 2^l + (u - 2^l) of the
+// Gini split above.
+// ---------------------------------------------------------------------------
+__global__ void k_cart_sub(const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
+                           const uint32_t *__restrict__ loc, uint32_t l,
+                           uint32_t *__restrict__ sub_l) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = sub_of[i];
+  sub_l[i] = s < nsub ? (s << l) + loc[i] - (1u << l) : nsub << l;
+}
+
+__global__ void k_cart_put(const uint8_t *__restrict__ fl, const uint32_t *__restrict__ tl,
+                           uint32_t cnt, uint32_t l, uint32_t SB, uint8_t *__restrict__ feat,
+                           uint32_t *__restrict__ tau) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cnt) return;
+  const uint32_t sub = q >> l, u = (1u << l) + (q & ((1u << l) - 1u));
+  feat[(size_t)sub * SB + u - 1] = fl[q];
+  tau[(size_t)sub * SB + u - 1] = tl[q];
+}
+
+__global__ void k_cart_route(const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
+                             uint32_t *__restrict__ loc, uint32_t l,
+                             const uint8_t *__restrict__ fl, const uint32_t *__restrict__ tl,
+                             const uint32_t *__restrict__ ranks, uint32_t ld, uint32_t F) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = sub_of[i];
+  if (s >= nsub) return;
+  const uint32_t u = loc[i], q = (s << l) + u - (1u << l);
+  const uint32_t f = fl[q];
+  const bool left = f != 0 && f <= F && ranks[(size_t)(f - 1) * ld + i] < tl[q];
+  loc[i] = left ? 2 * u : 2 * u + 1;
+}
+
 }  // namespace
+
+mh_status cart_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
+                       uint32_t D, uint8_t *feat, uint32_t *tau) {
+  hipStream_t st = ctx->stream;
+  const uint32_t n = ds->n, K = ds->K, SB = (1u << D) - 1u;
+  if (nsub == 0) return MH_OK;
+  const size_t maxq = (size_t)nsub << (D - 1);
+  uint32_t *loc = (uint32_t *)arena_get(ctx, "ct_loc", (size_t)(n ? n : 1) * 4);
+  uint32_t *sub_l = (uint32_t *)arena_get(ctx, "ct_sub", (size_t)(n ? n : 1) * 4);
+  uint32_t *hist = (uint32_t *)arena_get(ctx, "ct_hist", maxq * K * 4);
+  uint8_t *fl = (uint8_t *)arena_get(ctx, "ct_f", maxq);
+  uint32_t *tl = (uint32_t *)arena_get(ctx, "ct_t", maxq * 4);
+  if (!loc || !sub_l || !hist || !fl || !tl) return MH_ENOMEM;
+  if (maxq > 0xFFFFFFFFull / 2) return fail(ctx, MH_EINVAL, "CART: too many subsets");
+  if (n) {
+    k_fill_u32<<<nblk(n), 256, 0, st>>>(loc, n, 1u);
+    MH_LAUNCHED(ctx, "k_fill_u32");
+  }
+  for (uint32_t l = 0; l < D; ++l) {
+    const uint32_t cnt = nsub << l;
+    MH_HIP(ctx, hipMemsetAsync(hist, 0, (size_t)cnt * K * 4, st));
+    if (n) {
+      k_cart_sub<<<nblk(n), 256, 0, st>>>(sub_of, n, nsub, loc, l, sub_l);
+      MH_LAUNCHED(ctx, "k_cart_sub");
+      const bool in_lds = (size_t)cnt * K * 4 <= 32768;
+      k_level_hist<<<nblk(n), 256, in_lds ? (size_t)cnt * K * 4 : 0, st>>>(
+          sub_l, ds->labels, n, K, 0, cnt, hist, in_lds ? 1 : 0);
+      MH_LAUNCHED(ctx, "k_level_hist");
+    }
+    mh_status s = launch_split1(ctx, ds, sub_l, cnt, hist, fl, tl, nullptr, true);
+    if (s) return s;
+    k_cart_put<<<nblk(cnt), 256, 0, st>>>(fl, tl, cnt, l, SB, feat, tau);
+    MH_LAUNCHED(ctx, "k_cart_put");
+    if (l + 1 < D && n) {
+      k_cart_route<<<nblk(n), 256, 0, st>>>(sub_of, n, nsub, loc, l, fl, tl, ds->ranks, ds->ld,
+                                            ds->F);
+      MH_LAUNCHED(ctx, "k_cart_route");
+    }
+  }
+  return MH_OK;
+}
+
+mh_status cart_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uint32_t n_sub,
+                      uint32_t D, uint8_t *feat, uint32_t *tau) {
+  hipStream_t st = ctx->stream;
+  const uint32_t n = ds->n, SB = (1u << D) - 1u;
+  uint32_t *sub_of = (uint32_t *)arena_get(ctx, "s1_sub_of", (size_t)(n ? n : 1) * 4);
+  uint32_t *tot = (uint32_t *)arena_get(ctx, "s1_tot", (size_t)ds->K * 4);
+  uint8_t *f = (uint8_t *)arena_get(ctx, "ct_tree_f", SB);
+  uint32_t *t = (uint32_t *)arena_get(ctx, "ct_tree_t", (size_t)SB * 4);
+  if (!sub_of || !tot || !f || !t) return MH_ENOMEM;
+  MH_HIP(ctx, hipMemsetAsync(tot, 0, (size_t)ds->K * 4, st));
+  if (n) {
+    k_fill_u32<<<nblk(n), 256, 0, st>>>(sub_of, n, 1u);
+    MH_LAUNCHED(ctx, "k_fill_u32");
+  }
+  if (n_sub) {
+    k_mark_subset<<<nblk(n_sub), 256, 0, st>>>(idx, n_sub, n, ds->labels, ds->K, sub_of, tot);
+    MH_LAUNCHED(ctx, "k_mark_subset");
+  }
+  mh_status s = cart_batched(ctx, ds, sub_of, 1, D, f, t);
+  if (s) return s;
+  MH_HIP(ctx, hipMemcpyAsync(feat, f, SB, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipMemcpyAsync(tau, t, (size_t)SB * 4, hipMemcpyDeviceToHost, st));
+  MH_HIP(ctx, hipStreamSynchronize(st));
+  return MH_OK;
+}
 
 mh_status launch_compact(Ctx *ctx, const uint32_t *node_of, uint32_t n, uint32_t t, uint32_t *idx) {
   uint32_t *cursor = (uint32_t *)arena_get(ctx, "mh_cursor", 256);
@@ -285,7 +423,8 @@ mh_status split1_subset(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx, uin
 }
 
 mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, uint32_t nsub,
-                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct) {
+                        const uint32_t *tot, uint8_t *feat, uint32_t *tau, uint32_t *correct,
+                        bool gini) {
   hipStream_t st = ctx->stream;
   const uint32_t n = ds->n, F = ds->F, K = ds->K;
   uint32_t fbits = 1;
@@ -294,12 +433,14 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
   while ((1u << sbits) < nsub) ++sbits;
   if (fbits + sbits > 31) return fail(ctx, MH_EINVAL, "too many subsets for split1");
   uint32_t *cursor = (uint32_t *)arena_get(ctx, "sp_cursor", 256);
-  uint32_t *best_c = (uint32_t *)arena_get(ctx, "sp_best_c", (size_t)nsub * 4);
+  unsigned long long *best_c =
+      (unsigned long long *)arena_get(ctx, "sp_best_c", (size_t)nsub * 8);
   unsigned long long *best_ft =
       (unsigned long long *)arena_get(ctx, "sp_best_ft", (size_t)nsub * 8);
   if (!cursor || !best_c || !best_ft) return MH_ENOMEM;
   MH_HIP(ctx, hipMemsetAsync(cursor, 0, 4, st));
-  k_split_init<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, best_c, best_ft);
+  if (nsub == 0) return MH_OK;
+  k_split_init<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, gini ? 1u : 0u, best_c, best_ft);
   MH_LAUNCHED(ctx, "k_split_init");
   // elements: (member sample, feature) pairs; members counted on the host
   uint32_t members = 0;
@@ -341,12 +482,17 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
     k_split_bounds<<<nblk(N), 256, 0, st>>>(keys, N, seg_lo, seg_hi);
     MH_LAUNCHED(ctx, "k_split_bounds");
     for (uint32_t pass = 0; pass < 2; ++pass) {
-      k_split_eval<<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass, best_c,
-                                            best_ft);
+      if (gini)
+        k_split_eval<true><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass,
+                                                    best_c, best_ft);
+      else
+        k_split_eval<false><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass,
+                                                     best_c, best_ft);
       MH_LAUNCHED(ctx, "k_split_eval");
     }
   }
-  k_split_final<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, best_c, best_ft, feat, tau, correct);
+  k_split_final<<<nblk(nsub), 256, 0, st>>>(tot, nsub, K, gini ? 1u : 0u, best_c, best_ft, feat,
+                                             tau, correct);
   MH_LAUNCHED(ctx, "k_split_final");
   return MH_OK;
 }
@@ -356,7 +502,7 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
 mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
                         uint32_t n_problems, const uint64_t *prob_ids, uint32_t D,
                         const mh_de_params *prm, const uint32_t *class_counts,
-                        uint8_t *feat_out, uint32_t *tau_out) {
+                        const double *warm, uint32_t W, uint8_t *feat_out, uint32_t *tau_out) {
   const uint32_t P = prm->P, SB = (1u << D) - 1u, m = 2 * SB, K = ds->K, F = ds->F;
   if (D > 5 || F > 80) return fail(ctx, MH_EINVAL, "batched DEOCT needs depth <= 5 and F <= 80");
   hipStream_t st = ctx->stream;
@@ -377,7 +523,7 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
   const uint32_t *ctot =
       reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tiles) + h.off_ctot);
   DeDev de{P, D, F, prm->G, prm->M, prm->CR, prm->seed, ds->n_unique, true};
-  s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop, true);
+  s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, warm, W, pop, true);
   if (s) return s;
   if (class_counts && ctx->persist) {
     // every problem's whole run in one cooperative launch (a block group
@@ -399,7 +545,7 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
       // runs on the per-generation kernels from a fresh start
       coop_note_failure(ctx);
       MH_HIP(ctx, hipMemsetAsync(cnt, 0, cb, st));
-      s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, nullptr, 0, pop, true);
+      s = launch_de_init(ctx, P, D, F, prm->seed, prob_ids, 0, n_problems, warm, W, pop, true);
       if (s) return s;
     }
   }
@@ -434,17 +580,60 @@ mh_status deoct_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of,
   return launch_decode(ctx, pop, P, D, F, ds->n_unique, feat_out, tau_out, n_problems, best, true);
 }
 
-// Algorithm 2.  flags: MH_SEQUENTIAL or MH_BATCHED.
-// solve_one(ctx, ds, node_of, t, depth, prm, &feat, &tau): the root of the
-// DEOCT subtree of node t (sequential form).
+// Warm-start genes of na nodes of a level (Algorithm 2's warm-start branch):
+// per node, the whole-tree run's subtree of depth De at the node (when whole
+// is given; subtree node u at depth k is tree node t 2^k + u - 2^k) and then
+// the node's CART subtree (cf / ct, device [na][2^De - 1], when given),
+// encoded into genes (device [na][W][2 (2^De - 1)]).
+static mh_status level_warm(Ctx *ctx, const mh_dataset *ds, const uint32_t *nodes, uint32_t na,
+                            uint32_t D, uint32_t De, const mh_tree *whole, const uint8_t *cf,
+                            const uint32_t *ct, uint32_t W, double *genes) {
+  hipStream_t st = ctx->stream;
+  const uint32_t SBe = (1u << De) - 1u, SB = (1u << D) - 1u;
+  uint8_t *wf = (uint8_t *)arena_get(ctx, "mh_wf", (size_t)na * W * SBe);
+  uint32_t *wt = (uint32_t *)arena_get(ctx, "mh_wt", (size_t)na * W * SBe * 4);
+  if (!wf || !wt) return MH_ENOMEM;
+  if (whole) {
+    std::vector<uint8_t> hf((size_t)na * W * SBe, 0);
+    std::vector<uint32_t> ht((size_t)na * W * SBe, 0);
+    for (uint32_t a = 0; a < na; ++a)
+      for (uint32_t u = 1; u <= SBe; ++u) {
+        uint32_t k = 0;
+        while ((2u << k) <= u) ++k;
+        const uint64_t v = ((uint64_t)nodes[a] << k) + (u - (1u << k));
+        if (v > SB) continue;
+        hf[(size_t)a * W * SBe + u - 1] = whole->feat[v - 1];
+        ht[(size_t)a * W * SBe + u - 1] = whole->tau[v - 1];
+      }
+    MH_HIP(ctx, hipMemcpyAsync(wf, hf.data(), hf.size(), hipMemcpyHostToDevice, st));
+    MH_HIP(ctx, hipMemcpyAsync(wt, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, st));
+    MH_HIP(ctx, hipStreamSynchronize(st));  // the host vectors go out of scope
+  }
+  if (cf) {
+    const size_t w = W - 1;
+    MH_HIP(ctx, hipMemcpy2DAsync(wf + w * SBe, (size_t)W * SBe, cf, SBe, SBe, na,
+                                 hipMemcpyDeviceToDevice, st));
+    MH_HIP(ctx, hipMemcpy2DAsync(wt + w * SBe, (size_t)W * SBe * 4, ct, (size_t)SBe * 4,
+                                 (size_t)SBe * 4, na, hipMemcpyDeviceToDevice, st));
+  }
+  return launch_tree_encode(ctx, wf, wt, na * W, De, ds->F, ds->n_unique, genes);
+}
+
+// Algorithm 2.  flags: MH_SEQUENTIAL or MH_BATCHED, and the warm starts
+// MH_WS_CART, MH_WS_DEOCT, MH_WS_DEOCT_CART.
+// solve_one(ctx, ds, node_of, t, depth, prm, warm, W, &feat, &tau): the root
+// of the DEOCT subtree of node t (sequential form), warm-started with the
+// device genes warm [W][2 SB].
+// solve_all(ctx, ds, D, prm, warm, W, &tree): DEOCT of the whole tree on
+// every sample (problem id 0).
 mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_MH,
                         const mh_de_params *prm, uint32_t flags, mh_tree *out,
-                        mh_status (*solve_one)(Ctx *, const mh_dataset *, const uint32_t *,
-                                               uint32_t, uint32_t, const mh_de_params *,
-                                               uint8_t *, uint32_t *)) {
+                        SolveNodeFn solve_one, SolveAllFn solve_all) {
   hipStream_t st = ctx->stream;
   const uint32_t n = ds->n, K = ds->K, SB = (1u << D) - 1u, SL = 1u << D;
   const bool batched = (flags & MH_BATCHED) != 0;
+  const bool ws_cart = (flags & MH_WS_CART) != 0, ws_deoct = (flags & MH_WS_DEOCT) != 0;
+  const uint32_t W = (ws_cart ? 1u : 0u) + (ws_deoct ? 1u : 0u);
   uint32_t *node_of = (uint32_t *)arena_get(ctx, "mh_node_of", (size_t)(n ? n : 1) * 4);
   uint32_t *sub_of = (uint32_t *)arena_get(ctx, "mh_sub_of", (size_t)(n ? n : 1) * 4);
   uint8_t *tfeat = (uint8_t *)arena_get(ctx, "mh_feat", SB);
@@ -466,6 +655,29 @@ mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_M
   if (n) {
     k_fill_u32<<<nblk(n), 256, 0, st>>>(node_of, n, 1u);
     MH_LAUNCHED(ctx, "k_fill_u32");
+  }
+  // the whole-tree DEOCT run whose subtrees warm-start the nodes
+  mh_tree whole;
+  if (ws_deoct) {
+    const double *wg = nullptr;
+    uint32_t Wd = 0;
+    if (flags & MH_WS_DEOCT_CART) {
+      uint8_t *cf = (uint8_t *)arena_get(ctx, "mh_cf", SB);
+      uint32_t *ct = (uint32_t *)arena_get(ctx, "mh_ct", (size_t)SB * 4);
+      double *g = (double *)arena_get(ctx, "mh_wgenes", (size_t)2 * SB * 8);
+      if (!cf || !ct || !g) return MH_ENOMEM;
+      if (n) {
+        k_fill_u32<<<nblk(n), 256, 0, st>>>(sub_of, n, 0u);
+        MH_LAUNCHED(ctx, "k_fill_u32");
+      }
+      mh_status s = cart_batched(ctx, ds, sub_of, 1, D, cf, ct);
+      if (!s) s = launch_tree_encode(ctx, cf, ct, 1, D, ds->F, ds->n_unique, g);
+      if (s) return s;
+      wg = g;
+      Wd = 1;
+    }
+    mh_status s = solve_all(ctx, ds, D, prm, wg, Wd, &whole);
+    if (s) return s;
   }
   std::vector<uint32_t> hh((size_t)maxw * K);
   for (uint32_t L = 0; L < D; ++L) {
@@ -523,13 +735,49 @@ mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_M
         std::vector<uint32_t> cc((size_t)na * K);
         for (uint32_t a = 0; a < na; ++a)
           for (uint32_t k = 0; k < K; ++k) cc[(size_t)a * K + k] = hh[(size_t)(active[a] - t0) * K + k];
-        mh_status s = deoct_batched(ctx, ds, sub_of, na, pids, De, prm, cc.data(), rf, rt);
+        const uint32_t SBe = (1u << De) - 1u;
+        double *wg = nullptr;
+        if (W) {
+          uint8_t *cf = (uint8_t *)arena_get(ctx, "mh_cf", (size_t)na * SBe);
+          uint32_t *ct = (uint32_t *)arena_get(ctx, "mh_ct", (size_t)na * SBe * 4);
+          wg = (double *)arena_get(ctx, "mh_wgenes", (size_t)na * W * 2 * SBe * 8);
+          if (!cf || !ct || !wg) return MH_ENOMEM;
+          mh_status s = ws_cart ? cart_batched(ctx, ds, sub_of, na, De, cf, ct) : MH_OK;
+          if (!s)
+            s = level_warm(ctx, ds, active.data(), na, D, De, ws_deoct ? &whole : nullptr,
+                           ws_cart ? cf : nullptr, ct, W, wg);
+          if (s) return s;
+        }
+        mh_status s = deoct_batched(ctx, ds, sub_of, na, pids, De, prm, cc.data(), wg, W, rf, rt);
         if (s) return s;
       } else {
         std::vector<uint8_t> hf(na);
         std::vector<uint32_t> ht(na);
+        const uint32_t SBe = (1u << De) - 1u;
         for (uint32_t a = 0; a < na; ++a) {
-          mh_status s = solve_one(ctx, ds, node_of, active[a], De, prm, &hf[a], &ht[a]);
+          double *wg = nullptr;
+          if (W) {
+            // node t's own subset (subset 0) for its CART subtree
+            uint32_t *one = (uint32_t *)arena_get(ctx, "mh_smap1", 4);
+            uint8_t *cf = (uint8_t *)arena_get(ctx, "mh_cf", SBe);
+            uint32_t *ct = (uint32_t *)arena_get(ctx, "mh_ct", (size_t)SBe * 4);
+            wg = (double *)arena_get(ctx, "mh_wgenes", (size_t)W * 2 * SBe * 8);
+            if (!one || !cf || !ct || !wg) return MH_ENOMEM;
+            mh_status s = MH_OK;
+            if (ws_cart) {
+              MH_HIP(ctx, hipMemsetAsync(one, 0, 4, st));
+              if (n) {
+                k_assign_sub<<<nblk(n), 256, 0, st>>>(node_of, n, active[a], 1, one, 1, sub_of);
+                MH_LAUNCHED(ctx, "k_assign_sub");
+              }
+              s = cart_batched(ctx, ds, sub_of, 1, De, cf, ct);
+            }
+            if (!s)
+              s = level_warm(ctx, ds, &active[a], 1, D, De, ws_deoct ? &whole : nullptr,
+                             ws_cart ? cf : nullptr, ct, W, wg);
+            if (s) return s;
+          }
+          mh_status s = solve_one(ctx, ds, node_of, active[a], De, prm, wg, W, &hf[a], &ht[a]);
           if (s) return s;
         }
         MH_HIP(ctx, hipMemcpyAsync(rf, hf.data(), na, hipMemcpyHostToDevice, st));
