@@ -546,6 +546,91 @@ def alpha_sweep(mh, ctx, w, alphas=(0.0, 3.0, 10.0, 30.0, 100.0, 300.0, 1000.0),
     return {"depth": D, "sweep": rows, "chosen_alpha": best[1], "heldout_acc": ch / len(yh)}
 
 
+def ablation(mh, ctx, n=100_000, depths=((2, 2), (4, 3), (8, 3))):
+    """The warm-start ablation in the layout of Section 4's ablation table on
+    synthetic data: the plain-large generator (F = 32, K = 4, labels from a
+    planted depth-5 tree with 5 % flips) at 2n rows, split in half into
+    training and test rows.  Rows: 1 CART; 2-3 whole-tree DEOCT without and
+    with the CART warm start; 4-5 the same with 1,800 generations; 6-11 the
+    batched moving horizon (horizon 2 at depth 2, 3 at depths 4 and 8) with
+    the warm-start factors "CART WS in DE" (MH_WS_DEOCT_CART), "DE WS"
+    (MH_WS_DEOCT) and "CART WS" (MH_WS_CART).  DE in the paper's Normal
+    setting: P = 100, G = 600, CR = 0.1, a mutation factor drawn per
+    individual and generation.  Each timed run follows an untimed two-
+    generation run of the same configuration; times include computing the
+    warm starts."""
+    import numpy as np
+    import torch
+    from paper_2311_06952_amd import capi, synth
+    w = synth.plain_large(3, n=2 * n)
+    perm = np.random.default_rng(5).permutation(2 * n)
+    Xtr, ytr = np.ascontiguousarray(w.X[perm[:n]]), w.y[perm[:n]]
+    Xte, yte = np.ascontiguousarray(w.X[perm[n:]]), w.y[perm[n:]]
+    ds = mh.dataset(Xtr, ytr, w.K, ctx=ctx)
+    P, G, CR = 100, 600, 0.1
+    dev = torch.device("cuda", ctx.device)
+
+    def accs(tree):
+        thr = mh.tree_thresholds(ds, Xtr, tree, ctx=ctx)
+        _, ct = mh.predict(Xte, tree, thr, y=yte, ctx=ctx)
+        return tree["correct"] / n, ct / n
+
+    def cart_tree(D):
+        feat, tau = mh.cart(ds, D, ctx=ctx)
+        fd = torch.as_tensor(feat).to(dev)
+        td = torch.as_tensor(tau.view(np.int32)).to(dev)
+        _, corr, lab, cost = mh.fitness_eval(ds, fd, td, D, ctx=ctx, want_counts=False)
+        return {"D": D, "feat": feat, "tau": tau, "label": lab[0].cpu().numpy(),
+                "correct": int(corr[0].item()), "cost": float(cost[0].item())}
+
+    def deoct(D, g, ws):
+        t = None
+        if ws:
+            t = cart_tree(D)
+            genes = mh.tree_encode(t["feat"], t["tau"], D, w.F, ds.n_unique, ctx=ctx)
+            t = genes.cpu().numpy()
+        return mh.subtree_solve(ds, D, mh.de_params(P, g, -1.0, CR, 11), warm=t, ctx=ctx)
+
+    def timed(fn, warm_fn):
+        warm_fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tree = fn()
+        torch.cuda.synchronize()
+        return tree, time.perf_counter() - t0
+
+    rows = []
+
+    def add(no, method, D, tree, s):
+        tr, te = accs(tree)
+        rows.append({"no": no, "method": method, "D": D, "train_acc": tr, "test_acc": te,
+                     "s": s})
+
+    ws_rows = ((6, 0), (7, capi.MH_WS_CART), (8, capi.MH_WS_DEOCT),
+               (9, capi.MH_WS_DEOCT | capi.MH_WS_CART),
+               (10, capi.MH_WS_DEOCT_CART | capi.MH_WS_DEOCT),
+               (11, capi.MH_WS_DEOCT_CART | capi.MH_WS_DEOCT | capi.MH_WS_CART))
+    for D, H in depths:
+        tree, s = timed(lambda: cart_tree(D), lambda: cart_tree(D))
+        add(1, "CART", D, tree, s)
+        for no, g, ws in ((2, G, False), (3, G, True), (4, 3 * G, False), (5, 3 * G, True)):
+            if no >= 4 and D == 2:
+                continue
+            tree, s = timed(lambda: deoct(D, g, ws), lambda: deoct(D, 2, ws))
+            add(no, "DEOCT" + (" + CART WS" if ws else "") + (" (1800 gens)" if no >= 4 else ""),
+                D, tree, s)
+        for no, fl in ws_rows:
+            prm = mh.de_params(P, G, -1.0, CR, 11)
+            short = mh.de_params(P, 2, -1.0, CR, 11)
+            tree, s = timed(lambda: mh.mh_train(ds, D, H, prm, batched=True, ctx=ctx, warm=fl),
+                            lambda: mh.mh_train(ds, D, H, short, batched=True, ctx=ctx, warm=fl))
+            add(no, f"MH-DEOCT (horizon {H}, warm starts {fl:#x})", D, tree, s)
+        print(f"ablation: depth {D} done", file=sys.stderr, flush=True)
+    return {"workload": f"plain-large generator, {n} training + {n} test rows, F {w.F}, K {w.K}",
+            "de": {"P": P, "G": G, "CR": CR, "M": "U[0,1) per individual and generation"},
+            "rows": rows}
+
+
 def predict_bench(mh, ctx, w, Xd, yd, tree, reps=16, launches=20):
     """The trained tree on 10^6 held-out rows of the same mixture (test
     accuracy), and k_predict's duration on those rows tiled reps times
@@ -610,6 +695,8 @@ def main():
     ap.add_argument("--serving-full", action="store_true",
                     help="only the served configuration at its stated size (2,000 requests at "
                          "three loads, and the 10^7-sample moving-horizon run)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the warm-start ablation (CART, DEOCT, moving-horizon variants)")
     ap.add_argument("--workload", default="plain_large", choices=("plain_large", "plain_scale"),
                     help="workload of --kernel-only")
     ap.add_argument("--gens", type=int, default=10,
@@ -621,6 +708,10 @@ def main():
 
     if args.kernel_only:
         kernel_only(args)
+        return
+    if args.ablation:
+        import paper_2311_06952_amd as mh
+        print(json.dumps({"ablation": ablation(mh, mh.default_context(0))}), flush=True)
         return
     if args.serving_full:
         import paper_2311_06952_amd as mh

@@ -2,9 +2,24 @@
 //
 // All blocks of the barrier's group must be resident at once: the launcher
 // keeps the grid within what the device holds, with a margin, and a wait's
-// time limit turns a grid that is not resident into an error, not a hang.  Cross-block data that a barrier orders must move
-// through device-scope atomics or agent-scope loads and stores: the L2 of
-// one XCD is not coherent with the others for plain accesses.
+// time limit turns a grid that is not resident into an error, not a hang.
+//
+// Ordering.  Every datum that crosses blocks at a barrier is written with
+// agent-scope atomic stores or read-modify-writes and read with agent-scope
+// atomic loads, which the hardware performs at the point of coherence shared
+// by all XCDs (they do not stop in a CU's or an XCD's cache).  Before a block
+// arrives, each of its waves waits until its own memory operations have
+// completed (s_waitcnt 0) and the block synchronises, so the arrival is
+// issued after the block's atomics are done at that point; a waiter issues
+// its loads only after it has seen the release word and the block has
+// synchronised again, so they are served after the release.  The barrier
+// words themselves are relaxed agent-scope atomics.  Release on the arrivals
+// and an acquire fence after the wait, the language-level form of the same
+// ordering, cost an L2 write-back and invalidate at every barrier: a whole
+// DEOCT run at n = 10^5, F = 16, P = 256, depth 3 took 3.09 instead of
+// 2.14 ms, rank encoding 0.42 instead of 0.37 ms, with identical results.
+// Plain (non-atomic) memory written before a barrier must not be read by
+// another block after it.
 #pragma once
 
 #include <hip/hip_runtime.h>
