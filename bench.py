@@ -690,6 +690,8 @@ def main():
                     help="only one solve and the held-out predict measurement (for profiler runs)")
     ap.add_argument("--alpha-only", action="store_true",
                     help="only the alpha sweep with validation")
+    ap.add_argument("--deep-only", action="store_true",
+                    help="only the depth-8 whole-tree DEOCT run (for profiler runs)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a calibration copy and --steps DEOCT runs (for counter runs)")
     ap.add_argument("--serving-full", action="store_true",
@@ -731,12 +733,15 @@ def main():
 
     ctx = mh.default_context(0)
     dev = torch.device("cuda", 0)
-    if args.predict_only or args.alpha_only:
+    if args.predict_only or args.alpha_only or args.deep_only:
         w2 = synth.plain_scale(1)
         X2 = torch.as_tensor(w2.X).to(dev)
         y2 = torch.as_tensor(w2.y).to(dev)
         if args.alpha_only:
             print(json.dumps({"alpha_sweep": alpha_sweep(mh, ctx, w2)}), flush=True)
+        elif args.deep_only:
+            print(json.dumps({"deep_whole_tree": deep_whole_tree(mh, ctx, w2, X2, y2)}),
+                  flush=True)
         else:
             t = mh.subtree_solve(ds_of(mh, X2, y2, w2, ctx), w2.D,
                                  mh.de_params(w2.P, w2.G, w2.M, w2.CR, 1001), ctx=ctx)
