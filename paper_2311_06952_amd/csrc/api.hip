@@ -90,7 +90,6 @@ int coop_per_cu(Ctx *ctx, const void *kern, int threads, size_t lds) {
 
 hipError_t launch_grid_sync(Ctx *ctx, const void *kern, dim3 grid, dim3 block, void **args,
                             size_t lds) {
-  if (ctx->coop_api) return hipLaunchCooperativeKernel(kern, grid, block, args, lds, ctx->stream);
   return hipLaunchKernel(kern, grid, block, args, lds, ctx->stream);
 }
 
@@ -538,7 +537,10 @@ mh_status mh_ctx_create(int device, void *hip_stream, mh_ctx **out) {
   if (const char *v = std::getenv("MHDEOCT_WALK_IT")) c->c.walk_it = (uint32_t)std::max(0, atoi(v));
   if (const char *v = std::getenv("MHDEOCT_WALK_LDS"))
     c->c.walk_lds = atoi(v) > 0 ? (size_t)std::min(std::max(atoi(v), 8192), 150 * 1024) : 0;
-  if (const char *v = std::getenv("MHDEOCT_COOP_LAUNCH")) c->c.coop_api = atoi(v) != 0;
+  if (const char *v = std::getenv("MHDEOCT_SELECT_TPI")) {
+    const int t = atoi(v);
+    c->c.de_select_tpi = (t == 1 || t == 2 || t == 4 || t == 8) ? (uint32_t)t : 0u;
+  }
   if (const char *v = std::getenv("MHDEOCT_WAIT_TICKS"))
     c->c.wait_ticks = std::min<uint64_t>(strtoull(v, nullptr, 10), 200000000ull);
   if (const char *v = std::getenv("MHDEOCT_RANK_R")) {

@@ -97,42 +97,52 @@ __global__ __launch_bounds__(LB) void k_de_gen(StepArgs a, GenArgs e) {
 // of de_gen_body would make every individual's draws and float64 work one
 // after another on a single CU).  Same arithmetic and results.
 //
-// Part 1, thread r = individual r of problem blockIdx.y: the epilogue of the
-// evaluated population's node counts (its cost), then selection (eq.
-// selection, ties to the trial) or, in generation 0, the initial cost; the
-// consumed counters go back to zero.
+// Part 1, individual r of problem blockIdx.y on e.tpi adjacent lanes (lane j
+// of the group takes classes j, j + tpi, ... of the epilogue and genes j,
+// j + tpi, ... of the copy): the epilogue of the evaluated population's node
+// counts (its cost), then selection (eq. selection, ties to the trial) or, in
+// generation 0, the initial cost; the consumed counters go back to zero.
 constexpr uint32_t SPLIT_THREADS = 256;
 
-template <int D>
+template <int D, int TPI>
 __global__ __launch_bounds__(SPLIT_THREADS) void k_de_select(StepArgs a, GenArgs e) {
   constexpr int SB = (1 << D) - 1, m = 2 * SB;
+  constexpr uint32_t tpi = TPI;
   const uint32_t sub = blockIdx.y, P = a.P, Ppad = pad64(P), K = e.K;
-  const uint32_t r = blockIdx.x * SPLIT_THREADS + threadIdx.x;
-  if (r >= P) return;
+  const uint32_t r = (blockIdx.x * SPLIT_THREADS + threadIdx.x) / tpi, j = threadIdx.x % tpi;
+  if (r >= P) return;  // whole groups leave together
+  double *cost = a.cost + (size_t)sub * P;
+  // the parent's cost and this lane's share of the trial genes are loaded
+  // with the counts, before the selection is known, so that the step waits
+  // for memory once
+  constexpr int QM = (m + TPI - 1) / TPI;  // genes per lane
+  double v[QM];
+  double pc = 0.0;
+  if (!e.init) {
+    pc = cost[r];
+    const double *tr = a.trial + (size_t)sub * P * m + (size_t)r * a.rs;
+#pragma unroll
+    for (int i = 0; i < QM; ++i) {
+      const uint32_t q = j + (uint32_t)i * tpi;
+      if (q < (uint32_t)m) v[i] = tr[(size_t)q * a.qs];
+    }
+  }
   const size_t rep = cnt_copy_elems(e.n_problems, SB, K, P);
   const TreeScore sc = epilogue_node_counts<D, CNT_REP>(
       e.cnt + (size_t)sub * SB * K * Ppad, e.ctot + (size_t)sub * K, K, Ppad, r,
-      a.feat + ((size_t)sub * P + r) * SB, e.n_min, e.alpha, nullptr, nullptr, rep);
-  double *cost = a.cost + (size_t)sub * P;
+      a.feat + ((size_t)sub * P + r) * SB, e.n_min, e.alpha, nullptr, nullptr, rep, tpi);
   if (e.init) {
-    cost[r] = sc.cost;
+    if (j == 0) cost[r] = sc.cost;
     return;
   }
-  if (!(sc.cost <= cost[r])) return;
-  cost[r] = sc.cost;
-  const double *tr = a.trial + (size_t)sub * P * m + (size_t)r * a.rs;
+  if (!(sc.cost <= pc)) return;
   double *pr = a.pop + (size_t)sub * P * m + (size_t)r * a.rs;
-  constexpr int QB = 10;
 #pragma unroll
-  for (int q0 = 0; q0 < m; q0 += QB) {
-    double v[QB];
-#pragma unroll
-    for (int i = 0; i < QB; ++i)
-      if (q0 + i < m) v[i] = tr[(size_t)(q0 + i) * a.qs];
-#pragma unroll
-    for (int i = 0; i < QB; ++i)
-      if (q0 + i < m) pr[(size_t)(q0 + i) * a.qs] = v[i];
+  for (int i = 0; i < QM; ++i) {
+    const uint32_t q = j + (uint32_t)i * tpi;
+    if (q < (uint32_t)m) pr[(size_t)q * a.qs] = v[i];
   }
+  if (j == 0) cost[r] = sc.cost;
 }
 
 // Part 2, one thread per (node t, individual r) of problem blockIdx.y, r
@@ -450,13 +460,22 @@ mh_status launch_de_gen(Ctx *ctx, const DeDev &de, const uint64_t *prob_ids, uin
   const uint32_t tpi = 1;  // more threads per individual measured slower
   GenArgs e{cnt, ctot, K, n_min, alpha, init ? 1 : 0, tpi, n_problems};
   if (de.P >= DE_SPLIT_MIN_P) {
-    // large populations: the generation as two launches spread over the chip
+    // large populations: the generation as two launches spread over the chip;
+    // the epilogue and selection of an individual on up to 4 lanes (one per
+    // class), so that its count loads and gene copies are spread out
     hipStream_t st = ctx->stream;
     const uint32_t SB = (1u << de.D) - 1u;
-    const dim3 g1((de.P + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
+    uint32_t stpi = 1;
+    while (stpi < K && stpi < 4) stpi <<= 1;
+    if (ctx->de_select_tpi) stpi = ctx->de_select_tpi;
+    e.tpi = stpi;
+    const dim3 g1((de.P * stpi + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
     const dim3 g2((de.P * SB + SPLIT_THREADS - 1) / SPLIT_THREADS, n_problems);
 #define MH_SPLIT(DD)                                                          \
-  k_de_select<DD><<<g1, SPLIT_THREADS, 0, st>>>(a, e);                        \
+  if (stpi == 1) k_de_select<DD, 1><<<g1, SPLIT_THREADS, 0, st>>>(a, e);      \
+  else if (stpi == 2) k_de_select<DD, 2><<<g1, SPLIT_THREADS, 0, st>>>(a, e); \
+  else if (stpi == 4) k_de_select<DD, 4><<<g1, SPLIT_THREADS, 0, st>>>(a, e); \
+  else k_de_select<DD, 8><<<g1, SPLIT_THREADS, 0, st>>>(a, e);                \
   k_de_mutate<<<g2, SPLIT_THREADS, 0, st>>>(a);
     switch (de.D) {
       case 1: MH_SPLIT(1) break;

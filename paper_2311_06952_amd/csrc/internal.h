@@ -78,9 +78,9 @@ struct Ctx {
   // grid-barrier time limit in device wall-clock ticks (MHDEOCT_WAIT_TICKS;
   // tests set a tiny one to exercise the recovery from a barrier that gives up)
   uint64_t wait_ticks = 200000000ull;
-  // grid-synchronising kernels through the runtime's cooperative launch
-  // (MHDEOCT_COOP_LAUNCH=1) instead of an ordinary one
-  bool coop_api = false;
+  // lanes per individual of the split DE step's selection (MHDEOCT_SELECT_TPI,
+  // 1, 2, 4 or 8; 0: one per class up to 4)
+  uint32_t de_select_tpi = 0;
   // remembered occupancy queries
   struct Occ {
     const void *kern;
@@ -130,7 +130,6 @@ int coop_per_cu(Ctx *ctx, const void *kern, int threads, size_t lds);
 // with an empty kernel: 19.6 against 2.3 us per launch) and, as the failures
 // above show, does not make the grid resident either; the barriers' time
 // limit and the failure record cover a grid that does not run all at once.
-// MHDEOCT_COOP_LAUNCH=1 selects the runtime's cooperative launch.
 hipError_t launch_grid_sync(Ctx *ctx, const void *kern, dim3 grid, dim3 block, void **args,
                             size_t lds);
 // Whether (kern, grid) gave up at a grid barrier before in this context.
