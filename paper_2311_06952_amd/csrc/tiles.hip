@@ -191,7 +191,10 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
 
 // One wave per (tile, feature): sort the tile's ranks with their positions
 // (bitonic network across the 64 lanes), write the sorted ranks and the
-// prefix masks of the positions in sorted order.
+// prefix masks of the positions in sorted order.  The composite key (rank,
+// position) is 32 bits wide when every rank is below 2^26 (fewer than 2^26
+// samples), else 64.
+template <typename KT>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ ranks, uint32_t ld,
                                                    TileHdr *__restrict__ hdr) {
   const uint32_t lane = threadIdx.x & 63u;
@@ -203,22 +206,25 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ 
   const uint32_t info = reinterpret_cast<const uint32_t *>(base + hdr->off_info)[tile];
   const uint32_t *order = reinterpret_cast<const uint32_t *>(base + hdr->off_order);
   const uint32_t cnt = info & 0xFFu;
-  uint32_t key = 0xFFFFFFFFu;
+  // unused lanes sort last: all ones
+  constexpr uint32_t KB = sizeof(KT) * 8;
+  uint32_t key = (uint32_t)(~KT(0) >> 6);
   if (lane < cnt) key = ranks[(size_t)f * ld + order[tile * TILE_W + lane]];
   // composite (key, position): distinct, so the network sorts a total order
-  uint64_t v = ((uint64_t)key << 6) | lane;
+  KT v = ((KT)key << 6) | lane;
+  (void)KB;
 #pragma unroll
   for (uint32_t k = 2; k <= 64; k <<= 1) {
 #pragma unroll
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      uint64_t o = __shfl_xor(v, (int)j, 64);
+      KT o = __shfl_xor(v, (int)j, 64);
       bool up = (lane & k) == 0;
       bool lo = (lane & j) == 0;
-      uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+      KT mn = v < o ? v : o, mx = v < o ? o : v;
       v = (lo == up) ? mn : mx;
     }
   }
-  const uint32_t skey = (uint32_t)(v >> 6);
+  const uint32_t skey = lane < cnt ? (uint32_t)(v >> 6) : 0xFFFFFFFFu;
   const uint32_t pos = (uint32_t)(v & 63u);
   uint64_t bit = (lane < cnt) ? (1ull << pos) : 0ull;
   // inclusive OR-scan over lanes: pm[lane + 1]
@@ -267,7 +273,10 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
     MH_LAUNCHED(ctx, "k_tile_scatter");
     uint64_t waves = (uint64_t)h.max_tiles * ds->F;
     uint32_t blocks = (uint32_t)((waves + 3) / 4);
-    k_tile_sort<<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
+    if (ds->n < (1u << 26))
+      k_tile_sort<uint32_t><<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
+    else
+      k_tile_sort<uint64_t><<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
     MH_LAUNCHED(ctx, "k_tile_sort");
   }
   return MH_OK;
