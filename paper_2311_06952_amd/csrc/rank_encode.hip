@@ -387,27 +387,108 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_scatter(const uint64_t *__re
   }
 }
 
-// Distinct-value flags of the sorted segments: position p starts a value when
-// it is its segment's first or its value bits differ from position p - 1's.
-__global__ void k_seg_flags(const uint64_t *__restrict__ src, uint32_t n, uint32_t total,
-                            uint32_t *__restrict__ flags) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= total) return;
-  flags[p] = (p % n == 0 || (uint32_t)(src[p] >> 32) != (uint32_t)(src[p - 1] >> 32)) ? 1u : 0u;
+// Ranks from the sorted segments.  Position p of segment f starts a new value
+// when it is the segment's first or its value bits differ from position
+// p - 1's; a sample's rank is the number of such starts up to and including
+// its position, minus one.  Block (f, j) covers positions [j SG_R, (j + 1)
+// SG_R) of segment f, wave w the span of SG_WSPAN positions from j SG_R +
+// w SG_WSPAN, 64 at a time: the starts among a chunk's lanes come from one
+// ballot, so a lane's count is a popcount of the bits below it.
+//
+// Pass 1: starts per block, ucnt[f nbf + j].
+__global__ __launch_bounds__(SG_THREADS) void k_seg_ucount(const uint64_t *__restrict__ src,
+                                                           uint32_t n, uint32_t nbf,
+                                                           uint32_t *__restrict__ ucnt) {
+  __shared__ uint32_t wsum[SG_THREADS / 64];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint64_t *seg = src + (size_t)f * n;
+  const uint32_t q0 = j * SG_R + w * SG_WSPAN;
+  const uint32_t q1 = min(n, q0 + SG_WSPAN);
+  uint32_t starts = 0;
+  // value bits of the position before the chunk (none before the segment)
+  uint32_t prev = (q0 > 0 && q0 < n) ? (uint32_t)(seg[q0 - 1] >> 32) : 0u;
+  bool prev_ok = q0 > 0;
+  for (uint32_t c = q0; c < q1; c += 64) {
+    const uint32_t q = c + lane;
+    const bool valid = q < q1;
+    const uint32_t v = valid ? (uint32_t)(seg[q] >> 32) : 0u;
+    uint32_t left = __shfl_up(v, 1, 64);
+    if (lane == 0) left = prev;
+    const bool start = valid && (lane == 0 ? (!prev_ok || v != left) : v != left);
+    starts += (uint32_t)__popcll(__ballot(start));
+    prev = __shfl(v, 63, 64);
+    prev_ok = true;
+  }
+  if (lane == 0) wsum[w] = starts;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < SG_THREADS / 64; ++q) t += wsum[q];
+    ucnt[blockIdx.x] = t;
+  }
 }
 
-// rank = distinct values up to and including the position, minus the count
-// before the segment's first position (U inclusive scan of the flags).
-__global__ void k_seg_rank_write(const uint64_t *__restrict__ src, const uint32_t *__restrict__ U,
-                                 uint32_t n, uint32_t total, uint32_t ld,
-                                 uint32_t *__restrict__ ranks, uint32_t *__restrict__ n_unique) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= total) return;
-  const uint32_t f = p / n;
-  const uint32_t first = U[(size_t)f * n];
-  const uint32_t i = (uint32_t)src[p];
-  ranks[(size_t)f * ld + i] = U[p] - first;
-  if (p == f * n + n - 1) n_unique[f] = U[p] - first + 1u;
+// Pass 2, block f: exclusive scan of segment f's block counts in place, and
+// its number of distinct values.
+__global__ __launch_bounds__(SG_THREADS) void k_seg_ubase(uint32_t *__restrict__ ucnt, uint32_t nbf,
+                                                          uint32_t *__restrict__ n_unique) {
+  __shared__ uint32_t tmp[SG_THREADS / 64 + 1];
+  uint32_t *u = ucnt + (size_t)blockIdx.x * nbf;
+  uint32_t run = 0;
+  for (uint32_t c = 0; c < nbf; c += SG_THREADS) {
+    const uint32_t i = c + threadIdx.x;
+    const uint32_t v = i < nbf ? u[i] : 0u;
+    uint32_t all;
+    const uint32_t ex = rc_block_exscan(v, tmp, &all);
+    if (i < nbf) u[i] = run + ex;
+    run += all;
+  }
+  if (threadIdx.x == 0) n_unique[blockIdx.x] = run;
+}
+
+// Pass 3: each position's rank, written to its sample: ranks[f ld + sample].
+__global__ __launch_bounds__(SG_THREADS) void k_seg_rank_scatter(
+    const uint64_t *__restrict__ src, uint32_t n, uint32_t nbf, const uint32_t *__restrict__ ubase,
+    uint32_t ld, uint32_t *__restrict__ ranks) {
+  __shared__ uint32_t wsum[SG_THREADS / 64];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint64_t *seg = src + (size_t)f * n;
+  const uint32_t q0 = j * SG_R + w * SG_WSPAN;
+  const uint32_t q1 = min(n, q0 + SG_WSPAN);
+  constexpr uint32_t RND = SG_WSPAN / 64;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t loc[RND], idx[RND];
+  uint32_t starts = 0;
+  uint32_t prev = (q0 > 0 && q0 < n) ? (uint32_t)(seg[q0 - 1] >> 32) : 0u;
+  bool prev_ok = q0 > 0;
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k) {
+    const uint32_t q = q0 + k * 64 + lane;
+    const bool valid = q < q1;
+    const uint64_t x = valid ? seg[q] : 0ull;
+    const uint32_t v = (uint32_t)(x >> 32);
+    uint32_t left = __shfl_up(v, 1, 64);
+    if (lane == 0) left = prev;
+    const bool start = valid && (lane == 0 ? (!prev_ok || v != left) : v != left);
+    const uint64_t b = __ballot(start);
+    // starts of the wave's span up to and including this position
+    loc[k] = starts + (uint32_t)__popcll(b & lt_mask) + (start ? 1u : 0u);
+    idx[k] = valid ? (uint32_t)x : 0xFFFFFFFFu;
+    starts += (uint32_t)__popcll(b);
+    prev = __shfl(v, 63, 64);
+    prev_ok = true;
+  }
+  if (lane == 0) wsum[w] = starts;
+  __syncthreads();
+  uint32_t base = ubase[blockIdx.x];
+  for (uint32_t q = 0; q < w; ++q) base += wsum[q];
+  uint32_t *rk = ranks + (size_t)f * ld;
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k)
+    if (idx[k] != 0xFFFFFFFFu) rk[idx[k]] = base + loc[k] - 1u;
 }
 
 __global__ __launch_bounds__(RC_THREADS) void k_rank_coop(RankCoopArgs a) {
@@ -729,8 +810,8 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
     uint64_t *kb = (uint64_t *)arena_get(ctx, "re_keys_b", (size_t)total * 8);
     const uint32_t nbf = (n + SG_R - 1) / SG_R, nh = F * 256 * nbf;
     uint32_t *hist = (uint32_t *)arena_get(ctx, "re_seg_hist", (size_t)nh * 4);
-    uint32_t *flags = (uint32_t *)arena_get(ctx, "re_flags", (size_t)total * 4 + 256);
-    if (!ka || !kb || !hist || !flags) return MH_ENOMEM;
+    uint32_t *ucnt = (uint32_t *)arena_get(ctx, "re_ucnt", (size_t)F * nbf * 4);
+    if (!ka || !kb || !hist || !ucnt) return MH_ENOMEM;
     // rows per transposing block: an LDS tile of rows x (F + 1) words
     const uint32_t rows = std::max(1u, std::min(256u, (uint32_t)(16384u / (F + 1u))));
     const uint32_t kblocks = (n + rows - 1) / rows;
@@ -748,13 +829,12 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
       MH_LAUNCHED(ctx, "k_seg_scatter");
       std::swap(a, b);
     }
-    const uint32_t blocks = (total + 255) / 256;
-    k_seg_flags<<<blocks, 256, 0, st>>>(a, n, total, flags);
-    MH_LAUNCHED(ctx, "k_seg_flags");
-    mh_status s = scan_u32(ctx, flags, flags, total, true);
-    if (s) return s;
-    k_seg_rank_write<<<blocks, 256, 0, st>>>(a, flags, n, total, ld, ranks, n_unique);
-    MH_LAUNCHED(ctx, "k_seg_rank_write");
+    k_seg_ucount<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, ucnt);
+    MH_LAUNCHED(ctx, "k_seg_ucount");
+    k_seg_ubase<<<F, SG_THREADS, 0, st>>>(ucnt, nbf, n_unique);
+    MH_LAUNCHED(ctx, "k_seg_ubase");
+    k_seg_rank_scatter<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, ucnt, ld, ranks);
+    MH_LAUNCHED(ctx, "k_seg_rank_scatter");
   }
   if (nan_out) return MH_OK;
   uint32_t *h = host_words(ctx);

@@ -56,6 +56,24 @@ def test_rank_encode_forms(mh, monkeypatch, coop, R, seed, n, F, levels):
     ctx.close()
 
 
+@pytest.mark.parametrize("seed,n,F,levels", [(12, 64, 2, 3), (13, 65, 3, 2), (14, 1024, 2, 7),
+                                             (15, 4096, 3, 1), (16, 8193, 4, 2), (17, 12_289, 2, 40)])
+def test_rank_encode_separate_launch_boundaries(mh, monkeypatch, seed, n, F, levels):
+    """The separate launches at sizes that end exactly on, or one past, a
+    64-lane chunk, a wave's span (1,024) and a block (4,096), with runs of
+    equal values that cross those boundaries (one to forty distinct values)."""
+    from paper_2311_06952_amd import capi
+    monkeypatch.setenv("MHDEOCT_RANK_COOP", "0")
+    ctx = capi.Context(0)
+    X, y = synth.random_small(seed, n, F, 3, levels)
+    X = np.sort(X, axis=0)  # long sorted runs: equal values meet at the boundaries
+    want_r, want_nu = oracle.rank_encode(X)
+    ds = mh.dataset(X, y, 3, ctx=ctx)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :n], want_r)
+    ctx.close()
+
+
 def test_rank_encode_signed_zero_and_nan(mh):
     X = np.array([[0.0, 1.0], [-0.0, 1.0], [-2.5, np.inf], [3.0, -np.inf]], dtype=np.float32)
     want_r, want_nu = oracle.rank_encode(X)
