@@ -9,7 +9,7 @@ rank encoding of the resident float32 features, the tiled sample layout,
 initialisation and G + 1 population evaluations with the DE step between
 them, all on the device.  value = P * n * (G + 1) / (seconds per step).
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import json
@@ -705,7 +705,7 @@ def main():
                     help="generations per DEOCT run of --kernel-only (0: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     if args.kernel_only:

@@ -1,7 +1,7 @@
 """CPU oracle for the MH-DEOCT fitness-evaluation path (arXiv 2311.06952).
 
-TEST INFRASTRUCTURE ONLY.  This package is the checker the HIP library is
-compared against.  Only the test suite, ``__graft_entry__.smoke()`` and the
+TEST INFRASTRUCTURE ONLY.  This package is the CPU implementation that the
+HIP library's results are compared against.  Only the test suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import it; the product package never
 imports, links or calls anything here, and the two share no code.
 

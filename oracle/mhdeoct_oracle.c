@@ -4,8 +4,8 @@
  * Moving-Horizon Algorithm for Training Deep Classification Trees on Large
  * Datasets", arXiv 2311.06952).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP library is
- * compared against.  Only the test suite, the smoke entry point and the CPU
+ * TEST INFRASTRUCTURE ONLY.  This file is the CPU implementation that the HIP
+ * library's results are compared against.  Only the test suite, the smoke entry point and the CPU
  * baseline leg of the benchmark may load it.  The product library never links,
  * loads or calls it, and it shares no code, header, table or helper with the
  * HIP path.
