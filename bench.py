@@ -779,8 +779,11 @@ def main():
         "subtree_solves_per_s": 1e3 / ms,
         "best_correct": res["correct"],
         "roofline": roof,
-        "launch_config": {k: tuned[k] for k in ("persist", "halves", "persist_blocks_per_cu",
-                                                "fit_blocks_per_cu")},
+        "launch_config": dict(
+            {k: tuned[k] for k in ("persist", "halves", "persist_blocks_per_cu",
+                                   "fit_blocks_per_cu")},
+            note="persist = 1 allows the whole-run kernel; the library still runs the "
+                 "per-generation kernels where they keep more waves resident (the form above)"),
     }
     del Xd, yd
     if not args.no_extra:
