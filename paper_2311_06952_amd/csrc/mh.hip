@@ -155,6 +155,20 @@ __device__ __forceinline__ uint64_t split_gini_bits(const uint32_t *__restrict__
   return (uint64_t)__double_as_longlong(g);
 }
 
+// Pass 0 raises the subset's best score to c, pass 1 lowers its best (feature
+// + 1, tau) to ft, each only when the value read is not already as good.
+__device__ __forceinline__ void split_improve(uint32_t pass, unsigned long long *best_c,
+                                              unsigned long long *best_ft, uint64_t c,
+                                              uint64_t ft) {
+  if (pass == 0) {
+    if (c > __hip_atomic_load(best_c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(best_c, (unsigned long long)c);
+  } else {
+    if (ft < __hip_atomic_load(best_ft, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(best_ft, (unsigned long long)ft);
+  }
+}
+
 // pass 1: the best score per subset (atomicMax over candidates): the correct
 // count (GINI false) or the Gini score's bits (GINI true).
 // pass 2: the smallest (feature + 1, tau) among candidates attaining it.
@@ -195,13 +209,13 @@ __global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
       vc = oc > vc ? oc : vc;
       vf = of < vf ? of : vf;
     }
-    if ((threadIdx.x & 63u) == 0 && s0 != 0xFFFFFFFFu && any_cand) {
-      if (pass == 0) atomicMax(&best_c[s0], (unsigned long long)vc);
-      else atomicMin(&best_ft[s0], (unsigned long long)vf);
-    }
+    // (only a wave that can improve the subset's value updates it: most waves
+    // of a large subset see a value already better and skip the contended
+    // atomic; a stale read only costs an atomic that changes nothing)
+    if ((threadIdx.x & 63u) == 0 && s0 != 0xFFFFFFFFu && any_cand)
+      split_improve(pass, best_c + s0, best_ft + s0, vc, vf);
   } else if (cand) {
-    if (pass == 0) atomicMax(&best_c[s], (unsigned long long)c);
-    else atomicMin(&best_ft[s], (unsigned long long)ft);
+    split_improve(pass, best_c + s, best_ft + s, c, ft);
   }
 }
 
