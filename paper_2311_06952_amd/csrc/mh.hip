@@ -277,16 +277,25 @@ __global__ void k_compact(const uint32_t *__restrict__ node_of, uint32_t n, uint
 }
 
 // sub_of for an explicit subset: 0 for idx members, 1 for the rest; and the
-// subset's class totals.
-__global__ void k_mark_subset(const uint32_t *__restrict__ idx, uint32_t n_sub, uint32_t n,
-                              const uint8_t *__restrict__ labels, uint32_t K,
-                              uint32_t *__restrict__ sub_of, uint32_t *__restrict__ tot) {
+// subset's class totals, counted per block in LDS (one global add per block
+// and class: a million samples over a few classes would otherwise serialise
+// on a few addresses).
+__global__ __launch_bounds__(256) void k_mark_subset(const uint32_t *__restrict__ idx,
+                                                     uint32_t n_sub, uint32_t n,
+                                                     const uint8_t *__restrict__ labels,
+                                                     uint32_t K, uint32_t *__restrict__ sub_of,
+                                                     uint32_t *__restrict__ tot) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_sub) return;
-  const uint32_t i = idx ? idx[j] : j;
-  if (i >= n || labels[i] >= K) return;
-  if (atomicExch(&sub_of[i], 0u) == 0u) return;  // a repeated index counts once
-  atomicAdd(&tot[labels[i]], 1u);
+  if (j < n_sub) {
+    const uint32_t i = idx ? idx[j] : j;
+    // a repeated index counts once
+    if (i < n && labels[i] < K && atomicExch(&sub_of[i], 0u) != 0u) atomicAdd(&h[labels[i]], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < K && h[threadIdx.x]) atomicAdd(&tot[threadIdx.x], h[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
