@@ -249,6 +249,16 @@ constexpr uint32_t SG_ITEMS = 16;                  // pairs per thread
 constexpr uint32_t SG_R = SG_THREADS * SG_ITEMS;   // positions per block
 constexpr uint32_t SG_WSPAN = SG_R / (SG_THREADS / 64);  // positions per wave
 
+// Blocks go out to the 8 XCDs round-robin in launch order (block b runs on
+// XCD b % 8).  The segment kernels launch a multiple of 8 blocks and work as
+// block xcd_order(b, g) of the (feature, chunk) list, so that each XCD runs
+// one contiguous range of it: the chunks of a feature meet in one XCD's L2,
+// where the rank scatter's random 4-byte writes to that feature's row merge.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t g) {
+  return (b & 7u) * (g >> 3) + (b >> 3);
+}
+inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + 7u) & ~7u; }
+
 // Pairs of rows [r0, r0 + rows) for every feature: the rows come in
 // coalesced (row-major X) into LDS, padded to F + 1 words per row, and each
 // feature's run of positions f n + r0 .. goes out contiguously.
@@ -279,11 +289,14 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_keys(const float *__restrict
 // Digit counts of block (f, j): positions [j SG_R, (j + 1) SG_R) of segment f,
 // into hist[(f 256 + digit) nbf + j].
 __global__ __launch_bounds__(SG_THREADS) void k_seg_hist(const uint64_t *__restrict__ src,
-                                                         uint32_t n, uint32_t nbf, uint32_t shift,
+                                                         uint32_t n, uint32_t F, uint32_t nbf,
+                                                         uint32_t shift,
                                                          uint32_t *__restrict__ hist) {
   __shared__ uint32_t h[SG_THREADS / 64][256];
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t bi = xcd_order(blockIdx.x, gridDim.x);
+  if (bi >= F * nbf) return;
+  const uint32_t f = bi / nbf, j = bi % nbf;
   const uint32_t lo = j * SG_R, hi = min(n, lo + SG_R);
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) h[w][q * 64 + lane] = 0;
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_hist(const uint64_t *__restr
 // + d) nbf + j], the global position the scan gave it.
 __global__ __launch_bounds__(SG_THREADS) void k_seg_scatter(const uint64_t *__restrict__ src,
                                                             uint64_t *__restrict__ dst,
-                                                            uint32_t n, uint32_t nbf,
+                                                            uint32_t n, uint32_t F, uint32_t nbf,
                                                             uint32_t shift,
                                                             const uint32_t *__restrict__ offs) {
   __shared__ uint64_t kv[SG_R];
@@ -321,7 +334,9 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_scatter(const uint64_t *__re
   __shared__ uint32_t gpos[256];
   __shared__ uint32_t tmp[SG_THREADS / 64 + 1];
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t bi = xcd_order(blockIdx.x, gridDim.x);
+  if (bi >= F * nbf) return;
+  const uint32_t f = bi / nbf, j = bi % nbf;
   const uint32_t lo = j * SG_R, cnt = min(n - lo, SG_R);
   const uint64_t *seg = src + (size_t)f * n + lo;
   const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -397,11 +412,13 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_scatter(const uint64_t *__re
 //
 // Pass 1: starts per block, ucnt[f nbf + j].
 __global__ __launch_bounds__(SG_THREADS) void k_seg_ucount(const uint64_t *__restrict__ src,
-                                                           uint32_t n, uint32_t nbf,
+                                                           uint32_t n, uint32_t F, uint32_t nbf,
                                                            uint32_t *__restrict__ ucnt) {
   __shared__ uint32_t wsum[SG_THREADS / 64];
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t bi = xcd_order(blockIdx.x, gridDim.x);
+  if (bi >= F * nbf) return;
+  const uint32_t f = bi / nbf, j = bi % nbf;
   const uint64_t *seg = src + (size_t)f * n;
   const uint32_t q0 = j * SG_R + w * SG_WSPAN;
   const uint32_t q1 = min(n, q0 + SG_WSPAN);
@@ -426,7 +443,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_ucount(const uint64_t *__res
     uint32_t t = 0;
 #pragma unroll
     for (uint32_t q = 0; q < SG_THREADS / 64; ++q) t += wsum[q];
-    ucnt[blockIdx.x] = t;
+    ucnt[bi] = t;
   }
 }
 
@@ -450,11 +467,13 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_ubase(uint32_t *__restrict__
 
 // Pass 3: each position's rank, written to its sample: ranks[f ld + sample].
 __global__ __launch_bounds__(SG_THREADS) void k_seg_rank_scatter(
-    const uint64_t *__restrict__ src, uint32_t n, uint32_t nbf, const uint32_t *__restrict__ ubase,
-    uint32_t ld, uint32_t *__restrict__ ranks) {
+    const uint64_t *__restrict__ src, uint32_t n, uint32_t F, uint32_t nbf,
+    const uint32_t *__restrict__ ubase, uint32_t ld, uint32_t *__restrict__ ranks) {
   __shared__ uint32_t wsum[SG_THREADS / 64];
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t f = blockIdx.x / nbf, j = blockIdx.x % nbf;
+  const uint32_t bi = xcd_order(blockIdx.x, gridDim.x);
+  if (bi >= F * nbf) return;
+  const uint32_t f = bi / nbf, j = bi % nbf;
   const uint64_t *seg = src + (size_t)f * n;
   const uint32_t q0 = j * SG_R + w * SG_WSPAN;
   const uint32_t q1 = min(n, q0 + SG_WSPAN);
@@ -483,7 +502,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_rank_scatter(
   }
   if (lane == 0) wsum[w] = starts;
   __syncthreads();
-  uint32_t base = ubase[blockIdx.x];
+  uint32_t base = ubase[bi];
   for (uint32_t q = 0; q < w; ++q) base += wsum[q];
   uint32_t *rk = ranks + (size_t)f * ld;
 #pragma unroll
@@ -821,19 +840,19 @@ mh_status launch_rank_encode(Ctx *ctx, const float *X, uint32_t n, uint32_t F, u
     uint64_t *a = ka, *b = kb;
     for (uint32_t pass = 0; pass < 4; ++pass) {
       const uint32_t shift = 32 + 8 * pass;
-      k_seg_hist<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, shift, hist);
+      k_seg_hist<<<xcd_grid(F * nbf), SG_THREADS, 0, st>>>(a, n, F, nbf, shift, hist);
       MH_LAUNCHED(ctx, "k_seg_hist");
       mh_status s = scan_u32(ctx, hist, hist, nh, false);
       if (s) return s;
-      k_seg_scatter<<<F * nbf, SG_THREADS, 0, st>>>(a, b, n, nbf, shift, hist);
+      k_seg_scatter<<<xcd_grid(F * nbf), SG_THREADS, 0, st>>>(a, b, n, F, nbf, shift, hist);
       MH_LAUNCHED(ctx, "k_seg_scatter");
       std::swap(a, b);
     }
-    k_seg_ucount<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, ucnt);
+    k_seg_ucount<<<xcd_grid(F * nbf), SG_THREADS, 0, st>>>(a, n, F, nbf, ucnt);
     MH_LAUNCHED(ctx, "k_seg_ucount");
     k_seg_ubase<<<F, SG_THREADS, 0, st>>>(ucnt, nbf, n_unique);
     MH_LAUNCHED(ctx, "k_seg_ubase");
-    k_seg_rank_scatter<<<F * nbf, SG_THREADS, 0, st>>>(a, n, nbf, ucnt, ld, ranks);
+    k_seg_rank_scatter<<<xcd_grid(F * nbf), SG_THREADS, 0, st>>>(a, n, F, nbf, ucnt, ld, ranks);
     MH_LAUNCHED(ctx, "k_seg_rank_scatter");
   }
   if (nan_out) return MH_OK;

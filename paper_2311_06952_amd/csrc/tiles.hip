@@ -194,14 +194,24 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
 // prefix masks of the positions in sorted order.  The composite key (rank,
 // position) is 32 bits wide when every rank is below 2^26 (fewer than 2^26
 // samples), else 64.
+//
+// Block b works on feature f and tiles 4 q .. 4 q + 3 (one per wave), with
+// (f, q) = block xcd_order(b) of the feature-major list: blocks go out to the
+// 8 XCDs round-robin in launch order, so each XCD runs a contiguous range of
+// the list and its random reads of a feature's ranks stay in its own L2.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t g) {
+  return (b & 7u) * (g >> 3) + (b >> 3);
+}
+
 template <typename KT>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ ranks, uint32_t ld,
                                                    TileHdr *__restrict__ hdr) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t F = hdr->F;
-  const uint32_t tile = w / F, f = w % F;
-  if (tile >= hdr->n_tiles) return;
+  const uint32_t tq = (hdr->max_tiles + 3u) / 4u;  // tile quads per feature
+  const uint32_t bi = xcd_order(blockIdx.x, gridDim.x);
+  const uint32_t f = bi / tq, tile = (bi % tq) * 4u + (threadIdx.x >> 6);
+  if (f >= F || tile >= hdr->n_tiles) return;
   uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
   const uint32_t info = reinterpret_cast<const uint32_t *>(base + hdr->off_info)[tile];
   const uint32_t *order = reinterpret_cast<const uint32_t *>(base + hdr->off_order);
@@ -271,8 +281,9 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
     uint32_t nb = (n_sub + 255) / 256;
     k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, dh);
     MH_LAUNCHED(ctx, "k_tile_scatter");
-    uint64_t waves = (uint64_t)h.max_tiles * ds->F;
-    uint32_t blocks = (uint32_t)((waves + 3) / 4);
+    // F blocks per quad of tiles, a multiple of 8 in all (see k_tile_sort)
+    const uint64_t quads = ((uint64_t)h.max_tiles + 3) / 4;
+    const uint32_t blocks = (uint32_t)((quads * ds->F + 7) & ~(uint64_t)7);
     if (ds->n < (1u << 26))
       k_tile_sort<uint32_t><<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
     else
