@@ -17,15 +17,13 @@ def test_splitmix64_published_sequence(golden_dir):
 
 
 @pytest.mark.parametrize("seed,prob,g,r,slot", [(0, 0, 0, 0, 0), (1234567, 3, 0, 0, 5),
-                                                (99, 7, 0, 1, 2), (5, 1, 0, 2, 7)])
+                                                (99, 7, 0, 1, 2), (5, 1, 0, 0, 1000)])
 def test_draw_is_splitmix_output_number(seed, prob, g, r, slot):
     # draw = output (ctr + 1) of SplitMix64 seeded with key, key = output
     # (prob + 1) of SplitMix64 seeded with seed; checked against the
     # sequential generator (itself pinned above).
     key = oracle.splitmix64_sequence(seed, prob + 1)[-1]
     ctr = (g << 40) | (r << 20) | slot
-    if ctr > 1 << 21:
-        pytest.skip("sequence too long for the sequential check")
     assert oracle.draw(seed, prob, g, r, slot) == oracle.splitmix64_sequence(key, ctr + 1)[-1]
 
 
