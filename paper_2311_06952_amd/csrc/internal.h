@@ -197,7 +197,11 @@ struct TileHdr {
   uint64_t off_segoff;   // u32 [n_problems * K + 1]: first tile of a segment
   uint64_t off_cursor;   // u32 [n_problems * K]: fill cursors (build scratch)
   uint64_t total_bytes;
-  uint32_t pad1[64 - 22];
+  uint64_t off_perm;     // u8 [max_tiles][F][64]: the tile position of each sorted
+                         // rank (past the count, the last one's again); with the
+                         // sorted ranks a compact form of the record, the masks
+                         // rebuilt from it
+  uint32_t pad1[64 - 24];
 };
 static_assert(sizeof(TileHdr) == 256, "tile header is 256 bytes");
 

@@ -146,6 +146,37 @@ __host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint3
 // in the DE phase group h makes the genes of its share of the nodes (nodes
 // h * NA .. with NA = ceil(SB / H)).  Decoded nodes are exchanged through
 // LDS so that every group evaluates whole trees.
+// Prefix masks of a tile from its compact form: chunk q of the positions
+// holds, for feature f = q / 4, the tile positions of sorted entries
+// 16 (q % 4) .. 16 (q % 4) + 15 (past the tile's count the last sample's
+// position again, so the running union needs no test).  The four
+// chunks of a feature sit on the four lanes of an aligned quad (the chunk
+// index and the lane advance together and the chunk ranges start at
+// multiples of 4), which exchange their chunks' unions so that each lane
+// writes its 16 masks pm[16 (q % 4) + j + 1] = positions of the first
+// 16 (q % 4) + j + 1 sorted entries; lane 0 of the quad writes pm[0] = 0.
+// All four lanes of a quad call this together.
+__device__ __forceinline__ void stage_positions(uint8_t *__restrict__ lds, uint32_t mregion,
+                                                uint32_t q, const uint4 &v) {
+  const uint32_t f = q >> 2, part = q & 3u;
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint64_t run = 0;
+  uint64_t m[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t pos = (w[j >> 2] >> (8 * (j & 3))) & 63u;
+    run |= 1ull << pos;
+    m[j] = run;
+  }
+  // union of the earlier chunks of the feature (lanes part - 1 .. part - 3)
+  const uint64_t u1 = __shfl_up(run, 1, 4), u2 = __shfl_up(run, 2, 4), u3 = __shfl_up(run, 3, 4);
+  const uint64_t e = (part >= 1 ? u1 : 0ull) | (part >= 2 ? u2 : 0ull) | (part >= 3 ? u3 : 0ull);
+  uint64_t *pm = reinterpret_cast<uint64_t *>(lds + mregion + f * MCOL) + part * 16u;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) pm[j + 1] = e | m[j];
+  if (part == 0) pm[0] = 0ull;
+}
+
 template <int D, int WAVES, int H, bool RES>
 __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   constexpr int SB = (1 << D) - 1, SL = 1 << D, m = 2 * SB;
@@ -178,6 +209,11 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       reinterpret_cast<const uint32_t *>(base + pa.hdr->off_ctot) + (size_t)s_prob * pa.K;
   const size_t rec_bytes = tile_bytes(F);
   const uint32_t nchunk = 48u * F;
+  // tiles staged every generation come in the compact form: the record's
+  // sorted ranks (16 F chunks) and the tile positions in sorted order (4 F
+  // chunks), the masks rebuilt in LDS (stage_positions)
+  const uint8_t *__restrict__ perm = base + pa.hdr->off_perm;
+  const uint32_t nchunk_c = 20u * F;
   const uint32_t t_begin = T0 + (uint32_t)((uint64_t)(T1 - T0) * b / nb);
   const uint32_t t_end = T0 + (uint32_t)((uint64_t)(T1 - T0) * (b + 1) / nb);
   uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
@@ -271,10 +307,12 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
   uint4 pf[NPF];
   auto prefetch = [&](uint32_t tile) {
     const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
+    const uint4 *__restrict__ psrc = reinterpret_cast<const uint4 *>(perm + (size_t)tile * F * TILE_W);
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
       const uint32_t c = r + k * NTH;
-      if (c < nchunk) pf[k] = src[c];
+      if (c < 16u * F) pf[k] = src[c];
+      else if (c < nchunk_c) pf[k] = psrc[c - 16u * F];
     }
   };
   uint32_t inf_next = 0;
@@ -375,13 +413,18 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 #pragma unroll
           for (int k = 0; k < NPF; ++k) {
             const uint32_t c = r + k * NTH;
-            if (c < nchunk) stage_chunk(my_tile, mregion, F, c, pf[k]);
+            if (c < 16u * F) stage_chunk(my_tile, mregion, F, c, pf[k]);
+            else if (c < nchunk_c) stage_positions(my_tile, mregion, c - 16u * F, pf[k]);
           }
-          if (nchunk > NPF * NTH) {
+          if (nchunk_c > NPF * NTH) {
             const uint4 *__restrict__ src =
                 reinterpret_cast<const uint4 *>(data + (size_t)tile * rec_bytes);
-            for (uint32_t c = r + NPF * NTH; c < nchunk; c += NTH)
-              stage_chunk(my_tile, mregion, F, c, src[c]);
+            const uint4 *__restrict__ psrc =
+                reinterpret_cast<const uint4 *>(perm + (size_t)tile * F * TILE_W);
+            for (uint32_t c = r + NPF * NTH; c < nchunk_c; c += NTH) {
+              if (c < 16u * F) stage_chunk(my_tile, mregion, F, c, src[c]);
+              else stage_positions(my_tile, mregion, c - 16u * F, psrc[c - 16u * F]);
+            }
           }
         }
         __syncthreads();

@@ -35,6 +35,8 @@ TileHdr tile_layout(uint32_t n_sub, uint32_t F, uint32_t K, uint32_t n_problems)
   off = align256(off + ((size_t)n_problems * K + 1) * 4);
   h.off_cursor = off;
   off = align256(off + (size_t)n_problems * K * 4);
+  h.off_perm = off;
+  off = align256(off + (size_t)h.max_tiles * F * TILE_W);
   h.total_bytes = off;
   return h;
 }
@@ -249,6 +251,10 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ 
   sorted[lane] = skey;
   if (lane < 63u) pm[lane + 1] = bit;
   else pm[0] = 0ull;
+  // the compact form: past the count the last sample's position again, so
+  // that a running union of (1 << position) stays correct without a test
+  const uint32_t last = (uint32_t)__shfl((int)pos, (int)(cnt ? cnt - 1u : 0u), 64);
+  base[hdr->off_perm + ((size_t)tile * F + f) * TILE_W + lane] = (uint8_t)(lane < cnt ? pos : last);
 }
 
 }  // namespace
