@@ -146,6 +146,9 @@ __host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint3
 // in the DE phase group h makes the genes of its share of the nodes (nodes
 // h * NA .. with NA = ceil(SB / H)).  Decoded nodes are exchanged through
 // LDS so that every group evaluates whole trees.
+// Features from which tiles staged every generation come in the compact form.
+constexpr uint32_t PERSIST_COMPACT_MIN_F = 16;
+
 // Prefix masks of a tile from its compact form: chunk q of the positions
 // holds, for feature f = q / 4, the tile positions of sorted entries
 // 16 (q % 4) .. 16 (q % 4) + 15 (past the tile's count the last sample's
@@ -177,7 +180,9 @@ __device__ __forceinline__ void stage_positions(uint8_t *__restrict__ lds, uint3
   if (part == 0) pm[0] = 0ull;
 }
 
-template <int D, int WAVES, int H, bool RES>
+// CMP (staged tiles only): the tiles come in the compact form (sorted ranks
+// and positions, the masks rebuilt in LDS) rather than as whole records.
+template <int D, int WAVES, int H, bool RES, bool CMP = false>
 __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa) {
   constexpr int SB = (1 << D) - 1, SL = 1 << D, m = 2 * SB;
   constexpr uint32_t NTH = WAVES * 64, NT = H * NTH;
@@ -209,11 +214,12 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
       reinterpret_cast<const uint32_t *>(base + pa.hdr->off_ctot) + (size_t)s_prob * pa.K;
   const size_t rec_bytes = tile_bytes(F);
   const uint32_t nchunk = 48u * F;
-  // tiles staged every generation come in the compact form: the record's
-  // sorted ranks (16 F chunks) and the tile positions in sorted order (4 F
-  // chunks), the masks rebuilt in LDS (stage_positions)
+  // tiles staged every generation in the compact form: the record's sorted
+  // ranks (16 F chunks) and the tile positions in sorted order (4 F chunks),
+  // the masks rebuilt in LDS (stage_positions); else the whole record
   const uint8_t *__restrict__ perm = base + pa.hdr->off_perm;
-  const uint32_t nchunk_c = 20u * F;
+  constexpr bool compact = CMP && !RES;
+  const uint32_t nchunk_c = compact ? 20u * F : nchunk;
   const uint32_t t_begin = T0 + (uint32_t)((uint64_t)(T1 - T0) * b / nb);
   const uint32_t t_end = T0 + (uint32_t)((uint64_t)(T1 - T0) * (b + 1) / nb);
   uint32_t rounds = (t_end - t_begin + H - 1) / H;  // tile steps, same for both halves
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
       const uint32_t c = r + k * NTH;
-      if (c < 16u * F) pf[k] = src[c];
+      if (c < 16u * F || (!compact && c < nchunk_c)) pf[k] = src[c];
       else if (c < nchunk_c) pf[k] = psrc[c - 16u * F];
     }
   };
@@ -413,7 +419,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
 #pragma unroll
           for (int k = 0; k < NPF; ++k) {
             const uint32_t c = r + k * NTH;
-            if (c < 16u * F) stage_chunk(my_tile, mregion, F, c, pf[k]);
+            if (c < 16u * F || (!compact && c < nchunk_c)) stage_chunk(my_tile, mregion, F, c, pf[k]);
             else if (c < nchunk_c) stage_positions(my_tile, mregion, c - 16u * F, pf[k]);
           }
           if (nchunk_c > NPF * NTH) {
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(H * WAVES * 64) void k_deoct_persist(PersistArgs pa
             const uint4 *__restrict__ psrc =
                 reinterpret_cast<const uint4 *>(perm + (size_t)tile * F * TILE_W);
             for (uint32_t c = r + NPF * NTH; c < nchunk_c; c += NTH) {
-              if (c < 16u * F) stage_chunk(my_tile, mregion, F, c, src[c]);
+              if (c < 16u * F || !compact) stage_chunk(my_tile, mregion, F, c, src[c]);
               else stage_positions(my_tile, mregion, c - 16u * F, psrc[c - 16u * F]);
             }
           }
@@ -768,8 +774,15 @@ template <int D, int WAVES, int H>
 mh_status launch_w(Ctx *ctx, const PersistArgs &pa, uint32_t lds, uint32_t max_tiles,
                    const Groups &gr, bool *used) {
   const void *kres = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, true>);
+  // staged tiles: the compact form trades bytes for the work of rebuilding
+  // the masks, which pays from PERSIST_COMPACT_MIN_F features on (measured:
+  // F = 20, n = 10^6, a level's launch 6.0 -> 4.9 ms; F = 8, n = 10^7, the
+  // launches of a moving-horizon run 186 -> 237 ms)
   const void *kstage = nullptr;
-  if constexpr (H < 4) kstage = reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false>);
+  if constexpr (H < 4)
+    kstage = pa.F >= PERSIST_COMPACT_MIN_F
+                 ? reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false, true>)
+                 : reinterpret_cast<const void *>(k_deoct_persist<D, WAVES, H, false, false>);
   const void *kern = kstage ? kstage : kres;
   const int per_cu = coop_per_cu(ctx, kern, H * WAVES * 64, lds);
   if (per_cu < 1)

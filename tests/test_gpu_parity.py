@@ -474,7 +474,8 @@ def test_penalised_objective_deoct(mh, monkeypatch, D, P, K, n_min, alpha):
 
 
 _GROUP_SHAPES = [(1, 12, 2, 3000, 5), (3, 256, 3, 20000, 16), (3, 100, 6, 7000, 9),
-                 (4, 128, 3, 9000, 12), (5, 64, 2, 5000, 7), (2, 256, 40, 12000, 8)]
+                 (4, 128, 3, 9000, 12), (5, 64, 2, 5000, 7), (2, 256, 40, 12000, 8),
+                 (2, 40, 3, 6000, 40)]
 _group_want = {}
 
 
@@ -483,8 +484,11 @@ _group_want = {}
 @pytest.mark.parametrize("D,P,K,n,F", _GROUP_SHAPES)
 def test_persistent_wave_groups_agree(mh, monkeypatch, halves, resident, D, P, K, n, F):
     """One, two or four tile streams (wave groups) per block, tiles resident
-    in LDS or staged each generation: the whole-run kernel gives the oracle's
-    DEOCT run (the groups only change the order in which counts are added)."""
+    in LDS or staged each generation (whole records below 16 features, the
+    compact form with the masks rebuilt in LDS from 16 on; at F = 40 and one
+    wave per group part of a tile is staged without prefetch): the whole-run
+    kernel gives the oracle's DEOCT run (the groups only change the order in
+    which counts are added)."""
     from paper_2311_06952_amd import capi
     key = (D, P, K, n, F)
     X, y = synth.random_small(110 + D + K, n, F, K)
