@@ -140,12 +140,6 @@ __host__ __device__ __forceinline__ uint32_t persist_lds_bytes(uint32_t F, uint3
          align16u(F * 4) + PERSIST_TAIL;
 }
 
-// Wave groups (H = 1, 2 or 4): the block holds H copies of the population's
-// lanes; group h (threads h * NTH ..) counts every H-th tile of the block's
-// range in its own staging buffer, so H tiles are in flight per block, and
-// in the DE phase group h makes the genes of its share of the nodes (nodes
-// h * NA .. with NA = ceil(SB / H)).  Decoded nodes are exchanged through
-// LDS so that every group evaluates whole trees.
 // Features from which tiles staged every generation come in the compact form.
 constexpr uint32_t PERSIST_COMPACT_MIN_F = 16;
 
@@ -180,6 +174,12 @@ __device__ __forceinline__ void stage_positions(uint8_t *__restrict__ lds, uint3
   if (part == 0) pm[0] = 0ull;
 }
 
+// Wave groups (H = 1, 2 or 4): the block holds H copies of the population's
+// lanes; group h (threads h * NTH ..) counts every H-th tile of the block's
+// range in its own staging buffer, so H tiles are in flight per block, and
+// in the DE phase group h makes the genes of its share of the nodes (nodes
+// h * NA .. with NA = ceil(SB / H)).  Decoded nodes are exchanged through
+// LDS so that every group evaluates whole trees.
 // CMP (staged tiles only): the tiles come in the compact form (sorted ranks
 // and positions, the masks rebuilt in LDS) rather than as whole records.
 template <int D, int WAVES, int H, bool RES, bool CMP = false>
