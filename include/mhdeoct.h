@@ -194,7 +194,7 @@ mh_status fitness_eval(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
  * each GPU holds from the library's load until the process ends; the call
  * calls no allocating routine and only queues kernels on the context's
  * stream (no memset nodes, no timing events).  An evaluation that needs more
- * than 64 MiB of that scratch (the tile path needs about 12.2 * F bytes per
+ * than 64 MiB of that scratch (the tile path needs about 13.2 * F bytes per
  * sample plus 4 * (2^D - 1) * K * P rounded up; the walk path 4 * P * 2^D * K
  * bytes) fails with MH_EINVAL and queues nothing.  Every call on one GPU
  * shares that GPU's array: calls in flight at the same time on different
@@ -211,7 +211,8 @@ mh_status fitness_eval_static(mh_ctx *ctx, const mh_dataset *ds, const uint32_t 
 /* The tiled sample layout the fitness kernel reads: samples grouped by
  * class into tiles of at most 63, each tile holding, per feature, its ranks
  * in ascending order and the prefix bitmasks of the sample positions in
- * that order.  mh_tileset_bytes gives the device bytes a layout for n_sub
+ * that order, and beside the records the positions themselves (one byte per
+ * sorted rank).  mh_tileset_bytes gives the device bytes a layout for n_sub
  * samples needs; mh_tileset_build fills a caller-owned device buffer of at
  * least that size (256-byte aligned).  The layout stays valid as long as
  * the dataset's ranks and labels do not change. */
