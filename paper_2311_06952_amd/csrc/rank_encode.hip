@@ -27,6 +27,7 @@
 #include "device_common.h"
 #include "grid_sync.h"
 #include "internal.h"
+#include "xcd.h"
 
 namespace mh {
 namespace {
@@ -249,15 +250,8 @@ constexpr uint32_t SG_ITEMS = 16;                  // pairs per thread
 constexpr uint32_t SG_R = SG_THREADS * SG_ITEMS;   // positions per block
 constexpr uint32_t SG_WSPAN = SG_R / (SG_THREADS / 64);  // positions per wave
 
-// Blocks go out to the 8 XCDs round-robin in launch order (block b runs on
-// XCD b % 8).  The segment kernels launch a multiple of 8 blocks and work as
-// block xcd_order(b, g) of the (feature, chunk) list, so that each XCD runs
-// one contiguous range of it: the chunks of a feature meet in one XCD's L2,
-// where the rank scatter's random 4-byte writes to that feature's row merge.
-__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t g) {
-  return (b & 7u) * (g >> 3) + (b >> 3);
-}
-inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + 7u) & ~7u; }
+// The segment kernels work through the (feature, chunk) list in XCD order
+// (xcd.h): the chunks of a feature meet in one XCD's L2.
 
 // Pairs of rows [r0, r0 + rows) for every feature: the rows come in
 // coalesced (row-major X) into LDS, padded to F + 1 words per row, and each

@@ -10,6 +10,7 @@
 // per moving-horizon level), not once per evaluation.
 #include "device_common.h"
 #include "internal.h"
+#include "xcd.h"
 
 namespace mh {
 
@@ -198,12 +199,8 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
 // samples), else 64.
 //
 // Block b works on feature f and tiles 4 q .. 4 q + 3 (one per wave), with
-// (f, q) = block xcd_order(b) of the feature-major list: blocks go out to the
-// 8 XCDs round-robin in launch order, so each XCD runs a contiguous range of
-// the list and its random reads of a feature's ranks stay in its own L2.
-__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t g) {
-  return (b & 7u) * (g >> 3) + (b >> 3);
-}
+// (f, q) = block xcd_order(b) of the feature-major list (xcd.h), so that an
+// XCD's random reads of a feature's ranks stay in its own L2.
 
 template <typename KT>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ ranks, uint32_t ld,
@@ -287,9 +284,9 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
     uint32_t nb = (n_sub + 255) / 256;
     k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, dh);
     MH_LAUNCHED(ctx, "k_tile_scatter");
-    // F blocks per quad of tiles, a multiple of 8 in all (see k_tile_sort)
+    // F blocks per quad of tiles (see k_tile_sort)
     const uint64_t quads = ((uint64_t)h.max_tiles + 3) / 4;
-    const uint32_t blocks = (uint32_t)((quads * ds->F + 7) & ~(uint64_t)7);
+    const uint32_t blocks = xcd_grid((uint32_t)(quads * ds->F));
     if (ds->n < (1u << 26))
       k_tile_sort<uint32_t><<<blocks, 256, 0, st>>>(ds->ranks, ds->ld, dh);
     else
