@@ -215,7 +215,9 @@ mh_status fitness_eval_static(mh_ctx *ctx, const mh_dataset *ds, const uint32_t 
  * sorted rank).  mh_tileset_bytes gives the device bytes a layout for n_sub
  * samples needs; mh_tileset_build fills a caller-owned device buffer of at
  * least that size (256-byte aligned).  The layout stays valid as long as
- * the dataset's ranks and labels do not change. */
+ * the dataset's ranks and labels do not change.  The layout needs
+ * ds->n < 2^31 (MH_EINVAL otherwise; fitness_eval then takes the per-sample
+ * walk). */
 mh_status mh_tileset_bytes(uint32_t n_sub, uint32_t F, uint32_t K, size_t *bytes);
 mh_status mh_tileset_build(mh_ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
                            uint32_t n_sub, void *tiles, size_t bytes);

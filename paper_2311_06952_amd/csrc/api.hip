@@ -196,7 +196,9 @@ void *arena_get(Ctx *ctx, const char *name, size_t bytes) {
 }
 
 // Tile path limits: depth templates 1..5, one LDS tile <= 64 KiB.
-static bool tile_path_ok(uint32_t D, uint32_t F) { return D >= 1 && D <= 5 && F <= 80; }
+static bool tile_path_ok(uint32_t D, uint32_t F, uint32_t n) {
+  return D >= 1 && D <= 5 && F <= 80 && n < (1u << 31);
+}
 // Fewer trees than this leave most lanes of the tile kernel idle (lane =
 // tree) while it still stages every tile: the walk kernel (lane = sample)
 // evaluates them instead.
@@ -263,7 +265,7 @@ static mh_status eval_trees(Ctx *ctx, const EvalSet &es, const uint8_t *feat, co
 // counts (walk path) that one fitness evaluation of P depth-D trees over
 // n_sub samples of ds uses, each part 256-byte aligned.
 static size_t eval_scratch_bytes(const mh_dataset *ds, uint32_t n_sub, uint32_t D, uint32_t P) {
-  if (tile_path_ok(D, ds->F) && P >= TILE_MIN_TREES)
+  if (tile_path_ok(D, ds->F, ds->n) && P >= TILE_MIN_TREES)
     return align256(tile_layout(n_sub, ds->F, ds->K, 1).total_bytes) +
            align256(cnt_bytes(1, D, ds->K, P));
   return align256(walk_scratch_bytes(P, D, ds->K));
@@ -283,7 +285,7 @@ static mh_status prepare_eval(Ctx *ctx, const mh_dataset *ds, const uint32_t *id
   es.tiles = nullptr;
   es.cnt = nullptr;
   es.max_tiles = 0;
-  const bool use_tiles = tile_path_ok(D, ds->F) && P >= min_trees;
+  const bool use_tiles = tile_path_ok(D, ds->F, ds->n) && P >= min_trees;
   es.leafcnt = use_tiles ? nullptr : reinterpret_cast<uint32_t *>(static_base);
   if (!use_tiles) return MH_OK;
   TileHdr h = tile_layout(n_sub, ds->F, ds->K, 1);
@@ -717,7 +719,7 @@ mh_status fitness_eval_tiles(mh_ctx *ctx, const void *tiles, const uint32_t *n_u
   MH_HIP(c, hipMemcpyAsync(&h, tiles, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   MH_HIP(c, hipStreamSynchronize(c->stream));
   if (h.magic != TILE_MAGIC || h.n_problems != 1) return fail(c, MH_EINVAL, "not a tile set");
-  if (!tile_path_ok(D, h.F)) return fail(c, MH_EINVAL, "tile path needs D <= 5 and F <= 80");
+  if (!tile_path_ok(D, h.F, 0)) return fail(c, MH_EINVAL, "tile path needs D <= 5 and F <= 80");
   uint32_t *cnt = (uint32_t *)arena_get(c, "fe_cnt", cnt_bytes(1, D, h.K, P));
   if (!cnt) return MH_ENOMEM;
   MH_HIP(c, hipMemsetAsync(cnt, 0, cnt_bytes(1, D, h.K, P), c->stream));

@@ -48,6 +48,20 @@ __device__ __forceinline__ uint64_t lds_rd64(uint32_t addr) {
   return *reinterpret_cast<lds_u64_t *>(static_cast<uintptr_t>(addr));
 }
 
+// One search step: a + (v < t ? 4 s : 0) for ranks and thresholds below
+// 2^31 (the tile layout's unused entries are 0x7FFFFFFF), where the sign of
+// v - t is v < t.  The shift and add are the one instruction they are
+// written as, so that the compiler neither turns the sign test back into a
+// compare and select through VCC (whose hazard costs a wait state per step)
+// nor splits it into shift, mask and add.
+__device__ __forceinline__ uint32_t step_if_less(uint32_t a, uint32_t v, uint32_t t, int s) {
+  const uint32_t bit = (v - t) >> 31;
+  const uint32_t sh = (uint32_t)__builtin_ctz((unsigned)s) + 2u;  // log2(4 s)
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(bit), "s"(sh), "v"(a));
+  return r;
+}
+
 // delta: byte offset of the staged tile from the one the node columns were
 // set up for (kmask is that tile's), so that one node state serves several
 // staged tiles.
@@ -65,7 +79,7 @@ __device__ __forceinline__ void eval_group(uint32_t kmask, NodeState<D> &ns,
 #pragma unroll
     for (int i = 0; i < NG; ++i) v[i] = lds_rd32(a[i] + (s - 1) * 4);
 #pragma unroll
-    for (int i = 0; i < NG; ++i) a[i] += (v[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
+    for (int i = 0; i < NG; ++i) a[i] = step_if_less(a[i], v[i], ns.thr[T0 - 1 + i], s);
   }
   uint64_t m[NG];
 #pragma unroll
@@ -119,8 +133,8 @@ __device__ __forceinline__ void eval_group2(uint32_t kmask, NodeState<D> &ns,
     }
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-      a[i] += (va[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
-      c[i] += (vc[i] < ns.thr[T0 - 1 + i]) ? s * 4 : 0;
+      a[i] = step_if_less(a[i], va[i], ns.thr[T0 - 1 + i], s);
+      c[i] = step_if_less(c[i], vc[i], ns.thr[T0 - 1 + i], s);
     }
   }
   uint64_t ma[NG], mc[NG];

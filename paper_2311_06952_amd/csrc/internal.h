@@ -173,7 +173,7 @@ mh_status hip_fail(Ctx *ctx, hipError_t e, const char *what);
 //
 // Samples of each (subproblem, class) segment are cut into tiles of at most
 // TILE_CAP = 63.  A tile record holds, per feature f, the tile's ranks in
-// ascending order (64 u32; unused entries 0xFFFFFFFF) followed, per feature,
+// ascending order (64 u32; unused entries 0x7FFFFFFF) followed, per feature,
 // by the 64 prefix masks pm[c] = set of tile positions of the c smallest
 // ranks (u64; pm[0] = 0).  "rank < tau" over the tile is then pm[c] with
 // c = #{sorted ranks < tau}, found by binary search.

@@ -233,7 +233,8 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ 
       v = (lo == up) ? mn : mx;
     }
   }
-  const uint32_t skey = lane < cnt ? (uint32_t)(v >> 6) : 0xFFFFFFFFu;
+  // unused entries: 0x7FFFFFFF, above every rank and threshold (n < 2^31)
+  const uint32_t skey = lane < cnt ? (uint32_t)(v >> 6) : 0x7FFFFFFFu;
   const uint32_t pos = (uint32_t)(v & 63u);
   uint64_t bit = (lane < cnt) ? (1ull << pos) : 0ull;
   // inclusive OR-scan over lanes: pm[lane + 1]
@@ -263,6 +264,9 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   if (bytes < h.total_bytes) return fail(ctx, MH_EINVAL, "tile buffer too small");
   if (((uintptr_t)base & 255u) != 0) return fail(ctx, MH_EINVAL, "tile buffer not 256-byte aligned");
   if (n_problems == 0 || n_problems > 65535) return fail(ctx, MH_EINVAL, "bad subproblem count");
+  // the search takes v < tau from the sign of v - tau: ranks and thresholds
+  // below 2^31
+  if (ds->n >= (1u << 31)) return fail(ctx, MH_EINVAL, "tile layout needs fewer than 2^31 samples");
   hipStream_t st = ctx->stream;
   TileHdr *dh = reinterpret_cast<TileHdr *>(base);
   uint8_t *b = reinterpret_cast<uint8_t *>(base);
