@@ -195,7 +195,8 @@ void *arena_get(Ctx *ctx, const char *name, size_t bytes) {
   return nb.ptr;
 }
 
-// Tile path limits: depth templates 1..5, one LDS tile <= 64 KiB.
+// Tile path limits: depth templates 1..5, one LDS tile <= 64 KiB, ranks and
+// thresholds below 2^31 (the search step's sign test).
 static bool tile_path_ok(uint32_t D, uint32_t F, uint32_t n) {
   return D >= 1 && D <= 5 && F <= 80 && n < (1u << 31);
 }

@@ -201,7 +201,6 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
 // Block b works on feature f and tiles 4 q .. 4 q + 3 (one per wave), with
 // (f, q) = block xcd_order(b) of the feature-major list (xcd.h), so that an
 // XCD's random reads of a feature's ranks stay in its own L2.
-
 template <typename KT>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ ranks, uint32_t ld,
                                                    TileHdr *__restrict__ hdr) {
