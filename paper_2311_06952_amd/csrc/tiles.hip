@@ -8,6 +8,8 @@
 // bitmasks, selected by a 6-step binary search.  Every tree of the population
 // reuses the same tile, so the sort cost is paid once per dataset (or once
 // per moving-horizon level), not once per evaluation.
+#include <algorithm>
+
 #include "device_common.h"
 #include "internal.h"
 #include "xcd.h"
@@ -71,22 +73,26 @@ __device__ __forceinline__ bool sample_ok(const uint8_t *__restrict__ labels,
 }
 
 // Block-aggregated segment counts: LDS histogram when the segments fit,
-// then one global atomic per (block, segment).
+// then one global atomic per (block, segment).  Block b takes the samples
+// [b span, (b + 1) span), span a multiple of its 256 threads: with about two
+// blocks per CU the segments' totals take a few hundred global adds each
+// rather than one per 256 samples (adds to one address serialise).
 constexpr uint32_t LDS_SEGS = 2048;
 
 __global__ __launch_bounds__(256) void k_tile_count(
     const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
     const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n, uint32_t K,
-    uint32_t n_problems, uint32_t *__restrict__ ctot) {
+    uint32_t n_problems, uint32_t span, uint32_t *__restrict__ ctot) {
   __shared__ uint32_t h[LDS_SEGS];
   const uint32_t nseg = n_problems * K;
   const bool local = nseg <= LDS_SEGS;
   if (local)
     for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
   __syncthreads();
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t i, seg;
-  if (j < n_sub && sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) {
+  const uint32_t j0 = blockIdx.x * span, j1 = min(n_sub, j0 + span);
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    uint32_t i, seg;
+    if (!sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) continue;
     if (local) atomicAdd(&h[seg], 1u);
     else atomicAdd(&ctot[seg], 1u);
   }
@@ -159,13 +165,16 @@ __global__ void k_tile_info(TileHdr *__restrict__ hdr, uint32_t nseg) {
   info[t] = ((lo / K) << 16) | ((lo % K) << 8) | cnt;
 }
 
-// Scatter sample ids into their tile slots.  Each block reserves one range
-// per segment with a single global atomic and fills it from LDS positions.
-// The order inside a segment is whatever the atomics give; counts do not
-// depend on it.
+// Scatter sample ids into their tile slots.  Block b takes the samples
+// [b span, (b + 1) span) (as k_tile_count): it counts them per segment in
+// LDS, reserves one range per segment with a single global atomic, and
+// fills the ranges from LDS cursors in a second pass over its samples.  The
+// order inside a segment is whatever the atomics give; counts do not depend
+// on it.
 __global__ __launch_bounds__(256) void k_tile_scatter(
     const uint8_t *__restrict__ labels, const uint32_t *__restrict__ idx,
-    const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n, TileHdr *__restrict__ hdr) {
+    const uint32_t *__restrict__ sub_of, uint32_t n_sub, uint32_t n, uint32_t span,
+    TileHdr *__restrict__ hdr) {
   __shared__ uint32_t h[LDS_SEGS];
   uint8_t *base = reinterpret_cast<uint8_t *>(hdr);
   const uint32_t *segoff = reinterpret_cast<const uint32_t *>(base + hdr->off_segoff);
@@ -173,23 +182,32 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
   uint32_t *order = reinterpret_cast<uint32_t *>(base + hdr->off_order);
   const uint32_t K = hdr->K, n_problems = hdr->n_problems, nseg = n_problems * K;
   const bool local = nseg <= LDS_SEGS;
-  if (local)
-    for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
-  __syncthreads();
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t i = 0, s = 0, pos = 0;
-  const bool ok = j < n_sub && sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, s);
-  if (ok) pos = local ? atomicAdd(&h[s], 1u) : atomicAdd(&cursor[s], 1u);
-  if (local) {
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < nseg; q += blockDim.x)
-      if (h[q]) h[q] = atomicAdd(&cursor[q], h[q]);
-    __syncthreads();
-    if (ok) pos += h[s];
+  const uint32_t j0 = blockIdx.x * span, j1 = min(n_sub, j0 + span);
+  auto put = [&](uint32_t i, uint32_t s, uint32_t pos) {
+    const uint32_t tile = segoff[s] + pos / TILE_CAP;
+    order[tile * TILE_W + pos % TILE_CAP] = i;
+  };
+  if (!local) {
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      uint32_t i, s;
+      if (sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, s)) put(i, s, atomicAdd(&cursor[s], 1u));
+    }
+    return;
   }
-  if (!ok) return;
-  const uint32_t tile = segoff[s] + pos / TILE_CAP;
-  order[tile * TILE_W + pos % TILE_CAP] = i;
+  for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
+  __syncthreads();
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    uint32_t i, s;
+    if (sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, s)) atomicAdd(&h[s], 1u);
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < nseg; q += blockDim.x)
+    if (h[q]) h[q] = atomicAdd(&cursor[q], h[q]);
+  __syncthreads();
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    uint32_t i, s;
+    if (sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, s)) put(i, s, atomicAdd(&h[s], 1u));
+  }
 }
 
 // One wave per (tile, feature): sort the tile's ranks with their positions
@@ -266,6 +284,8 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   // the search takes v < tau from the sign of v - tau: ranks and thresholds
   // below 2^31
   if (ds->n >= (1u << 31)) return fail(ctx, MH_EINVAL, "tile layout needs fewer than 2^31 samples");
+  // the count and scatter loops step their sample index by 256 without wrapping
+  if (n_sub > 0xFFFFFF00u) return fail(ctx, MH_EINVAL, "too many (sample, subproblem) pairs");
   hipStream_t st = ctx->stream;
   TileHdr *dh = reinterpret_cast<TileHdr *>(base);
   uint8_t *b = reinterpret_cast<uint8_t *>(base);
@@ -273,9 +293,13 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   k_tile_hdr<<<std::min<uint32_t>((nseg + 255) / 256, 256u), 256, 0, st>>>(
       dh, h, reinterpret_cast<uint32_t *>(b + h.off_ctot), nseg);
   MH_LAUNCHED(ctx, "k_tile_hdr");
+  // samples per block of the count and scatter: a multiple of 256, about two
+  // blocks per CU
+  const uint32_t nb_max = 2u * (uint32_t)std::max(1, ctx->num_cu);
+  const uint32_t span = (uint32_t)(((((uint64_t)n_sub + nb_max - 1) / nb_max) + 255) / 256 * 256);
+  const uint32_t nb = n_sub ? (uint32_t)(((uint64_t)n_sub + span - 1) / span) : 0u;
   if (n_sub > 0) {
-    uint32_t nb = (n_sub + 255) / 256;
-    k_tile_count<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, ds->K, n_problems,
+    k_tile_count<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, ds->K, n_problems, span,
                                      reinterpret_cast<uint32_t *>(b + h.off_ctot));
     MH_LAUNCHED(ctx, "k_tile_count");
   }
@@ -284,8 +308,7 @@ mh_status launch_tile_build(Ctx *ctx, const mh_dataset *ds, const uint32_t *idx,
   k_tile_info<<<(h.max_tiles + 255) / 256, 256, 0, st>>>(dh, nseg);
   MH_LAUNCHED(ctx, "k_tile_info");
   if (n_sub > 0) {
-    uint32_t nb = (n_sub + 255) / 256;
-    k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, dh);
+    k_tile_scatter<<<nb, 256, 0, st>>>(ds->labels, idx, sub_of, n_sub, ds->n, span, dh);
     MH_LAUNCHED(ctx, "k_tile_scatter");
     // F blocks per quad of tiles (see k_tile_sort)
     const uint64_t quads = ((uint64_t)h.max_tiles + 3) / 4;
