@@ -28,14 +28,15 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t n, uint32_t v) {
 __global__ __launch_bounds__(256) void k_level_hist(const uint32_t *__restrict__ node_of,
                                                     const uint8_t *__restrict__ labels, uint32_t n,
                                                     uint32_t K, uint32_t t0, uint32_t width,
-                                                    uint32_t *__restrict__ hist, int in_lds) {
+                                                    uint32_t span, uint32_t *__restrict__ hist,
+                                                    int in_lds) {
   extern __shared__ uint32_t h[];
   const uint32_t cells = width * K;
   if (in_lds)
     for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) h[c] = 0;
   __syncthreads();
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
+  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  for (uint32_t i = j0 + threadIdx.x; i < j1; i += blockDim.x) {
     const uint32_t t = node_of[i], y = labels[i];
     if (t >= t0 && t - t0 < width && y < K) atomicAdd(in_lds ? &h[(t - t0) * K + y] : &hist[(t - t0) * K + y], 1u);
   }
@@ -92,37 +93,100 @@ __global__ void k_route_level(uint32_t *__restrict__ node_of, uint32_t n, uint32
 // holds two or more classes and has a candidate.  Scores are positive, so
 // their bit patterns order as u64.
 // ---------------------------------------------------------------------------
-__global__ void k_split_keys(const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
-                             const uint32_t *__restrict__ ranks, uint32_t ld, uint32_t F,
-                             const uint8_t *__restrict__ labels, uint32_t K,
-                             uint32_t *__restrict__ cursor, uint64_t *__restrict__ keys,
-                             uint32_t *__restrict__ vals, uint32_t fbits) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t s = (i < n && sub_of) ? sub_of[i] : 0u;
-  const uint32_t y = i < n ? labels[i] : 0u;
-  const bool member = i < n && s < nsub && y < K;
-  const uint32_t p = block_reserve(member, cursor);
-  if (!member) return;
-  for (uint32_t f = 0; f < F; ++f) {
-    const uint64_t sid = (uint64_t)s << fbits | f;
-    keys[(size_t)p * F + f] = sid << 32 | ranks[(size_t)f * ld + i];
-    vals[(size_t)p * F + f] = y;
+// Samples of [j0, j1) taken 256 at a time by a block: the chunk's members
+// (pred true) are numbered in thread order, their count returned and, for
+// member number l, put(l, i) called before the block's next barrier.  Must be
+// called by all threads of a 256-thread block with the same j0, j1.
+template <typename Pred, typename Fn>
+__device__ __forceinline__ uint32_t chunk_members(uint32_t c0, uint32_t j1, Pred pred, Fn put,
+                                                  uint32_t *s_w) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t i = c0 + threadIdx.x;
+  const bool m = i < j1 && pred(i);
+  const uint64_t bal = __ballot(m);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  __syncthreads();  // the previous chunk's readers of s_w and the staged members are done
+  if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    off += q < w ? s_w[q] : 0u;
+    tot += s_w[q];
   }
+  if (m) put(off + (uint32_t)__popcll(bal & lt), i);
+  return tot;
 }
 
+// Members of [j0, j1) (pred true), counted by a 256-thread block, and the
+// start of their range from one add to *cursor.
+template <typename Pred>
+__device__ __forceinline__ uint32_t range_reserve(uint32_t j0, uint32_t j1, Pred pred,
+                                                  uint32_t *__restrict__ cursor, uint32_t *s_w,
+                                                  uint32_t *s_base) {
+  uint32_t c = 0;
+  for (uint32_t i = j0 + threadIdx.x; i < j1; i += 256u) c += pred(i) ? 1u : 0u;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63u) == 0) s_w[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    *s_base = t ? atomicAdd(cursor, t) : 0u;
+  }
+  __syncthreads();
+  return *s_base;
+}
+
+// The elements of the subsets' members: key (subset << fbits | feature) << rb
+// | rank (ranks below 2^rb), the class as value.  Block b takes the samples
+// [b span, (b + 1) span): one global add reserves its members' elements,
+// then each chunk of 256 samples is staged in LDS and written F elements per
+// member in order, so that a wave's store covers 64 consecutive elements.
+__global__ __launch_bounds__(256) void k_split_keys(
+    const uint32_t *__restrict__ sub_of, uint32_t n, uint32_t nsub,
+    const uint32_t *__restrict__ ranks, uint32_t ld, uint32_t F,
+    const uint8_t *__restrict__ labels, uint32_t K, uint32_t span, uint32_t *__restrict__ cursor,
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t fbits, uint32_t rb) {
+  __shared__ uint32_t s_w[4], s_base;
+  __shared__ uint32_t s_i[256], s_s[256];
+  __shared__ uint8_t s_y[256];
+  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  auto member = [&](uint32_t i) {
+    const uint32_t s = sub_of ? sub_of[i] : 0u;
+    return s < nsub && labels[i] < K;
+  };
+  uint32_t base = range_reserve(j0, j1, member, cursor, s_w, &s_base);
+  for (uint32_t c0 = j0; c0 < j1; c0 += 256u) {
+    const uint32_t tot = chunk_members(c0, j1, member, [&](uint32_t l, uint32_t i) {
+      s_i[l] = i;
+      s_s[l] = sub_of ? sub_of[i] : 0u;
+      s_y[l] = labels[i];
+    }, s_w);
+    __syncthreads();
+    const size_t e0 = (size_t)base * F;
+    for (uint32_t e = threadIdx.x; e < tot * F; e += 256u) {
+      const uint32_t q = e / F, f = e - q * F;
+      const uint64_t sid = (uint64_t)s_s[q] << fbits | f;
+      keys[e0 + e] = sid << rb | ranks[(size_t)f * ld + s_i[q]];
+      vals[e0 + e] = s_y[q];
+    }
+    base += tot;
+  }
+}
 __global__ void k_split_flags(const uint32_t *__restrict__ vals, uint32_t N, uint32_t k,
                               uint32_t *__restrict__ flags) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < N) flags[j] = vals[j] == k ? 1u : 0u;
 }
 
-__global__ void k_split_bounds(const uint64_t *__restrict__ keys, uint32_t N,
+__global__ void k_split_bounds(const uint64_t *__restrict__ keys, uint32_t N, uint32_t rb,
                                uint32_t *__restrict__ seg_lo, uint32_t *__restrict__ seg_hi) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  const uint64_t sid = keys[j] >> 32;
-  if (j == 0 || (keys[j - 1] >> 32) != sid) seg_lo[sid] = j;
-  if (j == N - 1 || (keys[j + 1] >> 32) != sid) seg_hi[sid] = j;
+  const uint64_t sid = keys[j] >> rb;
+  if (j == 0 || (keys[j - 1] >> rb) != sid) seg_lo[sid] = j;
+  if (j == N - 1 || (keys[j + 1] >> rb) != sid) seg_hi[sid] = j;
 }
 
 __device__ __forceinline__ uint32_t split_correct(const uint32_t *__restrict__ pk, uint32_t N,
@@ -176,23 +240,24 @@ template <bool GINI>
 __global__ void k_split_eval(const uint64_t *__restrict__ keys, uint32_t N,
                              const uint32_t *__restrict__ pk, uint32_t K,
                              const uint32_t *__restrict__ seg_lo, const uint32_t *__restrict__ seg_hi,
-                             uint32_t fbits, uint32_t pass, unsigned long long *__restrict__ best_c,
+                             uint32_t fbits, uint32_t rb, uint32_t pass,
+                             unsigned long long *__restrict__ best_c,
                              unsigned long long *__restrict__ best_ft) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   bool cand = false;
   uint32_t s = 0xFFFFFFFFu;
   uint64_t c = 0, ft = ~0ull;
   if (j < N) {
-    const uint64_t key = keys[j];
-    const uint64_t sid = key >> 32;
+    const uint64_t key = keys[j], rmask = (1ull << rb) - 1u;
+    const uint64_t sid = key >> rb;
     const uint32_t hi = seg_hi[sid];
     s = (uint32_t)(sid >> fbits);
     // a boundary: the rank changes between j and j + 1 inside the segment
-    if (j != hi && (keys[j + 1] & 0xFFFFFFFFull) != (key & 0xFFFFFFFFull)) {
+    if (j != hi && (keys[j + 1] & rmask) != (key & rmask)) {
       const uint32_t f = (uint32_t)(sid & ((1u << fbits) - 1u));
       c = GINI ? split_gini_bits(pk, N, K, seg_lo[sid], j, hi)
                : (uint64_t)split_correct(pk, N, K, seg_lo[sid], j, hi);
-      ft = ((uint64_t)(f + 1) << 32) | ((key & 0xFFFFFFFFull) + 1);
+      ft = ((uint64_t)(f + 1) << 32) | ((key & rmask) + 1);
       cand = pass == 0 || c == best_c[s];
     }
   }
@@ -265,15 +330,32 @@ __global__ void k_put_roots(const uint8_t *__restrict__ f1, const uint32_t *__re
 }
 
 inline uint32_t nblk(uint32_t n, uint32_t b = 256) { return (n + b - 1) / b; }
+// Samples per block of the range kernels (k_compact, k_split_keys): a
+// multiple of 256, about two blocks per CU; and the blocks that cover n.
+// Their loops step by 256 without wrapping for n <= RANGE_MAX_N.
+constexpr uint32_t RANGE_MAX_N = 0xFFFFFF00u;
+inline uint32_t range_span(const Ctx *ctx, uint32_t n) {
+  const uint64_t nb = 2u * (uint64_t)(ctx->num_cu > 0 ? ctx->num_cu : 1);
+  const uint64_t s = ((((uint64_t)n + nb - 1) / nb) + 255) / 256 * 256;
+  return (uint32_t)(s < 256 ? 256 : s);
+}
+inline uint32_t range_blocks(uint32_t n, uint32_t span) {
+  return (uint32_t)(((uint64_t)n + span - 1) / span);
+}
 
-// Samples at node t, in whatever order the atomics give (the counts of a
-// subset do not depend on the order of its samples).
-__global__ void k_compact(const uint32_t *__restrict__ node_of, uint32_t n, uint32_t t,
-                          uint32_t *__restrict__ cursor, uint32_t *__restrict__ idx) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = i < n && node_of[i] == t;
-  const uint32_t p = block_reserve(in, cursor);
-  if (in) idx[p] = i;
+// Samples at node t, in whatever order the block adds give (the counts of a
+// subset do not depend on the order of its samples).  Block b takes the
+// samples [b span, (b + 1) span) and reserves their slots with one add.
+__global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ node_of, uint32_t n,
+                                                 uint32_t t, uint32_t span,
+                                                 uint32_t *__restrict__ cursor,
+                                                 uint32_t *__restrict__ idx) {
+  __shared__ uint32_t s_w[4], s_base;
+  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  auto in = [&](uint32_t i) { return node_of[i] == t; };
+  uint32_t base = range_reserve(j0, j1, in, cursor, s_w, &s_base);
+  for (uint32_t c0 = j0; c0 < j1; c0 += 256u)
+    base += chunk_members(c0, j1, in, [&](uint32_t l, uint32_t i) { idx[base + l] = i; }, s_w);
 }
 
 // sub_of for an explicit subset: 0 for idx members, 1 for the rest; and the
@@ -363,8 +445,10 @@ mh_status cart_batched(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, u
       k_cart_sub<<<nblk(n), 256, 0, st>>>(sub_of, n, nsub, loc, l, sub_l);
       MH_LAUNCHED(ctx, "k_cart_sub");
       const bool in_lds = (size_t)cnt * K * 4 <= 32768;
-      k_level_hist<<<nblk(n), 256, in_lds ? (size_t)cnt * K * 4 : 0, st>>>(
-          sub_l, ds->labels, n, K, 0, cnt, hist, in_lds ? 1 : 0);
+      if (n > RANGE_MAX_N) return fail(ctx, MH_EINVAL, "too many samples for the level counts");
+      const uint32_t span = range_span(ctx, n);
+      k_level_hist<<<range_blocks(n, span), 256, in_lds ? (size_t)cnt * K * 4 : 0, st>>>(
+          sub_l, ds->labels, n, K, 0, cnt, span, hist, in_lds ? 1 : 0);
       MH_LAUNCHED(ctx, "k_level_hist");
     }
     mh_status s = launch_split1(ctx, ds, sub_l, cnt, hist, fl, tl, nullptr, true);
@@ -410,8 +494,10 @@ mh_status launch_compact(Ctx *ctx, const uint32_t *node_of, uint32_t n, uint32_t
   uint32_t *cursor = (uint32_t *)arena_get(ctx, "mh_cursor", 256);
   if (!cursor) return MH_ENOMEM;
   MH_HIP(ctx, hipMemsetAsync(cursor, 0, 4, ctx->stream));
+  if (n > RANGE_MAX_N) return fail(ctx, MH_EINVAL, "too many samples for the compaction");
   if (n) {
-    k_compact<<<nblk(n), 256, 0, ctx->stream>>>(node_of, n, t, cursor, idx);
+    const uint32_t span = range_span(ctx, n);
+    k_compact<<<range_blocks(n, span), 256, 0, ctx->stream>>>(node_of, n, t, span, cursor, idx);
     MH_LAUNCHED(ctx, "k_compact");
   }
   return MH_OK;
@@ -455,6 +541,10 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
   uint32_t sbits = 0;
   while ((1u << sbits) < nsub) ++sbits;
   if (fbits + sbits > 31) return fail(ctx, MH_EINVAL, "too many subsets for split1");
+  if (n > RANGE_MAX_N) return fail(ctx, MH_EINVAL, "too many samples for split1");
+  // ranks lie below n: the low rb bits of a key
+  uint32_t rb = 1;
+  while ((1ull << rb) < n) ++rb;
   uint32_t *cursor = (uint32_t *)arena_get(ctx, "sp_cursor", 256);
   unsigned long long *best_c =
       (unsigned long long *)arena_get(ctx, "sp_best_c", (size_t)nsub * 8);
@@ -486,12 +576,14 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
     uint32_t *seg_lo = (uint32_t *)arena_get(ctx, "sp_seg_lo", nseg * 4);
     uint32_t *seg_hi = (uint32_t *)arena_get(ctx, "sp_seg_hi", nseg * 4);
     if (!ka || !kb || !va || !vb || !pk || !seg_lo || !seg_hi) return MH_ENOMEM;
-    k_split_keys<<<nblk(n), 256, 0, st>>>(sub_of, n, nsub, ds->ranks, ds->ld, F, ds->labels, K,
-                                           cursor, ka, va, fbits);
+    const uint32_t span = range_span(ctx, n);
+    k_split_keys<<<range_blocks(n, span), 256, 0, st>>>(sub_of, n, nsub, ds->ranks, ds->ld, F,
+                                                         ds->labels, K, span, cursor, ka, va,
+                                                         fbits, rb);
     MH_LAUNCHED(ctx, "k_split_keys");
     uint64_t *keys = ka;
     uint32_t *vals = va;
-    const uint32_t key_bits = ((32 + fbits + sbits + 7) / 8) * 8;
+    const uint32_t key_bits = ((rb + fbits + sbits + 7) / 8) * 8;
     mh_status s = radix_sort_pairs(ctx, &keys, &vals, keys == ka ? kb : ka, vals == va ? vb : va,
                                    N, key_bits);
     if (s) return s;
@@ -502,14 +594,14 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
       s = scan_u32(ctx, p, p, N, true);
       if (s) return s;
     }
-    k_split_bounds<<<nblk(N), 256, 0, st>>>(keys, N, seg_lo, seg_hi);
+    k_split_bounds<<<nblk(N), 256, 0, st>>>(keys, N, rb, seg_lo, seg_hi);
     MH_LAUNCHED(ctx, "k_split_bounds");
     for (uint32_t pass = 0; pass < 2; ++pass) {
       if (gini)
-        k_split_eval<true><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass,
+        k_split_eval<true><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, rb, pass,
                                                     best_c, best_ft);
       else
-        k_split_eval<false><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, pass,
+        k_split_eval<false><<<nblk(N), 256, 0, st>>>(keys, N, pk, K, seg_lo, seg_hi, fbits, rb, pass,
                                                      best_c, best_ft);
       MH_LAUNCHED(ctx, "k_split_eval");
     }
@@ -709,8 +801,12 @@ mh_status mh_train_impl(Ctx *ctx, const mh_dataset *ds, uint32_t D, uint32_t D_M
     MH_HIP(ctx, hipMemsetAsync(hist, 0, (size_t)width * K * 4, st));
     if (n) {
       const bool in_lds = (size_t)width * K * 4 <= 32768;
-      k_level_hist<<<nblk(n), 256, in_lds ? (size_t)width * K * 4 : 0, st>>>(
-          node_of, ds->labels, n, K, t0, width, hist, in_lds ? 1 : 0);
+      // a range of samples per block (about two blocks per CU): the few
+      // cells of a shallow level take a few hundred global adds each
+      if (n > RANGE_MAX_N) return fail(ctx, MH_EINVAL, "too many samples for the level counts");
+      const uint32_t span = range_span(ctx, n);
+      k_level_hist<<<range_blocks(n, span), 256, in_lds ? (size_t)width * K * 4 : 0, st>>>(
+          node_of, ds->labels, n, K, t0, width, span, hist, in_lds ? 1 : 0);
       MH_LAUNCHED(ctx, "k_level_hist");
     }
     MH_HIP(ctx, hipMemcpyAsync(hh.data(), hist, (size_t)width * K * 4, hipMemcpyDeviceToHost, st));

@@ -134,22 +134,46 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
 }
 
 // Stable scatter.  Keys of the block are taken in order, 256 at a time (a
-// round); inside a round wave w holds keys [64w, 64w + 64).  A key's
-// destination is its digit's global offset for this block plus the number
-// of earlier keys of the block with the same digit: earlier rounds (running),
-// earlier waves of this round, and earlier lanes of this wave (ballot match).
+// round); inside a round wave w holds keys [64w, 64w + 64).  A key's rank
+// among the block's keys of its digit counts the earlier ones: earlier rounds
+// (running), earlier waves of this round, and earlier lanes of this wave
+// (ballot match); its destination is its digit's global offset for this
+// block plus that rank.  The keys are first placed in LDS in digit order (the
+// digit's start inside the block plus the rank) and then written out in that
+// order, so that consecutive threads store consecutive slots of a digit's run.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, uint32_t n, uint32_t shift,
     uint32_t nb, const uint32_t *__restrict__ offs, uint64_t *__restrict__ okeys,
     uint32_t *__restrict__ ovals) {
-  __shared__ uint32_t running[RS_BINS];
+  static_assert(RS_BINS == RS_THREADS, "one digit per thread");
+  __shared__ uint64_t s_key[RS_CHUNK];
+  __shared__ uint32_t s_val[RS_CHUNK];
+  __shared__ uint32_t running[RS_BINS], lstart[RS_BINS], gstart[RS_BINS];
   __shared__ uint32_t wcnt[RS_THREADS / 64][RS_BINS];
+  __shared__ uint32_t wsum[RS_THREADS / 64];
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  running[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
+  const uint32_t b0 = blockIdx.x * RS_CHUNK;
+  // this block's count of digit d = threadIdx.x: the next entry of the scanned
+  // [digit][block] offsets less its own (the last entry's next is n)
+  const uint32_t o = threadIdx.x * nb + blockIdx.x;
+  const uint32_t g = offs[o];
+  const uint32_t c = (o + 1 < RS_BINS * nb ? offs[o + 1] : n) - g;
+  uint32_t x = c;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t ex = x - c;
+  for (uint32_t q = 0; q < w; ++q) ex += wsum[q];
+  lstart[threadIdx.x] = ex;
+  gstart[threadIdx.x] = g;
+  running[threadIdx.x] = ex;
   for (uint32_t q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = blockIdx.x * RS_CHUNK;
   for (uint32_t k = 0; k < RS_ITEMS; ++k) {
     const uint32_t j = b0 + k * RS_THREADS + threadIdx.x;
     const bool valid = j < n;
@@ -169,8 +193,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     if (valid) {
       uint32_t pre = running[d] + below;
       for (uint32_t q = 0; q < w; ++q) pre += wcnt[q][d];
-      okeys[pre] = key;
-      ovals[pre] = val;
+      s_key[pre] = key;
+      s_val[pre] = val;
     }
     __syncthreads();
     uint32_t add = 0;
@@ -180,6 +204,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
     running[threadIdx.x] += add;
     __syncthreads();
+  }
+  const uint32_t cnt = n - b0 < RS_CHUNK ? n - b0 : RS_CHUNK;
+  for (uint32_t p = threadIdx.x; p < cnt; p += RS_THREADS) {
+    const uint64_t key = s_key[p];
+    const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+    const uint32_t dst = gstart[d] + (p - lstart[d]);
+    okeys[dst] = key;
+    ovals[dst] = s_val[p];
   }
 }
 
