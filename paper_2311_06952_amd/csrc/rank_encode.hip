@@ -513,7 +513,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_rank_scatter(
   for (uint32_t k = 0; k < RND; ++k) {
     const uint32_t q = q0 + k * 64 + lane;
     const bool valid = q < q1;
-    const uint64_t x = valid ? seg[q] : 0ull;
+    const uint64_t x = valid ? __builtin_nontemporal_load(seg + q) : 0ull;
     const uint32_t v = (uint32_t)(x >> 32);
     uint32_t left = __shfl_up(v, 1, 64);
     if (lane == 0) left = prev;
