@@ -28,6 +28,7 @@ def mh():
     (7, 20_000, 40, 7, 50, 4),      # many (feature, threshold) candidates
     (8, 777, 255, 3, 5, 3),         # the largest feature count
     (9, 0, 4, 3, None, 3),          # empty dataset
+    (10, 300_001, 7, 3, 90, 3),     # level counts and key build over several chunks per block
 ])
 def test_cart_matches_oracle(mh, seed, n, F, K, levels, D):
     X, y = synth.random_small(seed, n, F, K, levels)

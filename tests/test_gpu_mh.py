@@ -20,7 +20,11 @@ def mh():
 
 @pytest.mark.parametrize("seed,n,F,K,levels", [(1, 1, 2, 2, None), (2, 40, 3, 2, None),
                                                (3, 500, 4, 3, 7), (4, 5000, 6, 5, None),
-                                               (5, 3000, 3, 2, 2), (6, 200, 9, 4, 30)])
+                                               (5, 3000, 3, 2, 2), (6, 200, 9, 4, 30),
+                                               # several 256-sample chunks per block of the
+                                               # key build, a ragged last block, F not a
+                                               # power of two
+                                               (8, 300_001, 7, 3, None)])
 def test_split1_all(mh, seed, n, F, K, levels):
     X, y = synth.random_small(seed, n, F, K, levels)
     want = oracle.split1(oracle.dataset_from_X(X, y, K))
@@ -37,6 +41,18 @@ def test_split1_subsets_and_pure(mh):
         assert mh.split1(ds, idx=dev(idx)) == oracle.split1(ods, idx=idx)
     pure = np.nonzero(y == 1)[0].astype(np.uint32)
     assert mh.split1(ds, idx=dev(pure)) == oracle.split1(ods, idx=pure) == (0, 0, len(pure))
+
+
+def test_split1_subsets_large(mh):
+    """Subsets of a dataset large enough that the key build's blocks take
+    several 256-sample chunks each (about two blocks per CU)."""
+    X, y = synth.random_small(9, 400_000, 5, 4, 60)
+    ods = oracle.dataset_from_X(X, y, 4)
+    ds = mh.dataset(X, y, 4)
+    rng = np.random.default_rng(1)
+    for size in (1, 513, 150_000, 399_999):
+        idx = np.sort(rng.choice(400_000, size=size, replace=False)).astype(np.uint32)
+        assert mh.split1(ds, idx=dev(idx)) == oracle.split1(ods, idx=idx)
 
 
 def _mh_both(mh, X, y, K, D, D_MH, P, G, seed, M=0.5, CR=0.9, n_min=1, alpha=0.0, ctx=None,
