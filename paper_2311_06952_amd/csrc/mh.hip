@@ -35,7 +35,8 @@ __global__ __launch_bounds__(256) void k_level_hist(const uint32_t *__restrict__
   if (in_lds)
     for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) h[c] = 0;
   __syncthreads();
-  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  const uint32_t j0 = blockIdx.x * span;
+  const uint32_t j1 = (uint32_t)min((uint64_t)n, (uint64_t)j0 + span);  // no wrap near 2^32
   for (uint32_t i = j0 + threadIdx.x; i < j1; i += blockDim.x) {
     const uint32_t t = node_of[i], y = labels[i];
     if (t >= t0 && t - t0 < width && y < K) atomicAdd(in_lds ? &h[(t - t0) * K + y] : &hist[(t - t0) * K + y], 1u);
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(256) void k_split_keys(
   __shared__ uint32_t s_w[4], s_base;
   __shared__ uint32_t s_i[256], s_s[256];
   __shared__ uint8_t s_y[256];
-  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  const uint32_t j0 = blockIdx.x * span;
+  const uint32_t j1 = (uint32_t)min((uint64_t)n, (uint64_t)j0 + span);  // no wrap near 2^32
   auto member = [&](uint32_t i) {
     const uint32_t s = sub_of ? sub_of[i] : 0u;
     return s < nsub && labels[i] < K;
@@ -351,7 +353,8 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ no
                                                  uint32_t *__restrict__ cursor,
                                                  uint32_t *__restrict__ idx) {
   __shared__ uint32_t s_w[4], s_base;
-  const uint32_t j0 = blockIdx.x * span, j1 = min(n, j0 + span);
+  const uint32_t j0 = blockIdx.x * span;
+  const uint32_t j1 = (uint32_t)min((uint64_t)n, (uint64_t)j0 + span);  // no wrap near 2^32
   auto in = [&](uint32_t i) { return node_of[i] == t; };
   uint32_t base = range_reserve(j0, j1, in, cursor, s_w, &s_base);
   for (uint32_t c0 = j0; c0 < j1; c0 += 256u)

@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void k_tile_count(
   if (local)
     for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) h[s] = 0;
   __syncthreads();
-  const uint32_t j0 = blockIdx.x * span, j1 = min(n_sub, j0 + span);
+  const uint32_t j0 = blockIdx.x * span;
+  const uint32_t j1 = (uint32_t)min((uint64_t)n_sub, (uint64_t)j0 + span);  // no wrap near 2^32
   for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     uint32_t i, seg;
     if (!sample_ok(labels, idx, sub_of, j, n, K, n_problems, i, seg)) continue;
@@ -182,7 +183,8 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
   uint32_t *order = reinterpret_cast<uint32_t *>(base + hdr->off_order);
   const uint32_t K = hdr->K, n_problems = hdr->n_problems, nseg = n_problems * K;
   const bool local = nseg <= LDS_SEGS;
-  const uint32_t j0 = blockIdx.x * span, j1 = min(n_sub, j0 + span);
+  const uint32_t j0 = blockIdx.x * span;
+  const uint32_t j1 = (uint32_t)min((uint64_t)n_sub, (uint64_t)j0 + span);  // no wrap near 2^32
   auto put = [&](uint32_t i, uint32_t s, uint32_t pos) {
     const uint32_t tile = segoff[s] + pos / TILE_CAP;
     order[tile * TILE_W + pos % TILE_CAP] = i;
