@@ -94,10 +94,10 @@ __global__ void k_route_level(uint32_t *__restrict__ node_of, uint32_t n, uint32
 // holds two or more classes and has a candidate.  Scores are positive, so
 // their bit patterns order as u64.
 // ---------------------------------------------------------------------------
-// Samples of [j0, j1) taken 256 at a time by a block: the chunk's members
-// (pred true) are numbered in thread order, their count returned and, for
-// member number l, put(l, i) called before the block's next barrier.  Must be
-// called by all threads of a 256-thread block with the same j0, j1.
+// The chunk of samples [c0, min(c0 + 256, j1)) of a block's range: its
+// members (pred true) are numbered in thread order, their count returned and,
+// for member number l, put(l, i) called before the block's next barrier.
+// Must be called by all threads of a 256-thread block with the same c0, j1.
 template <typename Pred, typename Fn>
 __device__ __forceinline__ uint32_t chunk_members(uint32_t c0, uint32_t j1, Pred pred, Fn put,
                                                   uint32_t *s_w) {
