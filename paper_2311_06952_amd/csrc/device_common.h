@@ -66,33 +66,6 @@ __device__ __forceinline__ void decode_node(double a, double b, uint32_t F,
   tau = th;
 }
 
-// Block-wide slot reservation for stream compaction: every thread with
-// `want` gets a distinct index in [base, base + block total) where base comes
-// from a single atomicAdd on *cursor per block (order inside the block is by
-// thread index).  Must be called by all threads of the block; blockDim.x a
-// multiple of 64 and at most 1024.
-__device__ __forceinline__ uint32_t block_reserve(bool want, uint32_t *__restrict__ cursor) {
-  __shared__ uint32_t s_wave[16];
-  __shared__ uint32_t s_base;
-  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint64_t bal = __ballot(want);
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const uint32_t below = (uint32_t)__popcll(bal & lt);
-  if (lane == 0) s_wave[w] = (uint32_t)__popcll(bal);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t tot = 0;
-    for (uint32_t q = 0; q < (blockDim.x >> 6); ++q) {
-      const uint32_t c = s_wave[q];
-      s_wave[q] = tot;
-      tot += c;
-    }
-    s_base = tot ? atomicAdd(cursor, tot) : 0u;
-  }
-  __syncthreads();
-  return s_base + s_wave[w] + below;
-}
-
 // wave64 helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
