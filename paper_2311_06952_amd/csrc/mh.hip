@@ -176,10 +176,81 @@ __global__ __launch_bounds__(256) void k_split_keys(
     base += tot;
   }
 }
-__global__ void k_split_flags(const uint32_t *__restrict__ vals, uint32_t N, uint32_t k,
-                              uint32_t *__restrict__ flags) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < N) flags[j] = vals[j] == k ? 1u : 0u;
+// Per-class inclusive prefix counts over the sorted classes, all classes at
+// once: pk[k][j] = #{i <= j : vals[i] == k}.  A block takes 1,024 positions,
+// four rounds of 256 (round q, thread t: position 1024 b + 256 q + t); a
+// wave's count of class k below a lane is the popcount of the class's ballot
+// under the lane.  k_split_class_sums writes the block's count of each class
+// (class-major, [k][block]); after one exclusive scan of them a class's base
+// for block b is its scanned entry less the entry of block 0 (the counts of
+// the classes before it).
+constexpr uint32_t CP_ROUNDS = 4, CP_SPAN = 256 * CP_ROUNDS;
+__global__ __launch_bounds__(256) void k_split_class_sums(const uint32_t *__restrict__ vals,
+                                                          uint32_t N, uint32_t K, uint32_t nb,
+                                                          uint32_t *__restrict__ sums) {
+  extern __shared__ uint32_t s_cnt[];  // [K]
+  for (uint32_t k = threadIdx.x; k < K; k += 256u) s_cnt[k] = 0;
+  __syncthreads();
+  const uint32_t j0 = blockIdx.x * CP_SPAN;
+  uint32_t v[CP_ROUNDS];
+#pragma unroll
+  for (uint32_t q = 0; q < CP_ROUNDS; ++q) {
+    const uint32_t j = j0 + q * 256u + threadIdx.x;
+    v[q] = j < N ? vals[j] : 0xFFFFFFFFu;
+  }
+  if (K <= 16) {
+    // few classes: a ballot per class and round, one LDS add per wave and
+    // class (adds of a whole block to one of a few words would serialise)
+    for (uint32_t k = 0; k < K; ++k) {
+      uint32_t c = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < CP_ROUNDS; ++q) c += (uint32_t)__popcll(__ballot(v[q] == k));
+      if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&s_cnt[k], c);
+    }
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < CP_ROUNDS; ++q)
+      if (v[q] < K) atomicAdd(&s_cnt[v[q]], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < K; k += 256u) sums[(size_t)k * nb + blockIdx.x] = s_cnt[k];
+}
+__global__ __launch_bounds__(256) void k_split_class_prefix(const uint32_t *__restrict__ vals,
+                                                            uint32_t N, uint32_t K, uint32_t nb,
+                                                            const uint32_t *__restrict__ scanned,
+                                                            uint32_t *__restrict__ pk) {
+  extern __shared__ uint32_t s_w[];  // [CP_ROUNDS][K][4]: wave totals per round and class
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const uint32_t j0 = blockIdx.x * CP_SPAN;
+  uint32_t v[CP_ROUNDS];
+#pragma unroll
+  for (uint32_t q = 0; q < CP_ROUNDS; ++q) {
+    const uint32_t j = j0 + q * 256u + threadIdx.x;
+    v[q] = j < N ? vals[j] : 0xFFFFFFFFu;
+  }
+  for (uint32_t k = 0; k < K; ++k)
+#pragma unroll
+    for (uint32_t q = 0; q < CP_ROUNDS; ++q) {
+      const uint64_t bal = __ballot(v[q] == k);
+      if (lane == 0) s_w[(q * K + k) * 4 + w] = (uint32_t)__popcll(bal);
+    }
+  __syncthreads();
+  for (uint32_t k = 0; k < K; ++k) {
+    uint32_t run = scanned[(size_t)k * nb + blockIdx.x] - scanned[(size_t)k * nb];
+#pragma unroll
+    for (uint32_t q = 0; q < CP_ROUNDS; ++q) {
+      const uint32_t *t = s_w + (q * K + k) * 4;
+      const uint64_t bal = __ballot(v[q] == k);
+      uint32_t below = 0;
+#pragma unroll
+      for (uint32_t x = 0; x < 4; ++x) below += x < w ? t[x] : 0u;
+      const uint32_t j = j0 + q * 256u + threadIdx.x;
+      if (j < N)
+        pk[(size_t)k * N + j] = run + below + (uint32_t)__popcll(bal & lt) + (v[q] == k ? 1u : 0u);
+      run += t[0] + t[1] + t[2] + t[3];
+    }
+  }
 }
 
 __global__ void k_split_bounds(const uint64_t *__restrict__ keys, uint32_t N, uint32_t rb,
@@ -590,12 +661,19 @@ mh_status launch_split1(Ctx *ctx, const mh_dataset *ds, const uint32_t *sub_of, 
     mh_status s = radix_sort_pairs(ctx, &keys, &vals, keys == ka ? kb : ka, vals == va ? vb : va,
                                    N, key_bits);
     if (s) return s;
-    for (uint32_t k = 0; k < K; ++k) {
-      uint32_t *p = pk + (size_t)k * N;
-      k_split_flags<<<nblk(N), 256, 0, st>>>(vals, N, k, p);
-      MH_LAUNCHED(ctx, "k_split_flags");
-      s = scan_u32(ctx, p, p, N, true);
+    // per-class inclusive prefix counts, all classes in two passes over vals
+    {
+      const uint32_t nbc = (uint32_t)(((uint64_t)N + CP_SPAN - 1) / CP_SPAN);
+      if ((uint64_t)nbc * K >= 0xFFFFFFFFull) return fail(ctx, MH_EINVAL, "split1: too many elements");
+      uint32_t *csum = (uint32_t *)arena_get(ctx, "sp_csum", (size_t)nbc * K * 4);
+      if (!csum) return MH_ENOMEM;
+      k_split_class_sums<<<nbc, 256, (size_t)K * 4, st>>>(vals, N, K, nbc, csum);
+      MH_LAUNCHED(ctx, "k_split_class_sums");
+      s = scan_u32(ctx, csum, csum, nbc * K, false);
       if (s) return s;
+      k_split_class_prefix<<<nbc, 256, (size_t)CP_ROUNDS * K * 4 * 4, st>>>(vals, N, K, nbc, csum,
+                                                                             pk);
+      MH_LAUNCHED(ctx, "k_split_class_prefix");
     }
     k_split_bounds<<<nblk(N), 256, 0, st>>>(keys, N, rb, seg_lo, seg_hi);
     MH_LAUNCHED(ctx, "k_split_bounds");

@@ -24,7 +24,10 @@ def mh():
                                                # several 256-sample chunks per block of the
                                                # key build, a ragged last block, F not a
                                                # power of two
-                                               (8, 300_001, 7, 3, None)])
+                                               (8, 300_001, 7, 3, None),
+                                               # more than 16 classes: the class counts'
+                                               # per-element LDS adds
+                                               (11, 50_000, 5, 40, None)])
 def test_split1_all(mh, seed, n, F, K, levels):
     X, y = synth.random_small(seed, n, F, K, levels)
     want = oracle.split1(oracle.dataset_from_X(X, y, K))
