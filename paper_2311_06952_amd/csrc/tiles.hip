@@ -9,6 +9,7 @@
 // reuses the same tile, so the sort cost is paid once per dataset (or once
 // per moving-horizon level), not once per evaluation.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "internal.h"
@@ -212,6 +213,59 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
   }
 }
 
+// v of lane ^ j.  j = 1, 2 by a quad permutation, j = 4, 8 by shifts within
+// rows of 16 (lane + j where bit j of the lane is clear, lane - j where it is
+// set; the other shift's lanes fall outside the row and are not used), all
+// DPP moves without the LDS pipe; j = 16, 32 by a permute through it.
+template <uint32_t J>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v, uint32_t lane) {
+  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (J == 4 || J == 8) {
+    const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + (int)J, 0xF, 0xF, false);
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + (int)J, 0xF, 0xF, false);
+    return (lane & J) ? dn : up;
+  } else {
+    return (uint32_t)__shfl_xor((int)v, (int)J, 64);
+  }
+}
+template <uint32_t J, typename KT>
+__device__ __forceinline__ KT xor_lane(KT v, uint32_t lane) {
+  if constexpr (sizeof(KT) == 4) {
+    return (KT)xor_lane32<J>((uint32_t)v, lane);
+  } else {
+    const uint32_t lo = xor_lane32<J>((uint32_t)v, lane);
+    const uint32_t hi = xor_lane32<J>((uint32_t)(v >> 32), lane);
+    return ((KT)hi << 32) | lo;
+  }
+}
+// One compare-exchange stage of the bitonic network: merge size K, distance J.
+template <uint32_t K, uint32_t J, typename KT>
+__device__ __forceinline__ KT bitonic_stage(KT v, uint32_t lane) {
+  const KT o = xor_lane<J>(v, lane);
+  const bool up = (lane & K) == 0, lo = (lane & J) == 0;
+  const KT mn = v < o ? v : o, mx = v < o ? o : v;
+  return (lo == up) ? mn : mx;
+}
+// Inclusive OR-scan of a 64-bit value over the wave: within rows of 16 by
+// row shifts of 1, 2, 4 and 8 (a lane without a source in the row ORs zero),
+// then the row totals across rows (row broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint64_t or_scan64(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  auto step = [&](auto ctrl_tag, auto mask_tag) {
+    constexpr int ctrl = decltype(ctrl_tag)::value, rmask = decltype(mask_tag)::value;
+    lo |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, ctrl, rmask, 0xF, false);
+    hi |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, ctrl, rmask, 0xF, false);
+  };
+  step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});  // row_shr:1
+  step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});  // row_shr:2
+  step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});  // row_shr:4
+  step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xF>{});  // row_shr:8
+  step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});  // row_bcast:15
+  step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});  // row_bcast:31
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // One wave per (tile, feature): sort the tile's ranks with their positions
 // (bitonic network across the 64 lanes), write the sorted ranks and the
 // prefix masks of the positions in sorted order.  The composite key (rank,
@@ -241,27 +295,33 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *__restrict__ 
   // composite (key, position): distinct, so the network sorts a total order
   KT v = ((KT)key << 6) | lane;
   (void)KB;
-#pragma unroll
-  for (uint32_t k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      KT o = __shfl_xor(v, (int)j, 64);
-      bool up = (lane & k) == 0;
-      bool lo = (lane & j) == 0;
-      KT mn = v < o ? v : o, mx = v < o ? o : v;
-      v = (lo == up) ? mn : mx;
-    }
-  }
+  // the network: merges of size 2, 4, ..., 64, each halving its distance
+  v = bitonic_stage<2, 1>(v, lane);
+  v = bitonic_stage<4, 2>(v, lane);
+  v = bitonic_stage<4, 1>(v, lane);
+  v = bitonic_stage<8, 4>(v, lane);
+  v = bitonic_stage<8, 2>(v, lane);
+  v = bitonic_stage<8, 1>(v, lane);
+  v = bitonic_stage<16, 8>(v, lane);
+  v = bitonic_stage<16, 4>(v, lane);
+  v = bitonic_stage<16, 2>(v, lane);
+  v = bitonic_stage<16, 1>(v, lane);
+  v = bitonic_stage<32, 16>(v, lane);
+  v = bitonic_stage<32, 8>(v, lane);
+  v = bitonic_stage<32, 4>(v, lane);
+  v = bitonic_stage<32, 2>(v, lane);
+  v = bitonic_stage<32, 1>(v, lane);
+  v = bitonic_stage<64, 32>(v, lane);
+  v = bitonic_stage<64, 16>(v, lane);
+  v = bitonic_stage<64, 8>(v, lane);
+  v = bitonic_stage<64, 4>(v, lane);
+  v = bitonic_stage<64, 2>(v, lane);
+  v = bitonic_stage<64, 1>(v, lane);
   // unused entries: 0x7FFFFFFF, above every rank and threshold (n < 2^31)
   const uint32_t skey = lane < cnt ? (uint32_t)(v >> 6) : 0x7FFFFFFFu;
   const uint32_t pos = (uint32_t)(v & 63u);
-  uint64_t bit = (lane < cnt) ? (1ull << pos) : 0ull;
   // inclusive OR-scan over lanes: pm[lane + 1]
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t t = __shfl_up(bit, (unsigned)d, 64);
-    if ((int)lane >= d) bit |= t;
-  }
+  const uint64_t bit = or_scan64((lane < cnt) ? (1ull << pos) : 0ull);
   uint8_t *rec = base + hdr->off_data + (size_t)tile * tile_bytes(F);
   uint32_t *sorted = reinterpret_cast<uint32_t *>(rec) + f * TILE_W;
   uint64_t *pm = reinterpret_cast<uint64_t *>(rec + (size_t)F * TILE_W * 4) + f * TILE_W;
