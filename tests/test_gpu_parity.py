@@ -74,6 +74,21 @@ def test_rank_encode_separate_launch_boundaries(mh, monkeypatch, seed, n, F, lev
     ctx.close()
 
 
+@pytest.mark.parametrize("seed,n,F,levels", [(18, 600_001, 3, None), (19, 1_000_000, 2, 5000)])
+def test_rank_encode_two_halves(mh, monkeypatch, seed, n, F, levels):
+    """Rows of ranks of 2 to 8 MB: the separate launches write the ranks of
+    the two halves of the sample ids in two passes of the rank scatter."""
+    from paper_2311_06952_amd import capi
+    monkeypatch.setenv("MHDEOCT_RANK_COOP", "0")
+    ctx = capi.Context(0)
+    X, y = synth.random_small(seed, n, F, 3, levels)
+    want_r, want_nu = oracle.rank_encode(X)
+    ds = mh.dataset(X, y, 3, ctx=ctx)
+    np.testing.assert_array_equal(u32(ds.n_unique), want_nu)
+    np.testing.assert_array_equal(u32(ds.ranks)[:, :n], want_r)
+    ctx.close()
+
+
 def test_rank_encode_signed_zero_and_nan(mh):
     X = np.array([[0.0, 1.0], [-0.0, 1.0], [-2.5, np.inf], [3.0, -np.inf]], dtype=np.float32)
     want_r, want_nu = oracle.rank_encode(X)
