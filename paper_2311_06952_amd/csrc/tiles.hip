@@ -213,10 +213,10 @@ __global__ __launch_bounds__(256) void k_tile_scatter(
   }
 }
 
-// v of lane ^ j.  j = 1, 2 by a quad permutation, j = 4, 8 by shifts within
-// rows of 16 (lane + j where bit j of the lane is clear, lane - j where it is
-// set; the other shift's lanes fall outside the row and are not used), all
-// DPP moves without the LDS pipe; j = 16, 32 by a permute through it.
+// v of lane ^ J.  J = 1, 2 by a quad permutation, J = 4, 8 by shifts within
+// rows of 16 (lane + J where lane & J is zero, else lane - J; the lanes whose
+// shift leaves the row are the ones that take the other shift), all DPP moves
+// without the LDS pipe; J = 16, 32 by a permute through it.
 template <uint32_t J>
 __device__ __forceinline__ uint32_t xor_lane32(uint32_t v, uint32_t lane) {
   if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);

@@ -400,6 +400,24 @@ def test_paper_parameter_modes(mh, mode, n, P, G):
     _same_tree(want, got)
 
 
+def test_tile_sort_wide_keys(mh):
+    """Over 2^26 samples with ranks past 2^26: the tile sort's composite
+    (rank << 6 | position) keys are 64 bits wide.  The values are positive
+    finite float32 bit patterns drawn uniformly, so nearly all are distinct.
+    DEOCT equals the oracle's run."""
+    n = (1 << 26) + (1 << 22)
+    rng = np.random.default_rng(2626)
+    bits = rng.integers(1, 0x7F000000, size=n, dtype=np.uint32)
+    X = bits.view(np.float32).reshape(n, 1)
+    y = ((bits > 0x3F800000) ^ (rng.random(n) < 0.25)).astype(np.uint8)
+    ods = oracle.dataset_from_X(X, y, 2)
+    assert int(ods.n_unique[0]) > (1 << 26)
+    prm = (8, 2, 0.5, 0.9, 77)
+    got = mh.subtree_solve(gpu_ds(mh, X, y, 2), 2, mh.de_params(*prm), with_pop=True)
+    want = oracle.deoct(ods, 2, oracle.de_params(*prm), with_pop=True)
+    _same_tree(want, got)
+
+
 def test_subtree_solve_depth6_walk_path(mh):
     w = synth.plain_small(7, n=1500)
     w.D = 6
