@@ -312,6 +312,26 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_keys(const float *__restrict
   }
 }
 
+// One wave's digits d (valid lanes only) into its LDS histogram h.  Lanes
+// that share the digit of the lowest pending lane add once, by popcount, while
+// such groups hold four lanes or more (the top bytes of real data repeat
+// within a wave, and adds of many lanes to one word serialise); the rest add
+// one by one.
+__device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t d, bool valid) {
+  const uint32_t lane = threadIdx.x & 63u;
+  uint64_t pending = __ballot(valid);
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, leader);
+    const uint64_t same = __ballot(valid && d == dl) & pending;
+    const uint32_t c = (uint32_t)__popcll(same);
+    if (c < 4) break;
+    if (lane == (uint32_t)leader) atomicAdd(&h[dl], c);
+    pending &= ~same;
+  }
+  if ((pending >> lane) & 1ull) atomicAdd(&h[d], 1u);
+}
+
 // Digit counts of block (f, j): positions [j SG_R, (j + 1) SG_R) of segment f,
 // into hist[(f 256 + digit) nbf + j].
 __global__ __launch_bounds__(SG_THREADS) void k_seg_hist(const uint64_t *__restrict__ src,
@@ -336,7 +356,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_hist(const uint64_t *__restr
   }
 #pragma unroll
   for (uint32_t k = 0; k < SG_ITEMS; ++k)
-    if (d[k] < 256u) atomicAdd(&h[w][d[k]], 1u);
+    wave_hist_add(h[w], d[k], d[k] < 256u);
   __syncthreads();
   uint32_t t = 0;
 #pragma unroll
