@@ -106,8 +106,9 @@ __device__ __forceinline__ uint32_t tile_div(uint32_t j, uint32_t w, uint32_t m)
 
 // Rows staged through LDS: a tile of consecutive rows is one contiguous
 // stretch of X, read with coalesced loads (float4 when rows are whole
-// float4s and X is 16-byte aligned), PRED_UNROLL per lane in flight; the
-// walk's dependent loads then hit LDS.  Rows are padded to F + 1 words so
+// float4s and X is 16-byte aligned: the next tile's float4s are loaded into
+// registers while the current tile is walked; else PRED_UNROLL per lane in
+// flight); the walk's dependent loads then hit LDS.  Rows are padded to F + 1 words so
 // that lanes reading the same column of different rows fall in different
 // banks.
 template <bool VEC>
@@ -127,40 +128,65 @@ __global__ __launch_bounds__(PRED_THREADS) void k_predict(PredArgs a) {
   for (uint32_t l = threadIdx.x; l <= SB; l += PRED_THREADS) s_label[l] = a.label[l];
   uint32_t ok_count = 0;
   const uint32_t n_tiles = (a.n + a.tile_rows - 1u) / a.tile_rows;
-  for (uint32_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
-    const uint32_t base = tl * a.tile_rows;
-    const uint32_t rows = min(a.tile_rows, a.n - base);
-    const float *src = a.X + (size_t)base * F;
-    __syncthreads();  // the previous tile's walk is done (and the tree is staged)
-    if constexpr (VEC) {
-      const uint32_t cnt = rows * a.div_w;  // float4 words
-      const float4 *src4 = reinterpret_cast<const float4 *>(src);
-      for (uint32_t j0 = threadIdx.x; j0 < cnt; j0 += PRED_UNROLL * PRED_THREADS) {
-        float4 v[PRED_UNROLL];
+  // the staged rows of a tile through the tree: prediction and count
+  auto walk = [&](uint32_t base, uint32_t rows) {
+    for (uint32_t r = threadIdx.x; r < rows; r += PRED_THREADS) {
+      const float *row = s_x + r * ldr;
+      uint32_t t = 0;
+      for (uint32_t d = 0; d < a.D; ++d) {
+        const uint32_t f = s_feat[t];
+        const bool left = f != 0 && (double)row[f - 1] < s_thr[t];
+        t = 2u * t + (left ? 1u : 2u);
+      }
+      const uint8_t p = s_label[t - SB];
+      if (a.pred) a.pred[base + r] = p;
+      if (a.y) ok_count += a.y[base + r] == p ? 1u : 0u;
+    }
+  };
+  if constexpr (VEC) {
+    // A tile is at most PRED_TILE_FLOATS / 4 float4s, PF per lane: the next
+    // tile's words are loaded into registers while this one is walked.
+    constexpr uint32_t PF = PRED_TILE_FLOATS / 4 / PRED_THREADS;
+    f4v nv[PF];
+    auto fetch = [&](uint32_t tl) {
+      if (tl >= n_tiles) return;
+      const uint32_t base = tl * a.tile_rows;
+      const uint32_t cnt = min(a.tile_rows, a.n - base) * a.div_w;  // float4 words
+      const f4v *src4 = reinterpret_cast<const f4v *>(a.X + (size_t)base * F);
 #pragma unroll
-        for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
-          const uint32_t j = j0 + u * PRED_THREADS;
-          if (j < cnt) {
-            const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(src4) + j);
-            v[u] = make_float4(t.x, t.y, t.z, t.w);
-          } else {
-            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-        }
+      for (uint32_t u = 0; u < PF; ++u) {
+        const uint32_t j = threadIdx.x + u * PRED_THREADS;
+        if (j < cnt) nv[u] = __builtin_nontemporal_load(src4 + j);
+      }
+    };
+    fetch(blockIdx.x);
+    for (uint32_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+      const uint32_t base = tl * a.tile_rows;
+      const uint32_t rows = min(a.tile_rows, a.n - base);
+      const uint32_t cnt = rows * a.div_w;
+      __syncthreads();  // the previous tile's walk is done (and the tree is staged)
 #pragma unroll
-        for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
-          const uint32_t j = j0 + u * PRED_THREADS;
-          if (j < cnt) {
-            const uint32_t r = tile_div(j, a.div_w, a.div_m);
-            float *dst = s_x + r * ldr + 4u * (j - r * a.div_w);
-            dst[0] = v[u].x;
-            dst[1] = v[u].y;
-            dst[2] = v[u].z;
-            dst[3] = v[u].w;
-          }
+      for (uint32_t u = 0; u < PF; ++u) {
+        const uint32_t j = threadIdx.x + u * PRED_THREADS;
+        if (j < cnt) {
+          const uint32_t r = tile_div(j, a.div_w, a.div_m);
+          float *dst = s_x + r * ldr + 4u * (j - r * a.div_w);
+          dst[0] = nv[u].x;
+          dst[1] = nv[u].y;
+          dst[2] = nv[u].z;
+          dst[3] = nv[u].w;
         }
       }
-    } else {
+      __syncthreads();
+      fetch(tl + gridDim.x);
+      walk(base, rows);
+    }
+  } else {
+    for (uint32_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+      const uint32_t base = tl * a.tile_rows;
+      const uint32_t rows = min(a.tile_rows, a.n - base);
+      const float *src = a.X + (size_t)base * F;
+      __syncthreads();  // the previous tile's walk is done (and the tree is staged)
       const uint32_t cnt = rows * F;
       for (uint32_t j0 = threadIdx.x; j0 < cnt; j0 += PRED_UNROLL * PRED_THREADS) {
         float v[PRED_UNROLL];
@@ -178,19 +204,8 @@ __global__ __launch_bounds__(PRED_THREADS) void k_predict(PredArgs a) {
           }
         }
       }
-    }
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < rows; r += PRED_THREADS) {
-      const float *row = s_x + r * ldr;
-      uint32_t t = 0;
-      for (uint32_t d = 0; d < a.D; ++d) {
-        const uint32_t f = s_feat[t];
-        const bool left = f != 0 && (double)row[f - 1] < s_thr[t];
-        t = 2u * t + (left ? 1u : 2u);
-      }
-      const uint8_t p = s_label[t - SB];
-      if (a.pred) a.pred[base + r] = p;
-      if (a.y) ok_count += a.y[base + r] == p ? 1u : 0u;
+      __syncthreads();
+      walk(base, rows);
     }
   }
   if (a.correct) {
@@ -266,10 +281,11 @@ mh_status mh_predict(mh_ctx *ctx, const float *X, uint32_t n, uint32_t F, const 
   const uint32_t m = w > 1 ? (uint32_t)(((1ull << 32) + w - 1) / w) : 0u;
   PredArgs a{X, feat, thr, label, y, pred, correct, n, F, D, tile_rows, w, m};
   const uint32_t tiles = (n + tile_rows - 1) / tile_rows;
-  // about 27 KB of LDS per block: five resident blocks per CU, two rounds
-  // of them (measured: faster than 32 KB tiles at three per CU and 8 KB or
-  // 12 KB tiles at seven)
-  const uint32_t blocks = std::min<uint32_t>(tiles, 5u * (uint32_t)c->num_cu * 2u);
+  // about 27 KB of LDS per block: five resident blocks per CU, one round
+  // (measured: faster than 32 KB tiles at three per CU and 8 KB or 12 KB
+  // tiles at seven; with the next tile prefetched into registers one round
+  // took 0.183 ms for 16M rows of 16 features, two 0.185 and four 0.186)
+  const uint32_t blocks = std::min<uint32_t>(tiles, 5u * (uint32_t)c->num_cu);
   if (vec)
     k_predict<true><<<blocks, PRED_THREADS, 0, c->stream>>>(a);
   else
