@@ -94,7 +94,6 @@ struct PredArgs {
 };
 
 constexpr uint32_t PRED_TILE_FLOATS = 4096;  // 16 KB of staged rows per block
-constexpr uint32_t PRED_UNROLL = 8;          // loads in flight per lane
 // the streaming loads of X are nontemporal (each row is read once)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -106,9 +105,9 @@ __device__ __forceinline__ uint32_t tile_div(uint32_t j, uint32_t w, uint32_t m)
 
 // Rows staged through LDS: a tile of consecutive rows is one contiguous
 // stretch of X, read with coalesced loads (float4 when rows are whole
-// float4s and X is 16-byte aligned: the next tile's float4s are loaded into
-// registers while the current tile is walked; else PRED_UNROLL per lane in
-// flight); the walk's dependent loads then hit LDS.  Rows are padded to F + 1 words so
+// float4s and X is 16-byte aligned, else single floats); the next tile is
+// loaded into registers while the current one is walked, and the walk's
+// dependent loads hit LDS.  Rows are padded to F + 1 words so
 // that lanes reading the same column of different rows fall in different
 // banks.
 template <bool VEC>
@@ -182,29 +181,36 @@ __global__ __launch_bounds__(PRED_THREADS) void k_predict(PredArgs a) {
       walk(base, rows);
     }
   } else {
+    // the same with single floats, PFS per lane
+    constexpr uint32_t PFS = PRED_TILE_FLOATS / PRED_THREADS;
+    float nv[PFS];
+    auto fetch = [&](uint32_t tl) {
+      if (tl >= n_tiles) return;
+      const uint32_t base = tl * a.tile_rows;
+      const uint32_t cnt = min(a.tile_rows, a.n - base) * F;
+      const float *src = a.X + (size_t)base * F;
+#pragma unroll
+      for (uint32_t u = 0; u < PFS; ++u) {
+        const uint32_t j = threadIdx.x + u * PRED_THREADS;
+        if (j < cnt) nv[u] = __builtin_nontemporal_load(src + j);
+      }
+    };
+    fetch(blockIdx.x);
     for (uint32_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
       const uint32_t base = tl * a.tile_rows;
       const uint32_t rows = min(a.tile_rows, a.n - base);
-      const float *src = a.X + (size_t)base * F;
-      __syncthreads();  // the previous tile's walk is done (and the tree is staged)
       const uint32_t cnt = rows * F;
-      for (uint32_t j0 = threadIdx.x; j0 < cnt; j0 += PRED_UNROLL * PRED_THREADS) {
-        float v[PRED_UNROLL];
+      __syncthreads();  // the previous tile's walk is done (and the tree is staged)
 #pragma unroll
-        for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
-          const uint32_t j = j0 + u * PRED_THREADS;
-          v[u] = j < cnt ? __builtin_nontemporal_load(src + j) : 0.0f;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < PRED_UNROLL; ++u) {
-          const uint32_t j = j0 + u * PRED_THREADS;
-          if (j < cnt) {
-            const uint32_t r = tile_div(j, a.div_w, a.div_m);
-            s_x[r * ldr + (j - r * F)] = v[u];
-          }
+      for (uint32_t u = 0; u < PFS; ++u) {
+        const uint32_t j = threadIdx.x + u * PRED_THREADS;
+        if (j < cnt) {
+          const uint32_t r = tile_div(j, a.div_w, a.div_m);
+          s_x[r * ldr + (j - r * F)] = nv[u];
         }
       }
       __syncthreads();
+      fetch(tl + gridDim.x);
       walk(base, rows);
     }
   }
