@@ -296,13 +296,28 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_keys(const float *__restrict
   const uint32_t r0 = blockIdx.x * rows;
   const uint32_t cnt = min(rows, n - r0);
   bool nan = false;
-  for (uint32_t e = threadIdx.x; e < cnt * F; e += SG_THREADS) {
-    const float x = X[(size_t)r0 * F + e];
-    nan |= x != x;
-    uint32_t u = __float_as_uint(x);
-    if (x == 0.0f) u = 0u;  // -0 == +0
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    sk[(e / F) * (F + 1) + e % F] = u;
+  // eight loads in flight per lane, then their transforms into LDS
+  constexpr uint32_t KU = 8;
+  const float *src = X + (size_t)r0 * F;
+  const uint32_t tot = cnt * F;
+  for (uint32_t e0 = threadIdx.x; e0 < tot; e0 += KU * SG_THREADS) {
+    float x[KU];
+#pragma unroll
+    for (uint32_t u = 0; u < KU; ++u) {
+      const uint32_t e = e0 + u * SG_THREADS;
+      x[u] = e < tot ? __builtin_nontemporal_load(src + e) : 0.0f;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < KU; ++u) {
+      const uint32_t e = e0 + u * SG_THREADS;
+      if (e < tot) {
+        nan |= x[u] != x[u];
+        uint32_t v = __float_as_uint(x[u]);
+        if (x[u] == 0.0f) v = 0u;  // -0 == +0
+        v = (v & 0x80000000u) ? ~v : (v | 0x80000000u);
+        sk[(e / F) * (F + 1) + e % F] = v;
+      }
+    }
   }
   if (__ballot(nan) && (threadIdx.x & 63u) == 0) atomicOr(nan_flag, 1u);
   __syncthreads();
