@@ -487,10 +487,19 @@ __global__ __launch_bounds__(SG_THREADS) void k_seg_ucount(const uint64_t *__res
   // value bits of the position before the chunk (none before the segment)
   uint32_t prev = (q0 > 0 && q0 < n) ? (uint32_t)(seg[q0 - 1] >> 32) : 0u;
   bool prev_ok = q0 > 0;
-  for (uint32_t c = q0; c < q1; c += 64) {
-    const uint32_t q = c + lane;
+  // the wave's span loaded up front (one round trip), then scanned 64 at a time
+  constexpr uint32_t RND = SG_WSPAN / 64;
+  uint32_t vv[RND];
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k) {
+    const uint32_t q = q0 + k * 64 + lane;
+    vv[k] = q < q1 ? (uint32_t)(seg[q] >> 32) : 0u;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < RND; ++k) {
+    const uint32_t q = q0 + k * 64 + lane;
     const bool valid = q < q1;
-    const uint32_t v = valid ? (uint32_t)(seg[q] >> 32) : 0u;
+    const uint32_t v = vv[k];
     uint32_t left = __shfl_up(v, 1, 64);
     if (lane == 0) left = prev;
     const bool start = valid && (lane == 0 ? (!prev_ok || v != left) : v != left);
