@@ -174,11 +174,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
   for (uint32_t q = 0; q < RS_THREADS / 64; ++q) wcnt[q][threadIdx.x] = 0;
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // the block's keys and values loaded up front (one round trip)
+  uint64_t kr[RS_ITEMS];
+  uint32_t vr[RS_ITEMS];
+#pragma unroll
+  for (uint32_t k = 0; k < RS_ITEMS; ++k) {
+    const uint32_t j = b0 + k * RS_THREADS + threadIdx.x;
+    kr[k] = j < n ? keys[j] : 0ull;
+    vr[k] = j < n ? vals[j] : 0u;
+  }
+#pragma unroll
   for (uint32_t k = 0; k < RS_ITEMS; ++k) {
     const uint32_t j = b0 + k * RS_THREADS + threadIdx.x;
     const bool valid = j < n;
-    uint64_t key = valid ? keys[j] : 0ull;
-    uint32_t val = valid ? vals[j] : 0u;
+    const uint64_t key = kr[k];
+    const uint32_t val = vr[k];
     const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
     uint64_t peers = __ballot(valid);
 #pragma unroll
